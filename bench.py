@@ -1,0 +1,242 @@
+"""Throughput of the surfel radiosity hot path on one MI355X.
+
+One step = the whole path over one synthetic fruit-bowl scene (100,000
+surfels on 20 spheres in a hemispherical bowl, SH degree 3, 128 rays per
+surfel, top-512 form factors, 8 bounces, one point light):
+  build_bvh -> reflectance -> form_factors -> direct_light ->
+  transport_solve (with tape) -> transport_backward -> opacity_backward.
+All inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  `value` = complete forward+backward steps per second
+(ray casting included); the JSON also carries Grays/s of the form-factor
+ray cast and fwd+bwd solves/s at fixed F, per-phase HIP-event timings, the
+roofline position of the dominant kernel, the error of sampled outputs
+against the FP64 oracle, and the oracle's own speed on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd transport solves/s + Grays/s at 100k surfels, rel err <=1e-3 vs FP64"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+
+# Algorithmic work per unit ("Rooflines"):
+FLOP_BOX = 24      # one ray / box slab test
+FLOP_HIT = 40      # one ray / surfel hit decision
+FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=100_000, help="surfel count (100k is the measured workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--cpu-receivers", type=int, default=24)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this path "
+              "is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2509_18497_amd as g
+    import scenes
+
+    torch.cuda.set_device(0)
+    sc = scenes.make_config("fruit_bowl", n=args.n)
+    N, R, K, nb, topk, Lt = sc.n, sc.R, sc.K, sc.n_bounces, sc.topk, sc.n_lights
+    dev = torch.device("cuda")
+    sur = {k: torch.from_numpy(v).to(dev) for k, v in sc.surfels.items()}
+    alb = torch.from_numpy(sc.albedo).to(dev)
+    lpos = torch.from_numpy(sc.light_pos).to(dev)
+    lI = torch.from_numpy(sc.light_I).to(dev)
+    gB = torch.from_numpy(scenes.seeded_array((N, Lt, K, 3), seed=99, lo=-1e-6, hi=1e-6)).to(dev)
+    E = torch.empty((N, Lt, K, 3), dtype=torch.float32, device=dev)
+    B = torch.empty_like(E)
+    st = torch.cuda.current_stream()
+    state = {"bvh": None, "ff": None, "tape": None}
+
+    def step():
+        bvh = g.build_bvh(sur, state["bvh"])
+        state["bvh"] = bvh
+        rho = g.reflectance(bvh, alb)
+        ff = g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, topk=topk, ff=state["ff"])
+        state["ff"] = ff
+        g.direct_light(bvh, alb, lpos, lI, K, out=E)
+        _, tape = g.transport_solve(ff, rho, E, nb, tape=state["tape"], out=B)
+        state["tape"] = tape
+        gE, grho, gF = g.transport_backward(ff, tape, rho, gB)
+        go, ga = g.opacity_backward(bvh, ff, gF, grho, alb)
+        return ff, gE, grho, gF, go, ga
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.gsrad.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.gsrad.profile_report()
+    g.gsrad.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    ff = out[0]
+    _, nnz = ff.info()
+
+    def avg(name):
+        return prof[name]["total_ms"] / args.steps if name in prof else 0.0
+
+    t_trace = avg("ff_trace")
+    t_ff = avg("ff_trace") + avg("ff_aggregate") + avg("ff_csr")
+    t_solve_bwd = avg("bounce") + avg("transpose") + avg("adjoint") + avg("sddmm") + avg("opacity_pass1") + \
+        avg("opacity_pass2") + avg("opacity_finish")
+    rays = N * R
+    grays = rays / (t_trace * 1e-3) / 1e9 if t_trace > 0 else None
+
+    # composited hits per ray on a sample (outside the timed region) for the
+    # algorithmic work of the ray cast
+    rng = np.random.default_rng(7)
+    samp = np.sort(rng.choice(N, size=64, replace=False)).astype(np.int64)
+    hits = g.ray_hits(state["bvh"], torch.from_numpy(samp).to(dev), R, sc.seed, t_min=sc.t_min, max_hits=1)
+    h_avg = float(hits["count"].float().mean().item())
+    flop_ray = 2 * math.log2(N) * FLOP_BOX + h_avg * (FLOP_HIT + FLOP_COMP)
+
+    # roofline of the dominant kernel (largest share of the step)
+    phases = {k: v["total_ms"] / args.steps for k, v in prof.items()}
+    dom = max(phases, key=phases.get)
+    dom_avg_ms = prof[dom]["avg_ms"]
+    C = Lt * K * 3
+    if dom in ("ff_trace", "opacity_pass1", "opacity_pass2"):
+        work = rays * flop_ray * (1.0 if dom == "ff_trace" else 1.0)
+        achieved = work / (dom_avg_ms * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "work_per_launch": {"rays": rays, "flop_per_ray": flop_ray, "hits_per_ray": h_avg}}
+    else:
+        per_launch = {"bounce": nnz * 8 + 3 * N * C * 4, "adjoint": nnz * 8 + 3 * N * C * 4,
+                      "sddmm": nnz * 12 + 2 * nb * N * C * 4}.get(dom, 0)
+        achieved = per_launch / (dom_avg_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": per_launch}
+
+    # HBM rate of the sparse bounce (for the record)
+    bounce_bytes = nnz * 8 + 3 * N * C * 4
+    bounce_gbs = bounce_bytes / (prof["bounce"]["avg_ms"] * 1e-3) / 1e9 if "bounce" in prof else None
+
+    result = {
+        "metric": METRIC,
+        "value": 1e3 / ms,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fruit bowl: {N} surfels, 20 spheres in a bowl, R={R} rays/surfel, top-{topk} F, "
+                               f"SH K={K}, {Lt} light, {nb} bounces, fwd+bwd (MSE-style grad_B)",
+                   "surfels": N, "rays_per_surfel": R, "topk": topk, "K": K, "lights": Lt, "bounces": nb},
+        "grays_per_s": grays,
+        "fwd_bwd_solves_per_s_fixed_F": (1e3 / t_solve_bwd) if t_solve_bwd > 0 else None,
+        "form_factor_ms": t_ff,
+        "nnz": nnz,
+        "bounce_hbm_GBps": bounce_gbs,
+        "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())},
+        "roofline": roof,
+    }
+
+    if not args.no_check:
+        result["err_vs_fp64"] = sampled_errors(g, sc, state, samp[:8], torch, np)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(sc, args.cpu_receivers, nnz, np)
+    print(json.dumps(result))
+
+
+def sampled_errors(g, sc, state, recv, torch, np):
+    """Relative max-norm error of sampled F rows and E rows vs the oracle."""
+    import oracle
+    te = oracle.default_t_eps(sc.surfels)
+    rp, col, val = state["ff"].csr()
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    rpo, co, vo, _ = oracle.ff_rows(sc.surfels, recv, sc.R, sc.seed, te, sc.t_min, sc.topk)
+    num = den = 0.0
+    for k, i in enumerate(recv):
+        a = dict(zip(col[rp[i]:rp[i + 1]].tolist(), val[rp[i]:rp[i + 1]].tolist()))
+        b = dict(zip(co[rpo[k]:rpo[k + 1]].tolist(), vo[rpo[k]:rpo[k + 1]].tolist()))
+        for j in set(a) | set(b):
+            num = max(num, abs(a.get(j, 0.0) - b.get(j, 0.0)))
+        den = max(den, max(b.values()) if b else 0.0)
+    Eg = g.direct_light(state["bvh"], torch.from_numpy(sc.albedo).cuda(), torch.from_numpy(sc.light_pos).cuda(),
+                        torch.from_numpy(sc.light_I).cuda(), sc.K).cpu().numpy()[recv]
+    Eo = oracle.direct_light(sc.surfels, sc.albedo, sc.light_pos, sc.light_I, sc.K, receivers=recv)
+    e_err = float(np.max(np.abs(Eg - Eo)) / max(np.max(np.abs(Eo)), 1e-300))
+    return {"F_rows": num / den if den > 0 else None, "E_rows": e_err, "rows_sampled": len(recv)}
+
+
+def cpu_baseline(sc, n_recv, nnz, np):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload, scaled to one full step."""
+    import oracle
+    import scenes
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    te = oracle.default_t_eps(sc.surfels)
+    rng = np.random.default_rng(11)
+    recv = np.sort(rng.choice(sc.n, size=n_recv, replace=False)).astype(np.int64)
+    t0 = time.perf_counter()
+    rp, co, vo, _ = oracle.ff_rows(sc.surfels, recv, sc.R, sc.seed, te, sc.t_min, sc.topk, n_threads=threads)
+    t_ff = time.perf_counter() - t0
+    gv = np.ones(vo.shape[0])
+    t0 = time.perf_counter()
+    oracle.opacity_backward(sc.surfels, sc.albedo, sc.R, sc.seed, te, sc.t_min, (rp, co, gv), receivers=recv,
+                            n_threads=threads)
+    t_ob = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.direct_light(sc.surfels, sc.albedo, sc.light_pos, sc.light_I, sc.K, te, receivers=recv,
+                        n_threads=threads)
+    t_dl = time.perf_counter() - t0
+    # bounces + adjoint on a 5,000-row synthetic operator of the same row
+    # length, scaled by the number of stored entries
+    m = 5000
+    rpc, cc, vc = scenes.seeded_csr(m, sc.topk, seed=5)
+    import scipy.sparse as sp
+    F = sp.csr_matrix((vc.astype(np.float64), cc, rpc), shape=(m, m))
+    C = sc.n_lights * sc.K * 3
+    Em = np.random.default_rng(1).uniform(0, 1, (m, C))
+    rho = np.random.default_rng(2).uniform(0.1, 0.9, (m, 3))
+    t0 = time.perf_counter()
+    Bm, tape = oracle.bounce(F, rho, Em, sc.n_bounces, keep_tape=True)
+    oracle.adjoint(F, rho, tape, Em)
+    t_lin = (time.perf_counter() - t0) * (nnz / max(F.nnz, 1))
+    per_receiver = (t_ff + t_ob + t_dl) / n_recv
+    t_step = per_receiver * sc.n + t_lin
+    return {"value": 1.0 / t_step, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_recv} receivers of the 100k fruit bowl (form-factor rows, compositing backward and direct "
+                      f"light, brute force) scaled x{sc.n / n_recv:.0f}, plus bounces+adjoint on a {m}-row operator "
+                      f"with {sc.topk} entries/row scaled to nnz={nnz}",
+            "seconds_measured": t_ff + t_ob + t_dl + t_lin * F.nnz / max(nnz, 1)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,272 @@
+/*
+ * gsrad.h -- C ABI of libgsrad: surfel-to-surfel light transport with
+ * alpha-composited visibility, its bounce iterations and their adjoint, on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: "Differentiable Light Transport with Gaussian Surfels via Adapted
+ * Radiosity for Efficient Relighting and Geometry Reconstruction" (Jiang et
+ * al., ACM TOG 2025, DOI 10.1145/3763305).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are DEVICE pointers unless stated otherwise, FP32,
+ *   C-contiguous, owned by the caller.  The library never frees them.
+ * - Opaque handles (gsrad_bvh, gsrad_ff, gsrad_tape) are owned by the
+ *   library and freed by the matching *_destroy.  Passing a pointer to a
+ *   NULL handle creates one; passing an existing handle re-uses (and if
+ *   needed grows) its device memory, so a steady-state loop allocates
+ *   nothing.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Work is queued
+ *   on it; arguments are validated synchronously before anything is queued.
+ *   gsrad_form_factors additionally waits for its own kernels once (it reads
+ *   the number of non-zeros and the overflow flags back to the host).
+ * - Errors: every call returns GSRAD_OK (0) or a negative code; the message
+ *   of the last error of the calling thread is gsrad_last_error().  No
+ *   exception crosses the ABI and handles stay valid after an error.
+ * - Layouts: E, B and their gradients are [N][Lt][K][3] (surfel, light,
+ *   spherical-harmonic coefficient in the order Y00, Y1-1, Y10, Y11, ...,
+ *   RGB), i.e. N rows of C = Lt*K*3 columns; colour = column % 3.  rho and
+ *   albedo are [N][3].  K must be 1, 4, 9 or 16 (SH degree 0..3).
+ */
+#ifndef GSRAD_H
+#define GSRAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gsrad_status;
+#define GSRAD_OK 0
+#define GSRAD_EINVAL (-1)    /* bad argument (null pointer, size, mismatch)   */
+#define GSRAD_ENOMEM (-2)    /* device allocation failed                       */
+#define GSRAD_EHIP (-3)      /* a HIP runtime call or kernel launch failed     */
+#define GSRAD_ENAN (-4)      /* non-finite value found by a check              */
+#define GSRAD_EOVERFLOW (-5) /* a fixed-capacity buffer overflowed             */
+#define GSRAD_ESTATE (-6)    /* handle used in the wrong state                 */
+
+#define GSRAD_FP32 0         /* precision argument of gsrad_transport_solve    */
+
+/*
+ * Gaussian surfels, structure of arrays, device FP32, length n
+ * (Sec. 3.1, Eq. G): centre p, unit tangents t_u, t_v, unit normal
+ * n = t_u x t_v, scales s_u, s_v > 0, and peak opacity o = alpha(0,0) of the
+ * App. E opacity profile alpha(u,v) = 1 - exp(-c exp(-1.7 (u^2+v^2))),
+ * c = -ln(1 - o).  o is clamped to [0, 0.9999].  The support is cut at
+ * u^2 + v^2 <= 9.
+ */
+typedef struct gsrad_surfels {
+    const float *px, *py, *pz;
+    const float *tux, *tuy, *tuz;
+    const float *tvx, *tvy, *tvz;
+    const float *nx, *ny, *nz;
+    const float *su, *sv;
+    const float *opacity;
+    int64_t n;
+} gsrad_surfels;
+
+/*
+ * Ray-cast form-factor estimation parameters.
+ *   rays_per_surfel  R >= 1: cosine-weighted hemisphere rays per receiver,
+ *                    drawn with Philox4x64-10, counter (ray, receiver,
+ *                    attempt, 0), key (seed, 0).
+ *   seed             Philox key.
+ *   t_min            compositing stops after the first hit that leaves the
+ *                    transmittance below t_min (0 = never).
+ *   t_eps            hits need t > t_eps; a value <= 0 selects
+ *                    1e-5 * diagonal of the bounding box of the centres.
+ *   topk             keep the topk largest entries per row (value desc,
+ *                    index asc), 0 = keep all.
+ */
+typedef struct gsrad_ff_params {
+    int32_t rays_per_surfel;
+    int32_t topk;
+    uint64_t seed;
+    float t_min;
+    float t_eps;
+} gsrad_ff_params;
+
+typedef struct gsrad_bvh gsrad_bvh;   /* prepared surfels + LBVH            */
+typedef struct gsrad_ff gsrad_ff;     /* sparse transport matrix F (CSR)    */
+typedef struct gsrad_tape gsrad_tape; /* forward iterates for the backward  */
+
+/* Library version string (static storage). */
+const char *gsrad_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *gsrad_last_error(void);
+
+/*
+ * Prepare the surfels and build a linear BVH over their 3-sigma bounds
+ * (Karras 2012: 30-bit Morton codes of the centres, stable radix sort,
+ * binary radix tree, bottom-up refit).  The surfel arrays are copied into
+ * the handle, so they may change or be freed afterwards; a change of any
+ * surfel (including its opacity) needs a new gsrad_build_bvh.
+ * EINVAL: s or bvh NULL, a field pointer NULL, n < 1.
+ */
+gsrad_status gsrad_build_bvh(const gsrad_surfels *s, gsrad_bvh **bvh, void *stream);
+
+/* Host query: number of surfels and the default t_eps (waits for the
+ * stream the BVH was built on). */
+gsrad_status gsrad_bvh_info(const gsrad_bvh *bvh, int64_t *n, float *t_eps_default);
+
+/* Host query: height of the BVH (waits for the build stream). */
+gsrad_status gsrad_bvh_height(const gsrad_bvh *bvh, int32_t *height);
+
+/*
+ * Effective area of every surfel, App. E closed form
+ * int_P alpha dA = (2 pi / 3.4) s_u s_v Ein(c), in FP64: area_out is a device
+ * double[n].  Used by the energy and reciprocity checks.
+ */
+gsrad_status gsrad_effective_area(const gsrad_bvh *bvh, double *area_out, void *stream);
+
+/*
+ * Lambertian reflectance per colour, rho_i = alpha_i(p_i) a_i = o_i a_i
+ * (Sec. 5.3: the receiver opacity absorbed into the BRDF; App. A: the DC
+ * coefficient c_00 = 4 a of the diffuse BRDF turns into the scalar a).
+ * albedo [n][3] -> rho_out [n][3].
+ */
+gsrad_status gsrad_reflectance(const gsrad_bvh *bvh, const float *albedo, float *rho_out, void *stream);
+
+/*
+ * Form factors by ray casting (Eq. final-radiosity with the receiver kernel
+ * a Dirac delta at p_i and a Lambertian receiver; App. B hemisphere form):
+ *   F_ij = (1/R) sum_rays sum_{composited front-face hits q on surfel j}
+ *          alpha_q prod_{k<q} (1 - alpha_k)
+ * with hits ordered by (t, j) (Eq. L_I), self hits disabled, back faces
+ * occluding but not reflecting (Sec. 5.1).  The result is a CSR matrix
+ * with columns ascending in each row, values FP32, deterministic (bit
+ * identical between runs).
+ * EINVAL: null arguments, R < 1, topk < 0, t_min < 0.
+ * EOVERFLOW: a receiver produced more composited hits or distinct senders
+ * than the per-receiver buffers hold (the message says how many).
+ */
+gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, gsrad_ff **ff, void *stream);
+
+/* Host query: matrix size and number of stored entries. */
+gsrad_status gsrad_ff_info(const gsrad_ff *ff, int64_t *n, int64_t *nnz);
+
+/* Read-only device views of the CSR arrays: row_ptr int64[n+1],
+ * col int32[nnz], val float[nnz].  Valid until the handle changes. */
+gsrad_status gsrad_ff_view(const gsrad_ff *ff, const int64_t **row_ptr, const int32_t **col, const float **val);
+
+/* Copy the CSR arrays into caller-owned device buffers of sizes n+1, nnz,
+ * nnz (queued on stream). */
+gsrad_status gsrad_ff_copy(const gsrad_ff *ff, int64_t *row_ptr, int32_t *col, float *val, void *stream);
+
+/*
+ * Wrap a caller-supplied CSR matrix (device arrays: row_ptr int64[n+1],
+ * col int32[nnz] ascending within rows, val float[nnz]) as a transport
+ * operator.  The arrays are copied.  For operator-level use of the solver
+ * with an F that did not come from gsrad_form_factors.
+ */
+gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                               const float *val, gsrad_ff **ff, void *stream);
+
+/*
+ * Direct light from isotropic point lights (Eq. forward rendering equation,
+ * direct illumination; lights are infinitesimal emitters, Sec. 5.1):
+ *   E_i,l,00,c = o_i a_i,c (2/sqrt(pi)) I_l max(0, n_i . w_il) / r_il^2 * T_il
+ * with w_il the unit direction from p_i to the light, r_il its distance and
+ * T_il the product of (1 - alpha) over every surfel crossed by the segment
+ * (both faces occlude, t_eps as in the BVH's default).  Coefficients with
+ * l >= 1 are written as 0.
+ * light_pos [Lt][3] and light_I [Lt] are device arrays; E_out [n][Lt][K][3].
+ */
+gsrad_status gsrad_direct_light(const gsrad_bvh *bvh, const float *albedo, const float *light_pos,
+                                const float *light_I, int32_t n_lights, int32_t K, float *E_out, void *stream);
+
+/*
+ * Bounce iterations (Eq. final-radiosity, scalar Lambertian transfer
+ * applied to every SH coefficient and light):
+ *   B^(0) = E,   B^(k+1) = E + rho * (F B^(k)),   k = 0 .. n_bounces-1
+ * B_out = B^(n_bounces) (n_bounces = 0 copies E: direct light only).  If
+ * tape is non-NULL the iterates B^(0..n-1) are kept in *tape (created or
+ * re-used) for gsrad_transport_backward.  precision must be GSRAD_FP32.
+ * The accumulation order is fixed, so results are bit identical between
+ * runs.
+ */
+gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const float *E, int32_t n_lights,
+                                   int32_t K, int32_t n_bounces, int32_t precision, float *B_out,
+                                   gsrad_tape **tape, void *stream);
+
+/*
+ * Exact adjoint of gsrad_transport_solve for dL/dB^(n) = grad_B (Eq.
+ * final_dL_dE in division-free form, truncated like the forward):
+ *   lambda^(n) = grad_B,  lambda^(k) = F^T (rho * lambda^(k+1))
+ *   grad_E     = sum_{k=0..n} lambda^(k)
+ *   grad_rho   = sum_{k<n} sum_{light, coef} lambda^(k+1) * (F B^(k))
+ *                (per colour; Eq. final-dl-dbrdf before its fixed-point limit)
+ *   grad_F[e]  = sum_{k<n} < rho_i * lambda_i^(k+1), B_j^(k) >  for the
+ *                stored entry e = (i, j) (decay term of Eq. dl-dgeo-0)
+ * grad_E [n][Lt][K][3], grad_rho [n][3], grad_F [nnz] in F's CSR order
+ * (may be NULL).  rho must be the rho of the forward call.
+ */
+gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape, const float *rho,
+                                      const float *grad_B, float *grad_E, float *grad_rho, float *grad_F,
+                                      void *stream);
+
+/*
+ * Opacity and albedo gradients (Eq. dl-dgeo-0, decay term, restricted to
+ * opacity; and rho = o a).  For every ray of every receiver i the hits of
+ * the forward pass are recomputed and, with G_q = grad_F[i, j_q] / R on
+ * front hits kept in F (0 otherwise) and w_q = alpha_q T_q,
+ *   dL/dalpha_q = G_q T_q - (sum_{p>q} G_p w_p) / (1 - alpha_q)
+ *   dL/do_j    += dL/dalpha_q * gamma_q (1 - o_j)^(gamma_q - 1),
+ *                 gamma_q = exp(-1.7 (u_q^2 + v_q^2))
+ * plus the receiver term dL/do_i += sum_c grad_rho_ic a_ic, and
+ * dL/da = grad_rho * o (both zero where the opacity clamp is active).
+ * grad_F is [nnz] in F's CSR order; grad_rho and albedo [n][3];
+ * grad_opacity [n], grad_albedo [n][3] (either may be NULL).  The hit
+ * recomputation needs the ff handle made from this bvh.
+ */
+gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *grad_F,
+                                    const float *grad_rho, const float *albedo, float *grad_opacity,
+                                    float *grad_albedo, void *stream);
+
+/*
+ * Recorded hits (Sec. 6: the pairs found visible in the forward pass), for
+ * diagnostics and tests: for every ray r of each listed receiver k (device
+ * int64 receivers[n_receivers], original indices) the ray direction
+ * dirs[(k*R + r)*3 + 0..2], the number of composited hits count[k*R + r] and
+ * the first max_hits of them in depth order: surfel hit_j, depth hit_t,
+ * front face hit_front, transmittance in front of it hit_T (arrays
+ * [n_receivers*R*max_hits]).  Same rays, decisions and compositing as
+ * gsrad_form_factors with the same parameters (t_eps <= 0: default).
+ */
+gsrad_status gsrad_ray_hits(const gsrad_bvh *bvh, const gsrad_ff_params *p, const int64_t *receivers,
+                            int64_t n_receivers, int32_t max_hits, float *dirs, int32_t *count, int32_t *hit_j,
+                            float *hit_t, int8_t *hit_front, float *hit_T, void *stream);
+
+/*
+ * FP64 checks on the GPU.  out_host[0] = || E + rho*(F B) - B ||_2 / ||B||_2
+ * (the fixed-point residual of B), out_host[1] = max_i sum_j F_ij (energy
+ * bound: <= 1 for ray-cast F), out_host[2] = 1 if any value of E, rho or
+ * B is not finite.  Waits for the stream.  Returns GSRAD_ENAN if
+ * out_host[2] != 0.
+ */
+gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, const float *B, int32_t n_lights,
+                         int32_t K, double *out_host, void *stream);
+
+/*
+ * Timing of the library's phases with HIP events recorded on the caller's
+ * stream around each kernel group (bvh_build, ff_trace, ff_aggregate,
+ * ff_csr, direct_light, bounce, transpose, adjoint, sddmm, opacity_pass1,
+ * opacity_pass2, opacity_finish).  gsrad_profile_enable(1) clears the record
+ * and starts recording, 0 stops.  gsrad_profile_report waits for the events
+ * and writes one line per phase into buf (host, len bytes):
+ * "name<TAB>count<TAB>total_ms<TAB>min_ms<TAB>max_ms\n".  Not thread safe.
+ */
+gsrad_status gsrad_profile_enable(int32_t on);
+gsrad_status gsrad_profile_report(char *buf, int64_t len);
+
+void gsrad_bvh_destroy(gsrad_bvh *bvh);
+void gsrad_ff_destroy(gsrad_ff *ff);
+void gsrad_tape_destroy(gsrad_tape *tape);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSRAD_H */

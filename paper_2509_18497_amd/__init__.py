@@ -1,0 +1,9 @@
+"""Surfel radiosity transport on AMD Instinct MI355X (gfx950).
+
+The HIP library libgsrad.so (C ABI in include/gsrad.h) holds every kernel;
+``paper_2509_18497_amd.gsrad`` is its Python binding.
+"""
+from . import gsrad  # noqa: F401
+from .gsrad import (BVH, FF, GsradError, RadiosityFn, Tape, build_bvh, check, direct_light,  # noqa: F401
+                    effective_area, ff_from_csr, form_factors, opacity_backward, ray_hits, reflectance, transport_backward,
+                    transport_solve, version)

@@ -1,0 +1,727 @@
+// C ABI of libgsrad: argument validation, handle lifetime, buffer reuse and
+// the order of kernel launches for each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bvh_build.h"
+#include "gsrad_internal.h"
+#include "trace_api.h"
+
+namespace gsrad {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+gsrad_status check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return GSRAD_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return GSRAD_EHIP;
+}
+
+// A growable device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    gsrad_status ensure(size_t want, const char *what) {
+        if (want <= bytes && p) return GSRAD_OK;
+        if (p) {
+            hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        if (want == 0) want = 256;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            set_error("out of device memory allocating %zu bytes for %s", want, what);
+            return GSRAD_ENOMEM;
+        }
+        bytes = want;
+        return GSRAD_OK;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const {
+        return static_cast<T *>(p);
+    }
+};
+
+// Maximum receivers traced per launch, so the hit slabs stay within a fixed
+// budget however large the scene is.
+constexpr size_t kSlabBudget = size_t(6) << 30;
+constexpr int kHitsPerRay = 64;     // slab capacity per ray (average ~25 here)
+constexpr int kLog2Table = 12;      // 4096-entry aggregation table per receiver
+
+// ---------------------------------------------------------------------------
+// optional per-phase timing with HIP events on the caller's stream
+// ---------------------------------------------------------------------------
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+static bool g_prof = false;
+static std::vector<ProfRec> g_recs;
+static std::vector<hipEvent_t> g_pool;
+
+static hipEvent_t prof_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+struct ProfScope {
+    ProfRec r{nullptr, nullptr, nullptr};
+    hipStream_t st;
+    ProfScope(const char *name, hipStream_t s) : st(s) {
+        if (!g_prof) return;
+        r.name = name;
+        r.a = prof_event();
+        if (r.a) hipEventRecord(r.a, st);
+    }
+    ~ProfScope() {
+        if (!g_prof || !r.a) return;
+        r.b = prof_event();
+        if (!r.b) return;
+        hipEventRecord(r.b, st);
+        g_recs.push_back(r);
+    }
+};
+
+static void prof_clear() {
+    for (ProfRec &r : g_recs) {
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+}
+
+}  // namespace gsrad
+
+using namespace gsrad;
+
+struct gsrad_bvh {
+    int64_t n = 0;
+    hipStream_t stream = nullptr;
+    DevBuf rec, nodes, leafbox, leaf_parent, inv, cst, opc, opraw, area, bounds, height, temp;
+    BvhBuffers B;
+    BvhDev dev() const {
+        BvhDev d;
+        d.n = n;
+        d.rec = B.rec;
+        d.nodes = B.nodes;
+        d.inv = B.inv;
+        d.c = B.cst;
+        d.op = B.opc;
+        d.raw_op = B.opraw;
+        d.bounds = B.bounds;
+        d.leaf_box_r = 0.0f;
+        return d;
+    }
+    ~gsrad_bvh() {
+        for (DevBuf *b : {&rec, &nodes, &leafbox, &leaf_parent, &inv, &cst, &opc, &opraw, &area, &bounds, &height, &temp})
+            b->release();
+    }
+};
+
+struct gsrad_ff {
+    int64_t n = 0, nnz = 0;
+    int max_row = 0;
+    DevBuf row_ptr, col, val;
+    // transpose, built on first use by the backward
+    bool has_t = false;
+    DevBuf t_row_ptr, t_col, t_val, perm, t_temp;
+    // provenance for the opacity backward
+    const gsrad_bvh *bvh = nullptr;
+    int R = 0, topk = 0;
+    uint64_t seed = 0;
+    float t_eps = 0.0f, t_min = 0.0f;
+    // scratch of the ray-cast path
+    DevBuf slab, slab_cnt, ell_col, ell_val, row_len, err, scan_temp;
+    Csr csr() const {
+        Csr c;
+        c.n = n;
+        c.nnz = nnz;
+        c.row_ptr = row_ptr.as<int64_t>();
+        c.col = col.as<int32_t>();
+        c.val = val.as<float>();
+        return c;
+    }
+    Csr csr_t() const {
+        Csr c;
+        c.n = n;
+        c.nnz = nnz;
+        c.row_ptr = t_row_ptr.as<int64_t>();
+        c.col = t_col.as<int32_t>();
+        c.val = t_val.as<float>();
+        return c;
+    }
+    ~gsrad_ff() {
+        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &slab_cnt, &ell_col,
+                          &ell_val, &row_len, &err, &scan_temp})
+            b->release();
+    }
+};
+
+struct gsrad_tape {
+    int64_t n = 0;
+    int C = 0, nb = 0, Lt = 0, K = 0;
+    const gsrad_ff *ff = nullptr;
+    DevBuf B, L, lam0, pp;
+    ~gsrad_tape() {
+        B.release();
+        L.release();
+        lam0.release();
+        pp.release();
+    }
+};
+
+namespace {
+
+#define GS_TRY(expr)                          \
+    do {                                      \
+        gsrad_status _s = (expr);             \
+        if (_s != GSRAD_OK) return _s;        \
+    } while (0)
+
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline gsrad_status einval(const char *msg) {
+    set_error("%s", msg);
+    return GSRAD_EINVAL;
+}
+
+bool valid_K(int K) { return K == 1 || K == 4 || K == 9 || K == 16; }
+
+__global__ void k_max_u32(const uint32_t *__restrict__ v, int64_t n, int *out) {
+    int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (int)v[i]);
+    atomicMax(out, m);
+}
+
+__global__ void k_row_len_from_ptr(const int64_t *__restrict__ rp, int64_t n, int *out) {
+    int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (int)(rp[i + 1] - rp[i]));
+    atomicMax(out, m);
+}
+
+gsrad_status ensure_transpose(gsrad_ff *ff, hipStream_t st) {
+    if (ff->has_t) return GSRAD_OK;
+    GS_TRY(ff->t_row_ptr.ensure((size_t)(ff->n + 1) * 8, "F^T row_ptr"));
+    GS_TRY(ff->t_col.ensure((size_t)std::max<int64_t>(ff->nnz, 1) * 4, "F^T col"));
+    GS_TRY(ff->t_val.ensure((size_t)std::max<int64_t>(ff->nnz, 1) * 4, "F^T val"));
+    GS_TRY(ff->perm.ensure((size_t)std::max<int64_t>(ff->nnz, 1) * 4, "F^T perm"));
+    const size_t tb = transpose_temp_bytes(ff->n, ff->nnz);
+    GS_TRY(ff->t_temp.ensure(tb, "transpose temp"));
+    GS_TRY(csr_transpose(ff->csr(), ff->t_row_ptr.as<int64_t>(), ff->t_col.as<int32_t>(), ff->t_val.as<float>(),
+                         ff->perm.as<uint32_t>(), ff->t_temp.p, tb, st));
+    ff->has_t = true;
+    return GSRAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gsrad_version(void) { return "gsrad 0.1 (gfx950)"; }
+
+const char *gsrad_last_error(void) { return g_err; }
+
+gsrad_status gsrad_build_bvh(const gsrad_surfels *s, gsrad_bvh **bvh, void *stream) {
+    if (!s || !bvh) return einval("gsrad_build_bvh: null argument");
+    if (s->n < 1) return einval("gsrad_build_bvh: n must be >= 1");
+    if (s->n >= (int64_t)1 << 31) return einval("gsrad_build_bvh: n must be < 2^31");
+    const float *f[] = {s->px, s->py, s->pz, s->tux, s->tuy, s->tuz, s->tvx, s->tvy, s->tvz, s->nx, s->ny, s->nz,
+                        s->su, s->sv, s->opacity};
+    for (const float *p : f)
+        if (!p) return einval("gsrad_build_bvh: a surfel field pointer is null");
+    const bool created = *bvh == nullptr;
+    gsrad_bvh *h = created ? new gsrad_bvh() : *bvh;
+    const int64_t n = s->n;
+    hipStream_t st = S(stream);
+    auto fail = [&](gsrad_status e) {
+        if (created) delete h;
+        return e;
+    };
+    gsrad_status e;
+#define ENS(buf, bytes, what)                                  \
+    if ((e = h->buf.ensure((size_t)(bytes), what)) != GSRAD_OK) return fail(e);
+    ENS(rec, n * sizeof(SurfRec), "surfel records");
+    ENS(nodes, std::max<int64_t>(n - 1, 1) * sizeof(Node), "bvh nodes");
+    ENS(leafbox, n * 6 * sizeof(float), "leaf boxes");
+    ENS(leaf_parent, n * 4, "leaf parents");
+    ENS(inv, n * 4, "inverse order");
+    ENS(cst, n * 4, "opacity constants");
+    ENS(opc, n * 4, "clamped opacity");
+    ENS(opraw, n * 4, "opacity");
+    ENS(area, n * 8, "areas");
+    ENS(bounds, 64, "bounds");
+    ENS(height, 64, "height");
+    ENS(temp, bvh_temp_bytes(n), "bvh temp");
+#undef ENS
+    h->n = n;
+    h->stream = st;
+    BvhBuffers &B = h->B;
+    B.rec = h->rec.as<SurfRec>();
+    B.nodes = h->nodes.as<Node>();
+    B.leafbox = h->leafbox.as<float>();
+    B.leaf_parent = h->leaf_parent.as<int32_t>();
+    B.inv = h->inv.as<int32_t>();
+    B.cst = h->cst.as<float>();
+    B.opc = h->opc.as<float>();
+    B.opraw = h->opraw.as<float>();
+    B.area = h->area.as<double>();
+    B.bounds = h->bounds.as<float>();
+    B.height = h->height.as<int>();
+    B.temp = h->temp.p;
+    B.temp_bytes = h->temp.bytes;
+    if ((e = check_hip(hipMemsetAsync(B.height, 0, sizeof(int), st), "bvh height")) != GSRAD_OK) return fail(e);
+    {
+        ProfScope ps("bvh_build", st);
+        if ((e = bvh_build(*s, B, st)) != GSRAD_OK) return fail(e);
+    }
+    *bvh = h;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_bvh_info(const gsrad_bvh *bvh, int64_t *n, float *t_eps_default) {
+    if (!bvh) return einval("gsrad_bvh_info: null handle");
+    if (n) *n = bvh->n;
+    if (t_eps_default) {
+        float b[8];
+        GS_TRY(check_hip(hipStreamSynchronize(bvh->stream), "bvh info sync"));
+        GS_TRY(check_hip(hipMemcpy(b, bvh->B.bounds, sizeof(b), hipMemcpyDeviceToHost), "bvh info copy"));
+        *t_eps_default = b[6];
+    }
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_bvh_height(const gsrad_bvh *bvh, int32_t *height) {
+    if (!bvh || !height) return einval("gsrad_bvh_height: null argument");
+    GS_TRY(check_hip(hipStreamSynchronize(bvh->stream), "bvh height sync"));
+    return check_hip(hipMemcpy(height, bvh->B.height, sizeof(int32_t), hipMemcpyDeviceToHost), "bvh height copy");
+}
+
+gsrad_status gsrad_effective_area(const gsrad_bvh *bvh, double *area_out, void *stream) {
+    if (!bvh || !area_out) return einval("gsrad_effective_area: null argument");
+    return check_hip(hipMemcpyAsync(area_out, bvh->B.area, (size_t)bvh->n * 8, hipMemcpyDeviceToDevice, S(stream)),
+                     "effective area copy");
+}
+
+gsrad_status gsrad_reflectance(const gsrad_bvh *bvh, const float *albedo, float *rho_out, void *stream) {
+    if (!bvh || !albedo || !rho_out) return einval("gsrad_reflectance: null argument");
+    return launch_reflectance(bvh->dev(), albedo, rho_out, S(stream));
+}
+
+gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, gsrad_ff **ff, void *stream) {
+    if (!bvh || !p || !ff) return einval("gsrad_form_factors: null argument");
+    if (p->rays_per_surfel < 1 || p->rays_per_surfel > (1 << 20))
+        return einval("gsrad_form_factors: rays_per_surfel must be in [1, 2^20]");
+    if (p->topk < 0 || p->topk > (1 << kLog2Table)) return einval("gsrad_form_factors: topk must be in [0, 4096]");
+    if (!(p->t_min >= 0.0f) || !(p->t_min <= 1.0f)) return einval("gsrad_form_factors: t_min must be in [0, 1]");
+    if (!std::isfinite(p->t_eps)) return einval("gsrad_form_factors: t_eps must be finite");
+    const bool created = *ff == nullptr;
+    gsrad_ff *h = created ? new gsrad_ff() : *ff;
+    auto fail = [&](gsrad_status e) {
+        if (created) delete h;
+        return e;
+    };
+    hipStream_t st = S(stream);
+    const int64_t n = bvh->n;
+    const int R = p->rays_per_surfel;
+    const int64_t cap = (int64_t)kHitsPerRay * R;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(kSlabBudget / ((size_t)cap * 8))));
+    const int64_t cap_row = p->topk > 0 ? p->topk : (1 << kLog2Table);
+    gsrad_status e;
+    float t_eps = p->t_eps;
+    if (!(t_eps > 0.0f)) {
+        float b[8];
+        if ((e = check_hip(hipStreamSynchronize(st), "ff sync")) != GSRAD_OK) return fail(e);
+        if ((e = check_hip(hipMemcpy(b, bvh->B.bounds, sizeof(b), hipMemcpyDeviceToHost), "ff t_eps")) != GSRAD_OK)
+            return fail(e);
+        t_eps = b[6];
+    }
+#define ENS(buf, bytes, what) \
+    if ((e = h->buf.ensure((size_t)(bytes), what)) != GSRAD_OK) return fail(e);
+    ENS(slab, chunk * cap * 8, "hit slab");
+    ENS(slab_cnt, chunk * 4, "slab counts");
+    ENS(ell_col, n * cap_row * 4, "row staging");
+    ENS(ell_val, n * cap_row * 4, "row staging");
+    ENS(row_len, n * 4, "row lengths");
+    ENS(err, 128, "error flags");
+    ENS(row_ptr, (n + 1) * 8, "row_ptr");
+    ENS(scan_temp, scan_temp_bytes(n), "scan temp");
+#undef ENS
+    int *err = h->err.as<int>();
+    if ((e = check_hip(hipMemsetAsync(err, 0, 64, st), "ff flags")) != GSRAD_OK) return fail(e);
+    const BvhDev bv = bvh->dev();
+    for (int64_t s0 = 0; s0 < n; s0 += chunk) {
+        const int64_t cnt = std::min(chunk, n - s0);
+        {
+            ProfScope ps("ff_trace", st);
+            if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, h->slab.as<uint2>(), cap,
+                                     h->slab_cnt.as<uint32_t>(), err, st)) != GSRAD_OK)
+                return fail(e);
+        }
+        hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->slab_cnt.as<uint32_t>(), cnt, err + 2);
+        ProfScope ps("ff_aggregate", st);
+        if ((e = launch_ff_aggregate(bv, h->slab.as<uint2>(), h->slab_cnt.as<uint32_t>(), cap, s0, cnt, R, p->topk,
+                                     kLog2Table, cap_row, h->ell_col.as<int32_t>(), h->ell_val.as<float>(),
+                                     h->row_len.as<uint32_t>(), err, st)) != GSRAD_OK)
+            return fail(e);
+    }
+    hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->row_len.as<uint32_t>(), n, err + 1);
+    if ((e = exclusive_scan_u32_i64(h->row_len.as<uint32_t>(), h->row_ptr.as<int64_t>(), n, h->scan_temp.p,
+                                    h->scan_temp.bytes, st)) != GSRAD_OK)
+        return fail(e);
+    int flags[4];
+    int64_t nnz = 0;
+    if ((e = check_hip(hipMemcpyAsync(flags, err, sizeof(flags), hipMemcpyDeviceToHost, st), "ff flags copy")) !=
+        GSRAD_OK)
+        return fail(e);
+    if ((e = check_hip(hipMemcpyAsync(&nnz, h->row_ptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st),
+                       "ff nnz copy")) != GSRAD_OK)
+        return fail(e);
+    if ((e = check_hip(hipStreamSynchronize(st), "ff sync")) != GSRAD_OK) return fail(e);
+    if (flags[0] != 0) {
+        set_error("gsrad_form_factors: overflow flags 0x%x (1 stack, 2 hit slab [max %d of %lld], 4 table, 8 row)",
+                  flags[0], flags[2], (long long)cap);
+        if (created) delete h;
+        return GSRAD_EOVERFLOW;
+    }
+    if ((e = h->col.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "F col")) != GSRAD_OK) return fail(e);
+    if ((e = h->val.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "F val")) != GSRAD_OK) return fail(e);
+    ProfScope ps_csr("ff_csr", st);
+    if ((e = launch_ell_to_csr(h->ell_col.as<int32_t>(), h->ell_val.as<float>(), cap_row, h->row_ptr.as<int64_t>(), n,
+                               h->col.as<int32_t>(), h->val.as<float>(), st)) != GSRAD_OK)
+        return fail(e);
+    h->n = n;
+    h->nnz = nnz;
+    h->max_row = flags[1];
+    h->has_t = false;
+    h->bvh = bvh;
+    h->R = R;
+    h->topk = p->topk;
+    h->seed = p->seed;
+    h->t_eps = t_eps;
+    h->t_min = p->t_min;
+    *ff = h;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_ff_info(const gsrad_ff *ff, int64_t *n, int64_t *nnz) {
+    if (!ff) return einval("gsrad_ff_info: null handle");
+    if (n) *n = ff->n;
+    if (nnz) *nnz = ff->nnz;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_ff_view(const gsrad_ff *ff, const int64_t **row_ptr, const int32_t **col, const float **val) {
+    if (!ff) return einval("gsrad_ff_view: null handle");
+    if (row_ptr) *row_ptr = ff->row_ptr.as<int64_t>();
+    if (col) *col = ff->col.as<int32_t>();
+    if (val) *val = ff->val.as<float>();
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_ff_copy(const gsrad_ff *ff, int64_t *row_ptr, int32_t *col, float *val, void *stream) {
+    if (!ff || !row_ptr || (ff->nnz > 0 && (!col || !val))) return einval("gsrad_ff_copy: null argument");
+    hipStream_t st = S(stream);
+    GS_TRY(check_hip(hipMemcpyAsync(row_ptr, ff->row_ptr.p, (size_t)(ff->n + 1) * 8, hipMemcpyDeviceToDevice, st),
+                     "ff copy row_ptr"));
+    if (ff->nnz > 0) {
+        GS_TRY(check_hip(hipMemcpyAsync(col, ff->col.p, (size_t)ff->nnz * 4, hipMemcpyDeviceToDevice, st), "ff copy col"));
+        GS_TRY(check_hip(hipMemcpyAsync(val, ff->val.p, (size_t)ff->nnz * 4, hipMemcpyDeviceToDevice, st), "ff copy val"));
+    }
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const float *val,
+                               gsrad_ff **ff, void *stream) {
+    if (!ff || !row_ptr || (nnz > 0 && (!col || !val))) return einval("gsrad_ff_from_csr: null argument");
+    if (n < 1 || nnz < 0 || nnz >= ((int64_t)1 << 32)) return einval("gsrad_ff_from_csr: bad size");
+    const bool created = *ff == nullptr;
+    gsrad_ff *h = created ? new gsrad_ff() : *ff;
+    auto fail = [&](gsrad_status e) {
+        if (created) delete h;
+        return e;
+    };
+    hipStream_t st = S(stream);
+    gsrad_status e;
+    if ((e = h->row_ptr.ensure((size_t)(n + 1) * 8, "row_ptr")) != GSRAD_OK) return fail(e);
+    if ((e = h->col.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "col")) != GSRAD_OK) return fail(e);
+    if ((e = h->val.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "val")) != GSRAD_OK) return fail(e);
+    if ((e = h->err.ensure(128, "flags")) != GSRAD_OK) return fail(e);
+    if ((e = check_hip(hipMemcpyAsync(h->row_ptr.p, row_ptr, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, st),
+                       "copy row_ptr")) != GSRAD_OK)
+        return fail(e);
+    if (nnz > 0) {
+        if ((e = check_hip(hipMemcpyAsync(h->col.p, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st), "copy col")) !=
+            GSRAD_OK)
+            return fail(e);
+        if ((e = check_hip(hipMemcpyAsync(h->val.p, val, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st), "copy val")) !=
+            GSRAD_OK)
+            return fail(e);
+    }
+    int mx = 0;
+    if ((e = check_hip(hipMemsetAsync(h->err.p, 0, 64, st), "flags")) != GSRAD_OK) return fail(e);
+    hipLaunchKernelGGL(k_row_len_from_ptr, dim3(64), dim3(256), 0, st, h->row_ptr.as<int64_t>(), n, h->err.as<int>());
+    if ((e = check_hip(hipMemcpyAsync(&mx, h->err.p, 4, hipMemcpyDeviceToHost, st), "max row")) != GSRAD_OK)
+        return fail(e);
+    if ((e = check_hip(hipStreamSynchronize(st), "ff_from_csr sync")) != GSRAD_OK) return fail(e);
+    h->n = n;
+    h->nnz = nnz;
+    h->max_row = mx;
+    h->has_t = false;
+    h->bvh = nullptr;
+    *ff = h;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_direct_light(const gsrad_bvh *bvh, const float *albedo, const float *light_pos,
+                                const float *light_I, int32_t n_lights, int32_t K, float *E_out, void *stream) {
+    if (!bvh || !albedo || !light_pos || !light_I || !E_out) return einval("gsrad_direct_light: null argument");
+    if (n_lights < 1) return einval("gsrad_direct_light: n_lights must be >= 1");
+    if (!valid_K(K)) return einval("gsrad_direct_light: K must be 1, 4, 9 or 16");
+    hipStream_t st = S(stream);
+    gsrad_bvh *h = const_cast<gsrad_bvh *>(bvh);
+    GS_TRY(h->height.ensure(64, "flags"));
+    ProfScope ps("direct_light", st);
+    return launch_direct(bvh->dev(), albedo, light_pos, light_I, n_lights, K, E_out, h->height.as<int>() + 4, st);
+}
+
+gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const float *E, int32_t n_lights, int32_t K,
+                                   int32_t n_bounces, int32_t precision, float *B_out, gsrad_tape **tape,
+                                   void *stream) {
+    if (!ff || !rho || !E || !B_out) return einval("gsrad_transport_solve: null argument");
+    if (n_lights < 1) return einval("gsrad_transport_solve: n_lights must be >= 1");
+    if (!valid_K(K)) return einval("gsrad_transport_solve: K must be 1, 4, 9 or 16");
+    if (n_bounces < 0 || n_bounces > 4096) return einval("gsrad_transport_solve: n_bounces must be in [0, 4096]");
+    if (precision != GSRAD_FP32) return einval("gsrad_transport_solve: only GSRAD_FP32 is supported");
+    hipStream_t st = S(stream);
+    const int C = n_lights * K * 3;
+    const int64_t n = ff->n;
+    const size_t row_bytes = (size_t)n * C * sizeof(float);
+    gsrad_tape *tp = nullptr;
+    bool created = false;
+    if (tape) {
+        created = *tape == nullptr;
+        tp = created ? new gsrad_tape() : *tape;
+    }
+    auto fail = [&](gsrad_status e) {
+        if (created) delete tp;
+        return e;
+    };
+    gsrad_status e;
+    const Csr F = ff->csr();
+    if (n_bounces == 0) {
+        if ((e = check_hip(hipMemcpyAsync(B_out, E, row_bytes, hipMemcpyDeviceToDevice, st), "solve copy")) !=
+            GSRAD_OK)
+            return fail(e);
+    } else {
+        float *slots = nullptr;
+        if (tp) {
+            if ((e = tp->B.ensure(row_bytes * n_bounces, "forward tape")) != GSRAD_OK) return fail(e);
+            slots = tp->B.as<float>();
+            if ((e = check_hip(hipMemcpyAsync(slots, E, row_bytes, hipMemcpyDeviceToDevice, st), "tape copy")) !=
+                GSRAD_OK)
+                return fail(e);
+        } else if (n_bounces > 1) {
+            gsrad_ff *m = const_cast<gsrad_ff *>(ff);
+            if ((e = m->slab.ensure(std::max(m->slab.bytes, row_bytes * 2), "ping-pong")) != GSRAD_OK) return fail(e);
+        }
+        const float *src = E;
+        for (int k = 0; k < n_bounces; ++k) {
+            float *dst;
+            if (k == n_bounces - 1) dst = B_out;
+            else if (tp) dst = slots + (size_t)(k + 1) * n * C;
+            else dst = const_cast<gsrad_ff *>(ff)->slab.as<float>() + (size_t)(k & 1) * n * C;
+            ProfScope ps("bounce", st);
+            if ((e = launch_bounce(F, C, src, E, rho, dst, st)) != GSRAD_OK) return fail(e);
+            src = dst;
+        }
+    }
+    if (tp) {
+        tp->n = n;
+        tp->C = C;
+        tp->nb = n_bounces;
+        tp->Lt = n_lights;
+        tp->K = K;
+        tp->ff = ff;
+        *tape = tp;
+    }
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape, const float *rho,
+                                      const float *grad_B, float *grad_E, float *grad_rho, float *grad_F,
+                                      void *stream) {
+    if (!ff || !tape || !rho || !grad_B || !grad_E) return einval("gsrad_transport_backward: null argument");
+    if (tape->ff != ff || tape->n != ff->n) return einval("gsrad_transport_backward: tape does not belong to this F");
+    hipStream_t st = S(stream);
+    gsrad_ff *f = const_cast<gsrad_ff *>(ff);
+    gsrad_tape *tp = const_cast<gsrad_tape *>(tape);
+    const int64_t n = ff->n;
+    const int C = tape->C, nb = tape->nb;
+    const size_t row_bytes = (size_t)n * C * sizeof(float);
+    GS_TRY(check_hip(hipMemcpyAsync(grad_E, grad_B, row_bytes, hipMemcpyDeviceToDevice, st), "grad_E init"));
+    if (nb == 0) {
+        if (grad_rho) GS_TRY(check_hip(hipMemsetAsync(grad_rho, 0, (size_t)n * 12, st), "grad_rho zero"));
+        if (grad_F && ff->nnz > 0)
+            GS_TRY(check_hip(hipMemsetAsync(grad_F, 0, (size_t)ff->nnz * 4, st), "grad_F zero"));
+        return GSRAD_OK;
+    }
+    {
+        ProfScope ps("transpose", st);
+        GS_TRY(ensure_transpose(f, st));
+    }
+    GS_TRY(tp->L.ensure(row_bytes * nb, "adjoint tape"));
+    GS_TRY(tp->lam0.ensure(row_bytes, "adjoint scratch"));
+    float *L = tp->L.as<float>();
+    GS_TRY(check_hip(hipMemcpyAsync(L + (size_t)(nb - 1) * n * C, grad_B, row_bytes, hipMemcpyDeviceToDevice, st),
+                     "adjoint seed"));
+    const Csr FT = f->csr_t();
+    for (int k = nb - 1; k >= 0; --k) {
+        const float *lam_in = L + (size_t)k * n * C;   // lambda^(k+1)
+        float *lam_out = k >= 1 ? L + (size_t)(k - 1) * n * C : tp->lam0.as<float>();
+        ProfScope ps("adjoint", st);
+        GS_TRY(launch_adjoint(FT, C, lam_in, rho, lam_out, grad_E, st));
+    }
+    ProfScope ps("sddmm", st);
+    if (grad_F || grad_rho) GS_TRY(launch_sddmm(ff->csr(), C, nb, tp->B.as<float>(), L, rho, grad_F, grad_rho, st));
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *grad_F,
+                                    const float *grad_rho, const float *albedo, float *grad_opacity,
+                                    float *grad_albedo, void *stream) {
+    if (!bvh || !ff) return einval("gsrad_opacity_backward: null handle");
+    if (grad_F && ff->bvh != bvh)
+        return einval("gsrad_opacity_backward: the F handle was not made from this BVH by gsrad_form_factors");
+    if (grad_rho && !albedo) return einval("gsrad_opacity_backward: grad_rho needs albedo");
+    hipStream_t st = S(stream);
+    gsrad_ff *f = const_cast<gsrad_ff *>(ff);
+    const int64_t n = bvh->n;
+    GS_TRY(f->t_temp.ensure(std::max(f->t_temp.bytes, (size_t)n * 8), "opacity accumulators"));
+    double *gacc = f->t_temp.as<double>();
+    GS_TRY(check_hip(hipMemsetAsync(gacc, 0, (size_t)n * 8, st), "opacity zero"));
+    if (grad_F && f->nnz > 0) {
+        if ((size_t)f->max_row * 8 + ff_stack_bytes(256) > 150 * 1024)
+            return einval("gsrad_opacity_backward: row too long for the LDS row cache");
+        GS_TRY(f->slab.ensure(std::max(f->slab.bytes, (size_t)n * f->R * 4), "ray sums"));
+        GS_TRY(f->err.ensure(128, "flags"));
+        for (int pass = 0; pass < 2; ++pass) {
+            ProfScope ps(pass == 0 ? "opacity_pass1" : "opacity_pass2", st);
+            GS_TRY(launch_opacity_bwd(bvh->dev(), f->R, f->seed, f->t_eps, f->t_min, f->row_ptr.as<int64_t>(),
+                                      f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1), f->slab.as<float>(), gacc,
+                                      pass, f->err.as<int>() + 8, st));
+        }
+    }
+    ProfScope ps("opacity_finish", st);
+    return launch_opacity_finish(bvh->dev(), gacc, grad_rho, albedo, grad_opacity, grad_albedo, st);
+}
+
+gsrad_status gsrad_ray_hits(const gsrad_bvh *bvh, const gsrad_ff_params *p, const int64_t *receivers,
+                            int64_t n_receivers, int32_t max_hits, float *dirs, int32_t *count, int32_t *hit_j,
+                            float *hit_t, int8_t *hit_front, float *hit_T, void *stream) {
+    if (!bvh || !p || !receivers || !dirs || !count) return einval("gsrad_ray_hits: null argument");
+    if (max_hits < 0 || (max_hits > 0 && (!hit_j || !hit_t || !hit_front || !hit_T)))
+        return einval("gsrad_ray_hits: bad hit buffers");
+    if (p->rays_per_surfel < 1 || n_receivers < 1) return einval("gsrad_ray_hits: bad sizes");
+    gsrad_bvh *h = const_cast<gsrad_bvh *>(bvh);
+    GS_TRY(h->height.ensure(64, "flags"));
+    return launch_ray_hits(bvh->dev(), p->rays_per_surfel, p->seed, p->t_eps, p->t_min, receivers, n_receivers,
+                           max_hits, dirs, count, hit_j, hit_t, hit_front, hit_T, h->height.as<int>() + 8, S(stream));
+}
+
+gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, const float *B, int32_t n_lights,
+                         int32_t K, double *out_host, void *stream) {
+    if (!ff || !rho || !E || !B || !out_host) return einval("gsrad_check: null argument");
+    if (n_lights < 1 || !valid_K(K)) return einval("gsrad_check: bad n_lights or K");
+    hipStream_t st = S(stream);
+    gsrad_ff *f = const_cast<gsrad_ff *>(ff);
+    GS_TRY(f->err.ensure(128, "check accumulators"));
+    double *acc = reinterpret_cast<double *>(f->err.as<char>() + 64);
+    GS_TRY(check_hip(hipMemsetAsync(acc, 0, 32, st), "check zero"));
+    GS_TRY(launch_check(ff->csr(), n_lights * K * 3, rho, E, B, acc, st));
+    double a[4];
+    GS_TRY(check_hip(hipMemcpyAsync(a, acc, sizeof(a), hipMemcpyDeviceToHost, st), "check copy"));
+    GS_TRY(check_hip(hipStreamSynchronize(st), "check sync"));
+    out_host[0] = a[1] > 0 ? std::sqrt(a[0] / a[1]) : std::sqrt(a[0]);
+    out_host[1] = a[2];
+    out_host[2] = a[3] > 0 ? 1.0 : 0.0;
+    if (a[3] > 0) {
+        set_error("gsrad_check: %g non-finite values", a[3]);
+        return GSRAD_ENAN;
+    }
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_profile_enable(int32_t on) {
+    prof_clear();
+    g_prof = on != 0;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_profile_report(char *buf, int64_t len) {
+    if (!buf || len < 1) return einval("gsrad_profile_report: null buffer");
+    struct Acc {
+        int64_t count = 0;
+        double total = 0.0, mn = 1e300, mx = 0.0;
+    };
+    std::map<std::string, Acc> acc;
+    for (ProfRec &r : g_recs) {
+        GS_TRY(check_hip(hipEventSynchronize(r.b), "profile sync"));
+        float ms = 0.0f;
+        GS_TRY(check_hip(hipEventElapsedTime(&ms, r.a, r.b), "profile elapsed"));
+        Acc &a = acc[r.name];
+        a.count += 1;
+        a.total += ms;
+        a.mn = std::min(a.mn, (double)ms);
+        a.mx = std::max(a.mx, (double)ms);
+    }
+    std::string out;
+    char line[256];
+    for (auto &kv : acc) {
+        snprintf(line, sizeof(line), "%s\t%lld\t%.6f\t%.6f\t%.6f\n", kv.first.c_str(), (long long)kv.second.count,
+                 kv.second.total, kv.second.mn, kv.second.mx);
+        out += line;
+    }
+    if ((int64_t)out.size() + 1 > len) return einval("gsrad_profile_report: buffer too small");
+    memcpy(buf, out.c_str(), out.size() + 1);
+    return GSRAD_OK;
+}
+
+void gsrad_bvh_destroy(gsrad_bvh *bvh) { delete bvh; }
+void gsrad_ff_destroy(gsrad_ff *ff) { delete ff; }
+void gsrad_tape_destroy(gsrad_tape *tape) { delete tape; }
+
+}  // extern "C"

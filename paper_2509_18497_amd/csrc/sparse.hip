@@ -1,0 +1,287 @@
+// Sparse transport kernels: CSR transpose (stable, deterministic), the
+// bounce SpMM B <- E + rho * (F B), its adjoint on F^T, the sampled
+// dense-dense product that yields dL/dF and dL/drho, and FP64 checks.
+//
+// Rows of B, E and the gradients hold C = Lt*K*3 contiguous floats; one
+// wave64 owns one output row and its lanes own columns, so every gathered
+// row of B is read with one coalesced access per wave.
+#include "gsrad_internal.h"
+#include "trace_api.h"
+
+namespace gsrad {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t g) {
+    const int64_t x = b & 7, q = b >> 3, per = g >> 3, rem = g & 7;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
+__global__ void __launch_bounds__(256) k_expand_rows(const int64_t *__restrict__ row_ptr, int64_t n,
+                                                     uint32_t *__restrict__ rows, uint32_t *__restrict__ keys_col,
+                                                     const int32_t *__restrict__ col, uint32_t *__restrict__ ids) {
+    const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / 64;
+    if (row >= n) return;
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    for (int64_t k = b + __lane_id(); k < e; k += 64) {
+        rows[k] = (uint32_t)row;
+        keys_col[k] = (uint32_t)col[k];
+        ids[k] = (uint32_t)k;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_col_hist(const int32_t *__restrict__ col, int64_t nnz,
+                                                  uint32_t *__restrict__ cnt) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * 256)
+        atomicAdd(&cnt[col[k]], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_transpose_gather(const uint32_t *__restrict__ sorted_ids,
+                                                          const uint32_t *__restrict__ rows,
+                                                          const float *__restrict__ val, int64_t nnz,
+                                                          int32_t *__restrict__ t_col, float *__restrict__ t_val,
+                                                          uint32_t *__restrict__ perm) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nnz) return;
+    const uint32_t e = sorted_ids[k];
+    t_col[k] = (int32_t)rows[e];
+    t_val[k] = val[e];
+    if (perm) perm[k] = e;
+}
+
+// B_out[row] = E[row] + rho[row] * sum_e val[e] * B_in[col[e]]
+__global__ void __launch_bounds__(256) k_bounce(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                const float *__restrict__ val, int64_t n, int C,
+                                                const float *__restrict__ Bin, const float *__restrict__ E,
+                                                const float *__restrict__ rho, float *__restrict__ Bout,
+                                                int64_t nblocks) {
+    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (row >= n) return;
+    const int lane = __lane_id();
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    for (int c0 = 0; c0 < C; c0 += 64) {
+        const int c = c0 + lane;
+        const bool on = c < C;
+        float acc = 0.0f;
+        for (int64_t k0 = b; k0 < e; k0 += 64) {
+            const int64_t kk = k0 + lane;
+            const int jv = kk < e ? col[kk] : 0;
+            const float vv = kk < e ? val[kk] : 0.0f;
+            const int m = (int)min<int64_t>(64, e - k0);
+            for (int q = 0; q < m; ++q) {
+                const int j = __builtin_amdgcn_readlane(jv, q);
+                const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), q));
+                if (on) acc = __builtin_fmaf(v, Bin[(int64_t)j * C + c], acc);
+            }
+        }
+        if (on) Bout[row * C + c] = __builtin_fmaf(rho[row * 3 + c % 3], acc, E[row * C + c]);
+    }
+}
+
+// lam_out[row] = sum_e val[e] * rho[col] * lam_in[col];  gE[row] += lam_out[row]
+__global__ void __launch_bounds__(256) k_adjoint(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                 const float *__restrict__ val, int64_t n, int C,
+                                                 const float *__restrict__ lam_in, const float *__restrict__ rho,
+                                                 float *__restrict__ lam_out, float *__restrict__ gE,
+                                                 int64_t nblocks) {
+    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (row >= n) return;
+    const int lane = __lane_id();
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    for (int c0 = 0; c0 < C; c0 += 64) {
+        const int c = c0 + lane;
+        const bool on = c < C;
+        const int colour = c % 3;
+        float acc = 0.0f;
+        for (int64_t k0 = b; k0 < e; k0 += 64) {
+            const int64_t kk = k0 + lane;
+            const int jv = kk < e ? col[kk] : 0;
+            const float vv = kk < e ? val[kk] : 0.0f;
+            const int m = (int)min<int64_t>(64, e - k0);
+            for (int q = 0; q < m; ++q) {
+                const int j = __builtin_amdgcn_readlane(jv, q);
+                const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), q));
+                if (on) acc = __builtin_fmaf(v * rho[(int64_t)j * 3 + colour], lam_in[(int64_t)j * C + c], acc);
+            }
+        }
+        if (on) {
+            lam_out[row * C + c] = acc;
+            gE[row * C + c] += acc;
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// For each stored entry e = (row, j):
+//   s_c = sum_k sum_{cols of colour c} lam^(k+1)[row] * B^(k)[j]
+//   grad_F[e] = sum_c rho[row, c] s_c ;  grad_rho[row, c] = sum_e F[e] s_c
+__global__ void __launch_bounds__(256) k_sddmm(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                               const float *__restrict__ val, int64_t n, int C, int nb,
+                                               const float *__restrict__ Bt, const float *__restrict__ Lt,
+                                               const float *__restrict__ rho, float *__restrict__ grad_F,
+                                               float *__restrict__ grad_rho, int64_t nblocks) {
+    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (row >= n) return;
+    const int lane = __lane_id();
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    const int64_t NC = n * (int64_t)C;
+    const float r0 = rho[row * 3 + 0], r1 = rho[row * 3 + 1], r2 = rho[row * 3 + 2];
+    float gr0 = 0.0f, gr1 = 0.0f, gr2 = 0.0f;
+    for (int64_t k = b; k < e; ++k) {
+        const int64_t j = col[k];
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        for (int c = lane; c < C; c += 64) {
+            float s = 0.0f;
+            for (int q = 0; q < nb; ++q) s = __builtin_fmaf(Lt[q * NC + row * C + c], Bt[q * NC + j * C + c], s);
+            const int colour = c % 3;
+            s0 += colour == 0 ? s : 0.0f;
+            s1 += colour == 1 ? s : 0.0f;
+            s2 += colour == 2 ? s : 0.0f;
+        }
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        if (lane == 0 && grad_F) grad_F[k] = r0 * s0 + r1 * s1 + r2 * s2;
+        const float f = val[k];
+        gr0 = __builtin_fmaf(f, s0, gr0);
+        gr1 = __builtin_fmaf(f, s1, gr1);
+        gr2 = __builtin_fmaf(f, s2, gr2);
+    }
+    if (lane == 0 && grad_rho) {
+        grad_rho[row * 3 + 0] = gr0;
+        grad_rho[row * 3 + 1] = gr1;
+        grad_rho[row * 3 + 2] = gr2;
+    }
+}
+
+// FP64 residual of the fixed point and the other checks.
+__global__ void __launch_bounds__(256) k_check(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                               const float *__restrict__ val, int64_t n, int C,
+                                               const float *__restrict__ rho, const float *__restrict__ E,
+                                               const float *__restrict__ B, double *acc) {
+    const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / 64;
+    if (row >= n) return;
+    const int lane = __lane_id();
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    double r2 = 0.0, b2 = 0.0, bad = 0.0, rs = 0.0;
+    for (int c = lane; c < C; c += 64) {
+        double s = 0.0;
+        for (int64_t k = b; k < e; ++k) s += (double)val[k] * (double)B[(int64_t)col[k] * C + c];
+        const double Bi = B[row * C + c], Ei = E[row * C + c], ri = rho[row * 3 + c % 3];
+        if (!isfinite(Bi) || !isfinite(Ei) || !isfinite(ri)) bad += 1.0;
+        const double r = Ei + ri * s - Bi;
+        r2 += r * r;
+        b2 += Bi * Bi;
+    }
+    for (int64_t k = b + lane; k < e; k += 64) rs += (double)val[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        r2 += __shfl_xor(r2, o, 64);
+        b2 += __shfl_xor(b2, o, 64);
+        bad += __shfl_xor(bad, o, 64);
+        rs += __shfl_xor(rs, o, 64);
+    }
+    if (lane == 0) {
+        unsafeAtomicAdd(&acc[0], r2);
+        unsafeAtomicAdd(&acc[1], b2);
+        unsafeAtomicAdd(&acc[3], bad);
+        // max of non-negative doubles through their bit patterns
+        atomicMax(reinterpret_cast<unsigned long long *>(&acc[2]), (unsigned long long)__double_as_longlong(rs));
+    }
+}
+
+inline unsigned row_blocks(int64_t n) { return (unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock); }
+
+}  // namespace
+
+size_t transpose_temp_bytes(int64_t n, int64_t nnz) {
+    size_t b = 0;
+    b += 4 * ((size_t)nnz * 4 + 256);       // rows, keys, ids, sorted keys
+    b += (size_t)nnz * 4 + 256;             // sorted ids
+    b += (size_t)n * 4 + 256;               // column counts
+    b += radix_temp_bytes(nnz) + 256;
+    b += scan_temp_bytes(n) + 256;
+    return b;
+}
+
+static inline char *carve(char *&p, size_t bytes) {
+    char *r = p;
+    p += (bytes + 255) / 256 * 256;
+    return r;
+}
+
+gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, float *t_val, uint32_t *perm,
+                           void *temp, size_t temp_bytes, hipStream_t st) {
+    const int64_t n = A.n, nnz = A.nnz;
+    char *p = static_cast<char *>(temp);
+    uint32_t *rows = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
+    uint32_t *keys = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
+    uint32_t *ids = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
+    uint32_t *skeys = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
+    uint32_t *sids = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(carve(p, (size_t)n * 4));
+    const size_t rbytes = radix_temp_bytes(nnz);
+    void *rtemp = carve(p, rbytes);
+    const size_t sbytes = scan_temp_bytes(n);
+    void *stemp = carve(p, sbytes);
+    if ((size_t)(p - static_cast<char *>(temp)) > temp_bytes) {
+        set_error("transpose: temp too small");
+        return GSRAD_EINVAL;
+    }
+    gsrad_status s = check_hip(hipMemsetAsync(cnt, 0, (size_t)n * 4, st), "transpose memset");
+    if (s != GSRAD_OK) return s;
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_expand_rows, dim3(row_blocks(n)), dim3(256), 0, st, A.row_ptr, n, rows, keys, A.col, ids);
+        const unsigned hb = (unsigned)std::min<int64_t>(4096, (nnz + 255) / 256);
+        hipLaunchKernelGGL(k_col_hist, dim3(hb), dim3(256), 0, st, A.col, nnz, cnt);
+        int bits = 1;
+        while (bits < 32 && ((int64_t)1 << bits) < n) ++bits;
+        s = radix_sort_pairs(keys, ids, skeys, sids, nnz, bits, rtemp, rbytes, st);
+        if (s != GSRAD_OK) return s;
+        hipLaunchKernelGGL(k_transpose_gather, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, sids, rows,
+                           A.val, nnz, t_col, t_val, perm);
+    }
+    s = exclusive_scan_u32_i64(cnt, t_row_ptr, n, stemp, sbytes, st);
+    if (s != GSRAD_OK) return s;
+    return check_hip(hipGetLastError(), "transpose");
+}
+
+gsrad_status launch_bounce(const Csr &F, int C, const float *Bin, const float *E, const float *rho, float *Bout,
+                           hipStream_t st) {
+    const unsigned g = row_blocks(F.n);
+    hipLaunchKernelGGL(k_bounce, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, Bin, E, rho, Bout,
+                       (int64_t)g);
+    return check_hip(hipGetLastError(), "bounce launch");
+}
+
+gsrad_status launch_adjoint(const Csr &FT, int C, const float *lam_in, const float *rho, float *lam_out, float *gE,
+                            hipStream_t st) {
+    const unsigned g = row_blocks(FT.n);
+    hipLaunchKernelGGL(k_adjoint, dim3(g), dim3(256), 0, st, FT.row_ptr, FT.col, FT.val, FT.n, C, lam_in, rho,
+                       lam_out, gE, (int64_t)g);
+    return check_hip(hipGetLastError(), "adjoint launch");
+}
+
+gsrad_status launch_sddmm(const Csr &F, int C, int nb, const float *Btape, const float *Ltape, const float *rho,
+                          float *grad_F, float *grad_rho, hipStream_t st) {
+    const unsigned g = row_blocks(F.n);
+    hipLaunchKernelGGL(k_sddmm, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, nb, Btape, Ltape, rho,
+                       grad_F, grad_rho, (int64_t)g);
+    return check_hip(hipGetLastError(), "sddmm launch");
+}
+
+gsrad_status launch_check(const Csr &F, int C, const float *rho, const float *E, const float *B, double *acc,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_check, dim3(row_blocks(F.n)), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, rho, E, B,
+                       acc);
+    return check_hip(hipGetLastError(), "check launch");
+}
+
+}  // namespace gsrad

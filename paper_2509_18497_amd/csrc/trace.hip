@@ -1,0 +1,648 @@
+// Ray casting through the surfel LBVH with alpha compositing.
+//
+// k_ff_trace      one workgroup per receiver surfel, one thread per ray:
+//                 multi-round k-buffer traversal (the KB nearest hits beyond
+//                 the last composited key per round, keys (t, j)), front-to-
+//                 back compositing, front-face weights appended to the
+//                 receiver's slab in HBM.
+// k_ff_aggregate  one workgroup per receiver: LDS hash table with 2^-40
+//                 fixed-point sums (integer adds are order independent, so F
+//                 is bit-deterministic), radix select of the top-k entries,
+//                 bitonic sort by column, one ELL row out.
+// k_direct        one thread per (surfel, light): shadow-ray transmittance.
+// k_opacity_bwd   compositing backward, two recomputing passes.
+#include "gsrad_internal.h"
+#include "trace_api.h"
+
+namespace gsrad {
+
+namespace {
+
+constexpr int kStack = 48;
+constexpr int kKB = 16;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of receivers so its L2 sees one region of the scene.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t g) {
+    const int64_t x = b & 7, q = b >> 3, per = g >> 3, rem = g & 7;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
+// Leaf visit of the sorted traversal: FP32 hit decision, then insertion
+// into the ascending k-buffer (keys (t bits, j), payload +-gamma with the
+// sign = front face).
+template <int KB>
+__device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int s, uint32_t self, float ox, float oy,
+                                           float oz, float dx, float dy, float dz, float t_eps, uint64_t last,
+                                           uint64_t (&key)[KB], float (&gam)[KB], int &found, float &t1) {
+    const SurfRec r = rec[s];
+    const uint32_t j = __float_as_uint(r.d.w);
+    if (j == self) return;
+    float t, r2;
+    bool front;
+    if (!hit_test(r, ox, oy, oz, dx, dy, dz, t_eps, 0.0f, false, t, r2, front)) return;
+    const uint64_t kk = ((uint64_t)__float_as_uint(t) << 32) | (uint64_t)j;
+    if (kk <= last) return;
+    ++found;
+    if (kk >= key[KB - 1]) return;
+    const float g = expf(-kKernelExp * r2);
+    uint64_t x = kk;
+    float y = front ? g : -g;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const bool lt = x < key[k];
+        const uint64_t tk = key[k];
+        const float tg = gam[k];
+        key[k] = lt ? x : tk;
+        gam[k] = lt ? y : tg;
+        x = lt ? tk : x;
+        y = lt ? tg : y;
+    }
+    if (found >= KB) t1 = __uint_as_float((uint32_t)(key[KB - 1] >> 32)) * 1.00001f + 1e-30f;
+}
+
+// All hits of one ray in (t, j) order, composited front to back until the
+// transmittance drops below t_min; on_hit(j, alpha, T_before, front, gamma)
+// is called for every composited hit (plus its depth t).  Returns the final
+// transmittance.
+template <int KB, typename OnHit>
+__device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float oy, float oz, float dx, float dy,
+                                              float dz, uint32_t self, float t_eps, float t_min,
+                                              uint32_t *stack, int stride, int *err, OnHit &&on_hit) {
+    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    uint64_t last = 0;
+    float T = 1.0f;
+    for (;;) {
+        uint64_t key[KB];
+        float gam[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            key[k] = ~0ull;
+            gam[k] = 0.0f;
+        }
+        int found = 0;
+        const float tlo = last ? __uint_as_float((uint32_t)(last >> 32)) : t_eps;
+        const float t0 = tlo * 0.99999f;
+        float t1 = INFINITY;
+        if (bv.n == 1) {
+            visit_leaf<KB>(bv.rec, 0, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, gam, found, t1);
+        } else {
+            int sp = 0, node = 0;
+            for (;;) {
+                const Node nd = bv.nodes[node];
+                float tn0, tn1;
+                bool h0 = slab(nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, ox, oy, oz, ix, iy, iz, t0, t1, tn0);
+                bool h1 = slab(nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, ox, oy, oz, ix, iy, iz, t0, t1, tn1);
+                const int c0 = nd.ch.x, c1 = nd.ch.y;
+                if (h0 && c0 < 0) {
+                    visit_leaf<KB>(bv.rec, ~c0, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, gam, found, t1);
+                    h0 = false;
+                }
+                if (h1 && c1 < 0) {
+                    visit_leaf<KB>(bv.rec, ~c1, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, gam, found, t1);
+                    h1 = false;
+                }
+                if (h0 && h1) {
+                    if (sp >= kStack) {
+                        atomicOr(err, kErrStack);
+                        return T;
+                    }
+                    const bool n0 = tn0 <= tn1;
+                    stack[sp * stride] = (uint32_t)(n0 ? c1 : c0);
+                    ++sp;
+                    node = n0 ? c0 : c1;
+                } else if (h0) {
+                    node = c0;
+                } else if (h1) {
+                    node = c1;
+                } else {
+                    if (sp == 0) break;
+                    --sp;
+                    node = (int)stack[sp * stride];
+                }
+            }
+        }
+        const int m = found < KB ? found : KB;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            if (k < m) {
+                const uint32_t j = (uint32_t)key[k];
+                const float g = fabsf(gam[k]);
+                const bool front = gam[k] > 0.0f;
+                const float x = bv.c[j] * g;
+                const float alpha = -expm1f(-x);
+                on_hit(j, alpha, T, front, g, __uint_as_float((uint32_t)(key[k] >> 32)));
+                T *= expf(-x);
+                if (T < t_min) return T;
+            }
+        }
+        // a full buffer pruned every box beyond its last entry, so more hits
+        // may exist: only a buffer that did not fill ends the ray
+        if (found < KB) return T;
+        last = key[KB - 1];
+    }
+}
+
+// Transmittance of the segment t in (t_lo, 1) of o + t d: product of
+// (1 - alpha) over every surfel crossed (order-free).
+__device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float oy, float oz, float dx, float dy,
+                                              float dz, uint32_t self, float t_lo, uint32_t *stack, int stride,
+                                              int *err) {
+    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    const float t0 = t_lo * 0.99999f, t1 = 1.00001f;
+    float T = 1.0f;
+    auto leaf = [&](int s) {
+        const SurfRec r = bv.rec[s];
+        const uint32_t j = __float_as_uint(r.d.w);
+        if (j == self) return;
+        float t, r2;
+        bool front;
+        if (!hit_test(r, ox, oy, oz, dx, dy, dz, t_lo, 1.0f, true, t, r2, front)) return;
+        T *= expf(-r.c.w * expf(-kKernelExp * r2));
+    };
+    if (bv.n == 1) {
+        leaf(0);
+        return T;
+    }
+    int sp = 0, node = 0;
+    for (;;) {
+        const Node nd = bv.nodes[node];
+        float tn0, tn1;
+        bool h0 = slab(nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, ox, oy, oz, ix, iy, iz, t0, t1, tn0);
+        bool h1 = slab(nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, ox, oy, oz, ix, iy, iz, t0, t1, tn1);
+        const int c0 = nd.ch.x, c1 = nd.ch.y;
+        if (h0 && c0 < 0) {
+            leaf(~c0);
+            h0 = false;
+        }
+        if (h1 && c1 < 0) {
+            leaf(~c1);
+            h1 = false;
+        }
+        if (h0 && h1) {
+            if (sp >= kStack) {
+                atomicOr(err, kErrStack);
+                return T;
+            }
+            stack[sp * stride] = (uint32_t)c1;
+            ++sp;
+            node = c0;
+        } else if (h0) {
+            node = c0;
+        } else if (h1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = (int)stack[sp * stride];
+        }
+    }
+    return T;
+}
+
+// ---------------------------------------------------------------------------
+// form factors
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
+                                                  int64_t s_begin, int64_t nblocks, uint2 *__restrict__ slab,
+                                                  int64_t cap, uint32_t *__restrict__ slab_cnt, int *err) {
+    extern __shared__ uint32_t stack_mem[];
+    __shared__ uint32_t cnt;
+    const int64_t b = xcd_block(blockIdx.x, nblocks);
+    const int tid = threadIdx.x;
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    const SurfRec rr = bv.rec[s_begin + b];
+    const uint32_t i = __float_as_uint(rr.d.w);
+    uint2 *out = slab + b * cap;
+    for (int r = tid; r < R; r += blockDim.x) {
+        float dx, dy, dz;
+        ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
+                      (uint64_t)i, seed, 0, dx, dy, dz);
+        trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x, err,
+                          [&](uint32_t j, float alpha, float T, bool front, float, float) {
+                              if (!front) return;
+                              const uint32_t pos = atomicAdd(&cnt, 1u);
+                              if (pos < cap) out[pos] = make_uint2(j, __float_as_uint(alpha * T));
+                          });
+    }
+    __syncthreads();
+    if (tid == 0) slab_cnt[b] = cnt;
+}
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t j, int log2h) { return (j * 0x9E3779B1u) >> (32 - log2h); }
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t badness(uint32_t j, float v) {
+    // ascending badness = value descending, then column ascending
+    return ((uint64_t)(~__float_as_uint(v)) << 32) | (uint64_t)j;
+}
+
+__global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__restrict__ slab,
+                                                      const uint32_t *__restrict__ slab_cnt, int64_t cap,
+                                                      int64_t s_begin, int R, int topk, int log2h, int64_t cap_row,
+                                                      int32_t *__restrict__ ell_col, float *__restrict__ ell_val,
+                                                      uint32_t *__restrict__ row_len, int *err) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    const int H = 1 << log2h;
+    unsigned long long *hval = reinterpret_cast<unsigned long long *>(sm);   // [H]
+    uint32_t *hkey = reinterpret_cast<uint32_t *>(hval + H);                  // [H]
+    uint32_t *cj = hkey + H;                                                  // [H]
+    float *cv = reinterpret_cast<float *>(cj + H);                            // [H]
+    __shared__ uint32_t m_sh, hist[256], dsel, before_sh;
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const uint32_t i = __float_as_uint(bv.rec[s_begin + b].d.w);
+    uint32_t count = slab_cnt[b];
+    if (count > cap) {
+        if (tid == 0) atomicOr(err, kErrSlab);
+        count = (uint32_t)cap;
+    }
+    for (int k = tid; k < H; k += 256) {
+        hkey[k] = kEmpty;
+        hval[k] = 0ull;
+    }
+    if (tid == 0) m_sh = 0;
+    __syncthreads();
+    const uint2 *in = slab + b * cap;
+    for (uint32_t e = tid; e < count; e += 256) {
+        const uint2 c = in[e];
+        const unsigned long long fx = (unsigned long long)__float2ull_rn(__uint_as_float(c.y) * kFixScaleF);
+        uint32_t h = hash_slot(c.x, log2h);
+        int probe = 0;
+        for (; probe < H; ++probe) {
+            const uint32_t prev = atomicCAS(&hkey[h], kEmpty, c.x);
+            if (prev == kEmpty || prev == c.x) {
+                atomicAdd(&hval[h], fx);
+                break;
+            }
+            h = (h + 1) & (uint32_t)(H - 1);
+        }
+        if (probe == H) atomicOr(err, kErrTable);
+    }
+    __syncthreads();
+    const double scale = 1.0 / (kFixScale * (double)R);
+    for (int k = tid; k < H; k += 256) {
+        if (hkey[k] != kEmpty) {
+            const uint32_t p = atomicAdd(&m_sh, 1u);
+            cj[p] = hkey[k];
+            cv[p] = (float)((double)hval[k] * scale);
+        }
+    }
+    __syncthreads();
+    uint32_t m = m_sh;
+    if (topk > 0 && m > (uint32_t)topk) {
+        // radix select of the topk-th smallest badness key, MSB first
+        uint64_t prefix = 0, pmask = 0;
+        uint32_t need = (uint32_t)topk;
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            hist[tid] = 0;
+            __syncthreads();
+            for (uint32_t e = tid; e < m; e += 256) {
+                const uint64_t key = badness(cj[e], cv[e]);
+                if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                uint32_t c4[4], s = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    c4[q] = hist[4 * tid + q];
+                    s += c4[q];
+                }
+                uint32_t run = wave_incl_scan_u32(s) - s;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (run < need && need <= run + c4[q]) {
+                        dsel = (uint32_t)(4 * tid + q);
+                        before_sh = run;
+                    }
+                    run += c4[q];
+                }
+            }
+            __syncthreads();
+            prefix |= (uint64_t)dsel << shift;
+            pmask |= 255ull << shift;
+            need -= before_sh;
+            __syncthreads();
+        }
+        // keep badness <= prefix (exactly topk entries: keys are unique)
+        if (tid == 0) m_sh = 0;
+        __syncthreads();
+        float *hv = reinterpret_cast<float *>(hval);
+        for (uint32_t e = tid; e < m; e += 256) {
+            if (badness(cj[e], cv[e]) <= prefix) {
+                const uint32_t p = atomicAdd(&m_sh, 1u);
+                hkey[p] = cj[e];
+                hv[p] = cv[e];
+            }
+        }
+        __syncthreads();
+        m = m_sh;
+        for (uint32_t e = tid; e < m; e += 256) {
+            cj[e] = hkey[e];
+            cv[e] = hv[e];
+        }
+        __syncthreads();
+    }
+    // bitonic sort of the m entries by column
+    uint32_t P = 1;
+    while (P < m) P <<= 1;
+    for (uint32_t e = m + tid; e < P; e += 256) cj[e] = kEmpty;
+    __syncthreads();
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = tid; t < P / 2; t += 256) {
+                const uint32_t idx = 2 * stride * (t / stride) + (t % stride);
+                const uint32_t par = idx + stride;
+                const bool asc = (idx & size) == 0;
+                const uint32_t a = cj[idx], c = cj[par];
+                if ((a > c) == asc) {
+                    cj[idx] = c;
+                    cj[par] = a;
+                    const float va = cv[idx];
+                    cv[idx] = cv[par];
+                    cv[par] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (m > cap_row) {
+        if (tid == 0) atomicOr(err, kErrRow);
+        m = (uint32_t)cap_row;
+    }
+    for (uint32_t e = tid; e < m; e += 256) {
+        ell_col[(int64_t)i * cap_row + e] = (int32_t)cj[e];
+        ell_val[(int64_t)i * cap_row + e] = cv[e];
+    }
+    if (tid == 0) row_len[i] = m;
+}
+
+__global__ void __launch_bounds__(256) k_ell_to_csr(const int32_t *__restrict__ ell_col,
+                                                    const float *__restrict__ ell_val, int64_t cap_row,
+                                                    const int64_t *__restrict__ row_ptr, int64_t n,
+                                                    int32_t *__restrict__ col, float *__restrict__ val) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (row >= n) return;
+    const int64_t b = row_ptr[row], len = row_ptr[row + 1] - b;
+    for (int64_t e = __lane_id(); e < len; e += 64) {
+        col[b + e] = ell_col[row * cap_row + e];
+        val[b + e] = ell_val[row * cap_row + e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct light
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(128) k_direct(BvhDev bv, const float *__restrict__ albedo,
+                                                const float *__restrict__ lpos, const float *__restrict__ lI, int Lt,
+                                                int K, float *__restrict__ E, int *err) {
+    extern __shared__ uint32_t stack_mem[];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= bv.n * Lt) return;
+    const int64_t i = idx / Lt;
+    const int l = (int)(idx - i * Lt);
+    const SurfRec rr = bv.rec[bv.inv[i]];
+    float *e = E + ((i * Lt + l) * K) * 3;
+    const float dx = __fsub_rn(lpos[3 * l + 0], rr.a.x);
+    const float dy = __fsub_rn(lpos[3 * l + 1], rr.a.y);
+    const float dz = __fsub_rn(lpos[3 * l + 2], rr.a.z);
+    const float dd = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __fmul_rn(dx, dx)));
+    const float len = sqrt_rn(dd);
+    const float ndot = rr.b.x * dx + rr.b.y * dy + rr.b.z * dz;
+    float base = 0.0f;
+    if (ndot > 0.0f && dd > 0.0f) {
+        const float t_lo = __fdiv_rn(bv.bounds[6], len);
+        const float T = trace_shadow(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, (uint32_t)i, t_lo,
+                                     stack_mem + threadIdx.x, blockDim.x, err);
+        base = bv.op[i] * 1.1283791670955126f * lI[l] * (ndot / len) / dd * T;
+    }
+    e[0] = base * albedo[3 * i + 0];
+    e[1] = base * albedo[3 * i + 1];
+    e[2] = base * albedo[3 * i + 2];
+    for (int c = 3; c < 3 * K; ++c) e[c] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// opacity backward (compositing backward, recomputing the hits)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float row_lookup(const uint32_t *lc, const float *lg, int len, uint32_t j) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lc[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < len && lc[lo] == j) ? lg[lo] : 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_opacity_bwd(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
+                                                     int64_t nblocks, const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, const float *__restrict__ gF,
+                                                     int max_row, float *__restrict__ wbuf, double *gacc, int pass,
+                                                     int *err) {
+    extern __shared__ uint32_t sm2[];
+    uint32_t *lc = sm2;                                   // [max_row]
+    float *lg = reinterpret_cast<float *>(lc + max_row);  // [max_row]
+    uint32_t *stack_mem = reinterpret_cast<uint32_t *>(lg + max_row);
+    const int64_t b = xcd_block(blockIdx.x, nblocks);
+    const int tid = threadIdx.x;
+    const SurfRec rr = bv.rec[b];
+    const uint32_t i = __float_as_uint(rr.d.w);
+    const int64_t e0 = row_ptr[i];
+    const int len = (int)(row_ptr[i + 1] - e0);
+    const float invR = 1.0f / (float)R;
+    for (int k = tid; k < len; k += blockDim.x) {
+        lc[k] = (uint32_t)col[e0 + k];
+        lg[k] = gF[e0 + k] * invR;
+    }
+    __syncthreads();
+    for (int r = tid; r < R; r += blockDim.x) {
+        float dx, dy, dz;
+        ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
+                      (uint64_t)i, seed, 0, dx, dy, dz);
+        if (pass == 0) {
+            float W = 0.0f;
+            trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x,
+                              err, [&](uint32_t j, float alpha, float T, bool front, float, float) {
+                                  if (front) W += row_lookup(lc, lg, len, j) * alpha * T;
+                              });
+            wbuf[(int64_t)i * R + r] = W;
+        } else {
+            const float W = wbuf[(int64_t)i * R + r];
+            float P = 0.0f;
+            trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x,
+                              err, [&](uint32_t j, float alpha, float T, bool front, float g, float) {
+                                  const float G = front ? row_lookup(lc, lg, len, j) : 0.0f;
+                                  const float gw = G * alpha * T;
+                                  const float S = W - P - gw;
+                                  P += gw;
+                                  const float oraw = bv.raw_op[j];
+                                  if (oraw > 0.0f && oraw < kOpacityMax) {
+                                      const float dLda = G * T - S / (1.0f - alpha);
+                                      const float dado = g * expf(bv.c[j] * (1.0f - g));
+                                      atomicAdd(&gacc[j], (double)(dLda * dado));
+                                  }
+                              });
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_opacity_finish(BvhDev bv, const double *__restrict__ gacc,
+                                                        const float *__restrict__ grad_rho,
+                                                        const float *__restrict__ albedo, float *grad_o, float *grad_a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= bv.n) return;
+    const float oraw = bv.raw_op[i];
+    const bool inside = oraw > 0.0f && oraw < kOpacityMax;
+    double g = gacc ? gacc[i] : 0.0;
+    if (grad_rho && albedo && inside)
+        g += (double)grad_rho[3 * i] * albedo[3 * i] + (double)grad_rho[3 * i + 1] * albedo[3 * i + 1] +
+             (double)grad_rho[3 * i + 2] * albedo[3 * i + 2];
+    if (grad_o) grad_o[i] = (float)g;
+    if (grad_a) {
+        const float o = bv.op[i];
+        for (int c = 0; c < 3; ++c) grad_a[3 * i + c] = grad_rho ? grad_rho[3 * i + c] * o : 0.0f;
+    }
+}
+
+// Composited hit list of every ray of the listed receivers (diagnostics and
+// parity tests): direction, count, and per hit (j, t, front).
+__global__ void __launch_bounds__(256) k_ray_hits(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
+                                                  const int64_t *__restrict__ recv, int max_hits, float *dirs,
+                                                  int32_t *cnt, int32_t *hj, float *ht, int8_t *hf, float *hT, int *err) {
+    extern __shared__ uint32_t stack_mem[];
+    const int64_t k = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t i = recv[k];
+    const SurfRec rr = bv.rec[bv.inv[i]];
+    for (int r = tid; r < R; r += blockDim.x) {
+        float dx, dy, dz;
+        ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
+                      (uint64_t)i, seed, 0, dx, dy, dz);
+        const int64_t ray = k * R + r;
+        dirs[ray * 3 + 0] = dx;
+        dirs[ray * 3 + 1] = dy;
+        dirs[ray * 3 + 2] = dz;
+        int q = 0;
+        const float te = t_eps > 0.0f ? t_eps : bv.bounds[6];
+        trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, (uint32_t)i, te, t_min, stack_mem + tid,
+                          blockDim.x, err, [&](uint32_t j, float, float T, bool front, float, float t) {
+                              if (q < max_hits) {
+                                  hj[ray * max_hits + q] = (int32_t)j;
+                                  ht[ray * max_hits + q] = t;
+                                  hf[ray * max_hits + q] = front ? 1 : 0;
+                                  hT[ray * max_hits + q] = T;
+                              }
+                              ++q;
+                          });
+        cnt[ray] = q;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_reflectance(BvhDev bv, const float *__restrict__ albedo, float *rho) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= bv.n) return;
+    const float o = bv.op[i];
+    rho[3 * i + 0] = o * albedo[3 * i + 0];
+    rho[3 * i + 1] = o * albedo[3 * i + 1];
+    rho[3 * i + 2] = o * albedo[3 * i + 2];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+size_t ff_stack_bytes(int threads) { return (size_t)kStack * threads * sizeof(uint32_t); }
+
+gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
+                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, int *err, hipStream_t st) {
+    const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
+    hipLaunchKernelGGL(k_ff_trace, dim3((unsigned)count), dim3(threads), ff_stack_bytes(threads), st, bv, R, seed,
+                       t_eps, t_min, s_begin, count, slab, cap, slab_cnt, err);
+    return check_hip(hipGetLastError(), "ff trace launch");
+}
+
+size_t ff_aggregate_smem(int log2h) { return (size_t)(1 << log2h) * (8 + 4 + 4 + 4); }
+
+gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *slab, const uint32_t *slab_cnt, int64_t cap,
+                                 int64_t s_begin, int64_t count, int R, int topk, int log2h, int64_t cap_row,
+                                 int32_t *ell_col, float *ell_val, uint32_t *row_len, int *err, hipStream_t st) {
+    const size_t smem = ff_aggregate_smem(log2h);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_aggregate),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_ff_aggregate, dim3((unsigned)count), dim3(256), smem, st, bv, slab, slab_cnt, cap, s_begin, R,
+                       topk, log2h, cap_row, ell_col, ell_val, row_len, err);
+    return check_hip(hipGetLastError(), "ff aggregate launch");
+}
+
+gsrad_status launch_ell_to_csr(const int32_t *ell_col, const float *ell_val, int64_t cap_row, const int64_t *row_ptr,
+                               int64_t n, int32_t *col, float *val, hipStream_t st) {
+    hipLaunchKernelGGL(k_ell_to_csr, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, ell_col, ell_val, cap_row,
+                       row_ptr, n, col, val);
+    return check_hip(hipGetLastError(), "ell to csr launch");
+}
+
+gsrad_status launch_direct(const BvhDev &bv, const float *albedo, const float *lpos, const float *lI, int Lt, int K,
+                           float *E, int *err, hipStream_t st) {
+    const int64_t total = bv.n * Lt;
+    hipLaunchKernelGGL(k_direct, dim3((unsigned)((total + 127) / 128)), dim3(128), ff_stack_bytes(128), st, bv, albedo,
+                       lpos, lI, Lt, K, E, err);
+    return check_hip(hipGetLastError(), "direct light launch");
+}
+
+gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min,
+                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float *wbuf,
+                                double *gacc, int pass, int *err, hipStream_t st) {
+    const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
+    const size_t smem = (size_t)max_row * 8 + ff_stack_bytes(threads);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_opacity_bwd), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024 - 4096);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_opacity_bwd, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, seed, t_eps, t_min, bv.n,
+                       row_ptr, col, gF, max_row, wbuf, gacc, pass, err);
+    return check_hip(hipGetLastError(), "opacity backward launch");
+}
+
+gsrad_status launch_opacity_finish(const BvhDev &bv, const double *gacc, const float *grad_rho, const float *albedo,
+                                   float *grad_o, float *grad_a, hipStream_t st) {
+    hipLaunchKernelGGL(k_opacity_finish, dim3((unsigned)((bv.n + 255) / 256)), dim3(256), 0, st, bv, gacc, grad_rho,
+                       albedo, grad_o, grad_a);
+    return check_hip(hipGetLastError(), "opacity finish launch");
+}
+
+gsrad_status launch_ray_hits(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, const int64_t *recv,
+                             int64_t n_recv, int max_hits, float *dirs, int32_t *cnt, int32_t *hj, float *ht,
+                             int8_t *hf, float *hT, int *err, hipStream_t st) {
+    const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
+    hipLaunchKernelGGL(k_ray_hits, dim3((unsigned)n_recv), dim3(threads), ff_stack_bytes(threads), st, bv, R, seed,
+                       t_eps, t_min, recv, max_hits, dirs, cnt, hj, ht, hf, hT, err);
+    return check_hip(hipGetLastError(), "ray hits launch");
+}
+
+gsrad_status launch_reflectance(const BvhDev &bv, const float *albedo, float *rho, hipStream_t st) {
+    hipLaunchKernelGGL(k_reflectance, dim3((unsigned)((bv.n + 255) / 256)), dim3(256), 0, st, bv, albedo, rho);
+    return check_hip(hipGetLastError(), "reflectance launch");
+}
+
+}  // namespace gsrad

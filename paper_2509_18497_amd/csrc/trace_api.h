@@ -1,0 +1,62 @@
+// Host launchers of the ray-casting kernels (trace.hip) and the sparse
+// kernels (sparse.hip).
+#pragma once
+
+#include "gsrad_internal.h"
+
+namespace gsrad {
+
+// device error flag bits
+constexpr int kErrStack = 1;   // traversal stack overflow
+constexpr int kErrSlab = 2;    // a receiver produced more hits than its slab holds
+constexpr int kErrTable = 4;   // more distinct senders than the aggregation table holds
+constexpr int kErrRow = 8;     // row longer than the ELL capacity
+
+size_t ff_stack_bytes(int threads);
+size_t ff_aggregate_smem(int log2h);
+gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
+                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, int *err, hipStream_t st);
+gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *slab, const uint32_t *slab_cnt, int64_t cap,
+                                 int64_t s_begin, int64_t count, int R, int topk, int log2h, int64_t cap_row,
+                                 int32_t *ell_col, float *ell_val, uint32_t *row_len, int *err, hipStream_t st);
+gsrad_status launch_ell_to_csr(const int32_t *ell_col, const float *ell_val, int64_t cap_row, const int64_t *row_ptr,
+                               int64_t n, int32_t *col, float *val, hipStream_t st);
+gsrad_status launch_direct(const BvhDev &bv, const float *albedo, const float *lpos, const float *lI, int Lt, int K,
+                           float *E, int *err, hipStream_t st);
+gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min,
+                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float *wbuf,
+                                double *gacc, int pass, int *err, hipStream_t st);
+gsrad_status launch_opacity_finish(const BvhDev &bv, const double *gacc, const float *grad_rho, const float *albedo,
+                                   float *grad_o, float *grad_a, hipStream_t st);
+gsrad_status launch_ray_hits(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, const int64_t *recv,
+                             int64_t n_recv, int max_hits, float *dirs, int32_t *cnt, int32_t *hj, float *ht,
+                             int8_t *hf, float *hT, int *err, hipStream_t st);
+gsrad_status launch_reflectance(const BvhDev &bv, const float *albedo, float *rho, hipStream_t st);
+
+// sparse.hip
+struct Csr {
+    int64_t n = 0, nnz = 0;
+    const int64_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const float *val = nullptr;
+};
+
+size_t transpose_temp_bytes(int64_t n, int64_t nnz);
+gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, float *t_val, uint32_t *perm,
+                           void *temp, size_t temp_bytes, hipStream_t st);
+// Bout = E + rho * (F Bin), rows of C columns
+gsrad_status launch_bounce(const Csr &F, int C, const float *Bin, const float *E, const float *rho, float *Bout,
+                           hipStream_t st);
+// lam_out = F^T (rho * lam_in) given FT = transpose(F); gE += lam_out
+gsrad_status launch_adjoint(const Csr &FT, int C, const float *lam_in, const float *rho, float *lam_out, float *gE,
+                            hipStream_t st);
+// grad_F[e] and grad_rho from the forward tape B^(k) and the adjoint tape
+// lambda^(k+1), both [nb][N][C]
+gsrad_status launch_sddmm(const Csr &F, int C, int nb, const float *Btape, const float *Ltape, const float *rho,
+                          float *grad_F, float *grad_rho, hipStream_t st);
+// FP64 checks: acc[0] = sum r^2, acc[1] = sum B^2, acc[2] = max row sum,
+// acc[3] = number of non-finite inputs
+gsrad_status launch_check(const Csr &F, int C, const float *rho, const float *E, const float *B, double *acc,
+                          hipStream_t st);
+
+}  // namespace gsrad

@@ -1,0 +1,335 @@
+"""Python binding of libgsrad (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name in
+``include/gsrad.h``; all arithmetic runs in the HIP kernels of libgsrad.so.
+PyTorch supplies device memory and the current stream.  If the shared
+library is missing this module raises on first use: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsrad.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENAN, EOVERFLOW, ESTATE = 0, -1, -2, -3, -4, -5, -6
+FP32 = 0
+SOA = ("px", "py", "pz", "tux", "tuy", "tuz", "tvx", "tvy", "tvz", "nx", "ny", "nz", "su", "sv", "opacity")
+
+EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_info", "gsrad_bvh_height",
+           "gsrad_effective_area", "gsrad_reflectance", "gsrad_form_factors", "gsrad_ff_info", "gsrad_ff_view",
+           "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_direct_light", "gsrad_transport_solve",
+           "gsrad_transport_backward", "gsrad_opacity_backward", "gsrad_ray_hits", "gsrad_check", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy",
+           "gsrad_ff_destroy", "gsrad_tape_destroy")
+
+
+class GsradError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+class _Surfels(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in SOA] + [("n", ctypes.c_int64)]
+
+
+class _FFParams(ctypes.Structure):
+    _fields_ = [("rays_per_surfel", ctypes.c_int32), ("topk", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("t_min", ctypes.c_float), ("t_eps", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgsrad.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2509_18497_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        pvp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "gsrad_version": ([], ctypes.c_char_p),
+            "gsrad_last_error": ([], ctypes.c_char_p),
+            "gsrad_build_bvh": ([ctypes.POINTER(_Surfels), pvp, vp], i32),
+            "gsrad_bvh_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(f32)], i32),
+            "gsrad_bvh_height": ([vp, ctypes.POINTER(i32)], i32),
+            "gsrad_effective_area": ([vp, vp, vp], i32),
+            "gsrad_reflectance": ([vp, vp, vp, vp], i32),
+            "gsrad_form_factors": ([vp, ctypes.POINTER(_FFParams), pvp, vp], i32),
+            "gsrad_ff_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
+            "gsrad_ff_view": ([vp, pvp, pvp, pvp], i32),
+            "gsrad_ff_copy": ([vp, vp, vp, vp, vp], i32),
+            "gsrad_ff_from_csr": ([i64, i64, vp, vp, vp, pvp, vp], i32),
+            "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
+            "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
+            "gsrad_transport_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
+            "gsrad_opacity_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
+            "gsrad_ray_hits": ([vp, ctypes.POINTER(_FFParams), vp, i64, i32, vp, vp, vp, vp, vp, vp, vp], i32),
+            "gsrad_check": ([vp, vp, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_double), vp], i32),
+            "gsrad_profile_enable": ([i32], i32),
+            "gsrad_profile_report": ([ctypes.c_char_p, i64], i32),
+            "gsrad_bvh_destroy": ([vp], None),
+            "gsrad_ff_destroy": ([vp], None),
+            "gsrad_tape_destroy": ([vp], None),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int, fn: str):
+    if status != OK:
+        raise GsradError(fn, status, lib().gsrad_last_error().decode())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float32, name: str = "tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self):
+        self.h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        if self.h and self.h.value and _lib is not None:
+            getattr(_lib, self._destroy)(self.h)
+            self.h = ctypes.c_void_p(None)
+
+
+class BVH(_Handle):
+    _destroy = "gsrad_bvh_destroy"
+    n = 0
+
+    def info(self):
+        n, te = ctypes.c_int64(), ctypes.c_float()
+        _check(lib().gsrad_bvh_info(self.h, ctypes.byref(n), ctypes.byref(te)), "gsrad_bvh_info")
+        return int(n.value), float(te.value)
+
+    def height(self) -> int:
+        h = ctypes.c_int32()
+        _check(lib().gsrad_bvh_height(self.h, ctypes.byref(h)), "gsrad_bvh_height")
+        return int(h.value)
+
+
+class FF(_Handle):
+    _destroy = "gsrad_ff_destroy"
+
+    def info(self):
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gsrad_ff_info(self.h, ctypes.byref(n), ctypes.byref(nnz)), "gsrad_ff_info")
+        return int(n.value), int(nnz.value)
+
+    def csr(self, stream=None):
+        """Copies of (row_ptr int64[n+1], col int32[nnz], val float32[nnz])."""
+        n, nnz = self.info()
+        dev = torch.device("cuda")
+        rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)
+        _check(lib().gsrad_ff_copy(self.h, _ptr(rp, torch.int64), _ptr(col, torch.int32), _ptr(val), _stream(stream)),
+               "gsrad_ff_copy")
+        return rp, col[:nnz], val[:nnz]
+
+
+class Tape(_Handle):
+    _destroy = "gsrad_tape_destroy"
+
+
+def version() -> str:
+    return lib().gsrad_version().decode()
+
+
+def build_bvh(surfels: Dict[str, torch.Tensor], bvh: Optional[BVH] = None, stream=None) -> BVH:
+    n = int(surfels["px"].shape[0])
+    ptrs = []
+    for f in SOA:
+        t = surfels[f]
+        if t.shape != (n,):
+            raise ValueError(f"surfel field {f} must have shape ({n},)")
+        ptrs.append(_ptr(t, name=f))
+    s = _Surfels(*ptrs, n)
+    out = bvh if bvh is not None else BVH()
+    _check(lib().gsrad_build_bvh(ctypes.byref(s), ctypes.byref(out.h), _stream(stream)), "gsrad_build_bvh")
+    out.n = n
+    return out
+
+
+def effective_area(bvh: BVH, stream=None) -> torch.Tensor:
+    a = torch.empty(bvh.n, dtype=torch.float64, device="cuda")
+    _check(lib().gsrad_effective_area(bvh.h, _ptr(a, torch.float64), _stream(stream)), "gsrad_effective_area")
+    return a
+
+
+def reflectance(bvh: BVH, albedo: torch.Tensor, stream=None) -> torch.Tensor:
+    if albedo.shape != (bvh.n, 3):
+        raise ValueError("albedo must be [n, 3]")
+    rho = torch.empty_like(albedo)
+    _check(lib().gsrad_reflectance(bvh.h, _ptr(albedo, name="albedo"), _ptr(rho), _stream(stream)),
+           "gsrad_reflectance")
+    return rho
+
+
+def form_factors(bvh: BVH, rays_per_surfel: int, seed: int, t_min: float = 1e-4, t_eps: float = 0.0,
+                 topk: int = 0, ff: Optional[FF] = None, stream=None) -> FF:
+    p = _FFParams(int(rays_per_surfel), int(topk), int(seed) & 0xFFFFFFFFFFFFFFFF, float(t_min), float(t_eps))
+    out = ff if ff is not None else FF()
+    _check(lib().gsrad_form_factors(bvh.h, ctypes.byref(p), ctypes.byref(out.h), _stream(stream)),
+           "gsrad_form_factors")
+    return out
+
+
+def ff_from_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, ff: Optional[FF] = None,
+                stream=None) -> FF:
+    n = int(row_ptr.shape[0]) - 1
+    nnz = int(col.shape[0])
+    out = ff if ff is not None else FF()
+    _check(lib().gsrad_ff_from_csr(n, nnz, _ptr(row_ptr, torch.int64, "row_ptr"), _ptr(col, torch.int32, "col"),
+                                   _ptr(val, name="val"), ctypes.byref(out.h), _stream(stream)), "gsrad_ff_from_csr")
+    return out
+
+
+def direct_light(bvh: BVH, albedo: torch.Tensor, light_pos: torch.Tensor, light_I: torch.Tensor, K: int,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    Lt = int(light_pos.shape[0])
+    if light_pos.shape != (Lt, 3) or light_I.shape != (Lt,):
+        raise ValueError("light_pos must be [Lt, 3] and light_I [Lt]")
+    E = out if out is not None else torch.empty((bvh.n, Lt, K, 3), dtype=torch.float32, device="cuda")
+    _check(lib().gsrad_direct_light(bvh.h, _ptr(albedo, name="albedo"), _ptr(light_pos, name="light_pos"),
+                                    _ptr(light_I, name="light_I"), Lt, int(K), _ptr(E, name="E"), _stream(stream)),
+           "gsrad_direct_light")
+    return E
+
+
+def transport_solve(ff: FF, rho: torch.Tensor, E: torch.Tensor, n_bounces: int, tape: Optional[Tape] = None,
+                    keep_tape: bool = True, out: Optional[torch.Tensor] = None, stream=None):
+    """B = E + rho*(F B) iterated n_bounces times from B^(0) = E.  E is
+    [n, Lt, K, 3].  Returns (B, tape)."""
+    if E.dim() != 4 or E.shape[3] != 3:
+        raise ValueError("E must be [n, Lt, K, 3]")
+    n, Lt, K = int(E.shape[0]), int(E.shape[1]), int(E.shape[2])
+    B = out if out is not None else torch.empty_like(E)
+    tp = tape if tape is not None else (Tape() if keep_tape else None)
+    _check(lib().gsrad_transport_solve(ff.h, _ptr(rho, name="rho"), _ptr(E, name="E"), Lt, K, int(n_bounces), FP32,
+                                       _ptr(B, name="B"), ctypes.byref(tp.h) if tp is not None else None,
+                                       _stream(stream)), "gsrad_transport_solve")
+    return B, tp
+
+
+def transport_backward(ff: FF, tape: Tape, rho: torch.Tensor, grad_B: torch.Tensor, want_grad_F: bool = True,
+                       stream=None):
+    grad_E = torch.empty_like(grad_B)
+    grad_rho = torch.empty_like(rho)
+    _, nnz = ff.info()
+    grad_F = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda") if want_grad_F else None
+    _check(lib().gsrad_transport_backward(ff.h, tape.h, _ptr(rho, name="rho"), _ptr(grad_B, name="grad_B"),
+                                          _ptr(grad_E), _ptr(grad_rho), _ptr(grad_F) if grad_F is not None else None,
+                                          _stream(stream)), "gsrad_transport_backward")
+    return grad_E, grad_rho, (grad_F[:nnz] if grad_F is not None else None)
+
+
+def opacity_backward(bvh: BVH, ff: FF, grad_F: Optional[torch.Tensor], grad_rho: Optional[torch.Tensor],
+                     albedo: Optional[torch.Tensor], stream=None):
+    grad_o = torch.empty(bvh.n, dtype=torch.float32, device="cuda")
+    grad_a = torch.empty((bvh.n, 3), dtype=torch.float32, device="cuda")
+    gF = grad_F
+    if gF is not None and gF.numel() == 0:
+        gF = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().gsrad_opacity_backward(bvh.h, ff.h, _ptr(gF, name="grad_F"), _ptr(grad_rho, name="grad_rho"),
+                                        _ptr(albedo, name="albedo"), _ptr(grad_o), _ptr(grad_a), _stream(stream)),
+           "gsrad_opacity_backward")
+    return grad_o, grad_a
+
+
+def ray_hits(bvh: BVH, receivers: torch.Tensor, rays_per_surfel: int, seed: int, t_min: float = 1e-4,
+             t_eps: float = 0.0, max_hits: int = 256, stream=None) -> dict:
+    """Directions and composited hit lists of every ray of the listed
+    receivers (same decisions as form_factors)."""
+    p = _FFParams(int(rays_per_surfel), 0, int(seed) & 0xFFFFFFFFFFFFFFFF, float(t_min), float(t_eps))
+    m = int(receivers.shape[0])
+    R = int(rays_per_surfel)
+    dev = torch.device("cuda")
+    dirs = torch.empty((m, R, 3), dtype=torch.float32, device=dev)
+    cnt = torch.empty((m, R), dtype=torch.int32, device=dev)
+    hj = torch.full((m, R, max_hits), -1, dtype=torch.int32, device=dev)
+    ht = torch.zeros((m, R, max_hits), dtype=torch.float32, device=dev)
+    hf = torch.zeros((m, R, max_hits), dtype=torch.int8, device=dev)
+    hT = torch.zeros((m, R, max_hits), dtype=torch.float32, device=dev)
+    _check(lib().gsrad_ray_hits(bvh.h, ctypes.byref(p), _ptr(receivers, torch.int64, "receivers"), m, int(max_hits),
+                                _ptr(dirs), _ptr(cnt, torch.int32), _ptr(hj, torch.int32), _ptr(ht),
+                                _ptr(hf, torch.int8), _ptr(hT), _stream(stream)), "gsrad_ray_hits")
+    return {"dirs": dirs, "count": cnt, "j": hj, "t": ht, "front": hf, "T": hT}
+
+
+def check(ff: FF, rho: torch.Tensor, E: torch.Tensor, B: torch.Tensor, stream=None) -> dict:
+    """FP64 residual ||E + rho*(F B) - B|| / ||B||, max row sum of F, and
+    whether any input is non-finite."""
+    out = (ctypes.c_double * 3)()
+    Lt, K = int(E.shape[1]), int(E.shape[2])
+    st = lib().gsrad_check(ff.h, _ptr(rho), _ptr(E), _ptr(B), Lt, K, out, _stream(stream))
+    res = {"residual": out[0], "max_row_sum": out[1], "non_finite": bool(out[2])}
+    if st not in (OK, ENAN):
+        _check(st, "gsrad_check")
+    return res
+
+
+def profile_enable(on: bool = True):
+    _check(lib().gsrad_profile_enable(1 if on else 0), "gsrad_profile_enable")
+
+
+def profile_report() -> Dict[str, dict]:
+    """Per-phase HIP-event timings since profile_enable(True)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().gsrad_profile_report(buf, len(buf)), "gsrad_profile_report")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, tot, mn, mx = line.split("\t")
+        out[name] = {"count": int(cnt), "total_ms": float(tot), "min_ms": float(mn), "max_ms": float(mx),
+                     "avg_ms": float(tot) / max(int(cnt), 1)}
+    return out
+
+
+class RadiosityFn(torch.autograd.Function):
+    """B = solve(F(opacity), rho = o*a, E) with the hand-written adjoint:
+    backward returns dL/dopacity (compositing backward through F plus the
+    receiver term), dL/dalbedo and dL/dE.  The BVH and F handles must have
+    been built from the same opacity values."""
+
+    @staticmethod
+    def forward(ctx, opacity, albedo, E, bvh: BVH, ff: FF, n_bounces: int):
+        rho = reflectance(bvh, albedo.contiguous())
+        B, tape = transport_solve(ff, rho, E.contiguous(), n_bounces)
+        ctx.bvh, ctx.ff, ctx.tape = bvh, ff, tape
+        ctx.save_for_backward(rho, albedo)
+        return B
+
+    @staticmethod
+    def backward(ctx, grad_B):
+        rho, albedo = ctx.saved_tensors
+        grad_E, grad_rho, grad_F = transport_backward(ctx.ff, ctx.tape, rho, grad_B.contiguous())
+        grad_o, grad_a = opacity_backward(ctx.bvh, ctx.ff, grad_F, grad_rho, albedo.contiguous())
+        return grad_o, grad_a, grad_E, None, None, None

@@ -1,0 +1,295 @@
+"""GPU path (libgsrad through its C ABI) against the FP64 oracle.
+
+Bars: ray directions and hit lists bit-exact; FP32 results within a
+relative max-norm error of 1e-4 (form factors, direct light, bounces,
+gradients), as stated for FP32 results of this path.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from tests.gpu_common import dev, dev_surfels, gpu_csr, rel_err  # noqa: E402
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_18497_amd as g
+    g.gsrad.lib()
+    return g
+
+
+def _scene(name, n=None, **kw):
+    return scenes.make_config(name, n=n, **kw)
+
+
+SMALL = [
+    ("furnace", dict(), 64, 0),
+    ("box_room", dict(n=2500), 32, 0),
+    ("fruit_bowl", dict(n=3000), 32, 0),
+    ("fruit_bowl", dict(n=3000), 32, 48),
+]
+
+
+# ---------------------------------------------------------------------------
+# geometry, rays and hits
+# ---------------------------------------------------------------------------
+def test_t_eps_and_area_match_oracle(g, orc):
+    sc = _scene("fruit_bowl", n=5000)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    n, te = bvh.info()
+    assert n == sc.n
+    assert np.float32(te) == orc.default_t_eps(sc.surfels)
+    A = g.effective_area(bvh).cpu().numpy()
+    ref = orc.effective_area(sc.surfels["su"], sc.surfels["sv"], sc.surfels["opacity"])
+    assert np.max(np.abs(A - ref) / ref) < 1e-12
+    assert 0 < bvh.height() < 48
+
+
+@pytest.mark.parametrize("name,kw,R,seed", [("fruit_bowl", dict(n=3000), 32, 3), ("box_room", dict(n=2000), 32, 2),
+                                            ("furnace", dict(), 64, 1)])
+def test_ray_directions_and_hit_lists_bit_exact(g, orc, name, kw, R, seed):
+    sc = _scene(name, **kw)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    te = orc.default_t_eps(sc.surfels)
+    rng = np.random.default_rng(0)
+    recv = np.sort(rng.choice(sc.n, size=12, replace=False)).astype(np.int64)
+    out = g.ray_hits(bvh, dev(recv), R, seed, t_min=1e-4, max_hits=512)
+    dirs = out["dirs"].cpu().numpy()
+    cnt = out["count"].cpu().numpy()
+    hj = out["j"].cpu().numpy()
+    ht = out["t"].cpu().numpy()
+    hf = out["front"].cpu().numpy()
+    compared = boundary = 0
+    for k, i in enumerate(recv):
+        for r in range(R):
+            ref = orc.trace_ray(sc.surfels, int(i), r, seed, te, 1e-4)
+            assert np.array_equal(dirs[k, r].view(np.uint32), ref["d"].view(np.uint32)), (i, r)
+            m_ref, m = ref["n_comp"], int(cnt[k, r])
+            m0 = min(m, m_ref)
+            assert np.array_equal(hj[k, r, :m0], ref["j"][:m0]), (i, r)
+            assert np.array_equal(ht[k, r, :m0].view(np.uint32), ref["t"][:m0].view(np.uint32)), (i, r)
+            assert np.array_equal(hf[k, r, :m0].astype(bool), ref["front"][:m0]), (i, r)
+            if m != m_ref:
+                # the cut T < t_min is taken in FP32 on the GPU and FP64 in the
+                # oracle: they may differ only when T sits on the threshold
+                boundary += 1
+                q = m0 - 1
+                T_after = ref["T"][q] * (1 - ref["alpha"][q])
+                assert abs(T_after - 1e-4) / 1e-4 < 1e-4, (i, r, m, m_ref, T_after)
+                assert abs(m - m_ref) == 1
+            compared += 1
+    assert compared == len(recv) * R
+    assert boundary <= max(2, compared // 500)
+
+
+# ---------------------------------------------------------------------------
+# form factors
+# ---------------------------------------------------------------------------
+def _ff_compare(g, orc, sc, R, topk, seed=None):
+    seed = sc.seed if seed is None else seed
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    ff = g.form_factors(bvh, R, seed, t_min=1e-4, topk=topk)
+    Fg = gpu_csr(ff)
+    te = orc.default_t_eps(sc.surfels)
+    Fo, diag = orc.ff_matrix(sc.surfels, R, seed, te, 1e-4, topk)
+    return Fg, Fo, bvh, ff
+
+
+@pytest.mark.parametrize("name,kw,R,topk", SMALL)
+def test_form_factors_match_oracle(g, orc, name, kw, R, topk):
+    sc = _scene(name, **kw)
+    Fg, Fo, _, _ = _ff_compare(g, orc, sc, R, topk)
+    D = (Fg - Fo).toarray() if sc.n <= 4000 else None
+    err = np.max(np.abs(D)) / np.max(np.abs(Fo.data))
+    assert err < TOL, err
+    if topk == 0:
+        # same sparsity except entries created or dropped by a cut that sits
+        # on the threshold (weights <= t_min / R)
+        diff = (Fg != 0).astype(int) - (Fo != 0).astype(int)
+        assert abs(diff).sum() <= max(4, Fo.nnz // 20000)
+    else:
+        assert np.all(np.diff(Fg.indptr) <= topk)
+    # rows are sorted and F's row sums stay below one
+    for i in range(0, sc.n, max(1, sc.n // 50)):
+        cols = Fg.indices[Fg.indptr[i]:Fg.indptr[i + 1]]
+        assert np.all(np.diff(cols) > 0)
+    assert np.asarray(Fg.sum(axis=1)).max() <= 1.0 + 1e-6
+
+
+def test_form_factors_are_deterministic(g):
+    sc = _scene("fruit_bowl", n=6000)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    a = g.form_factors(bvh, 64, 11, topk=64).csr()
+    b = g.form_factors(bvh, 64, 11, topk=64).csr()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65])
+def test_form_factors_tiny_scenes(g, orc, n):
+    sur = scenes.random_frame_surfels(n, seed=40 + n, extent=0.3, scale=(0.1, 0.3), opacity=(0.5, 0.99))
+    bvh = g.build_bvh(dev_surfels(sur))
+    ff = g.form_factors(bvh, 100, 5, t_min=1e-4)
+    Fg = gpu_csr(ff)
+    Fo, _ = orc.ff_matrix(sur, 100, 5, None, 1e-4, 0)
+    if Fo.nnz == 0:
+        assert Fg.nnz == 0
+    else:
+        assert rel_err(Fg.toarray(), Fo.toarray()) < TOL
+
+
+def test_form_factors_rays_not_multiple_of_wave(g, orc):
+    sc = _scene("box_room", n=1500)
+    Fg, Fo, _, _ = _ff_compare(g, orc, sc, 45, 0, seed=9)
+    assert rel_err(Fg.toarray(), Fo.toarray()) < TOL
+
+
+# ---------------------------------------------------------------------------
+# direct light
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,kw,K", [("furnace", {}, 1), ("box_room", dict(n=3000), 9),
+                                       ("fruit_bowl", dict(n=4000), 16), ("multi_light", dict(n=2000), 4)])
+def test_direct_light_matches_oracle(g, orc, name, kw, K):
+    sc = _scene(name, **kw)
+    lights = sc.light_pos[:8]
+    li = sc.light_I[:8]
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    E = g.direct_light(bvh, dev(sc.albedo), dev(lights), dev(li), K).cpu().numpy()
+    ref = orc.direct_light(sc.surfels, sc.albedo, lights, li, K)
+    assert rel_err(E, ref) < TOL
+    assert np.all(E[:, :, 1:, :] == 0)
+
+
+# ---------------------------------------------------------------------------
+# bounces and adjoint (operator level: seeded F, E, rho, grad_B)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,k,Lt,K,nb", [(700, 40, 1, 16, 8), (513, 17, 3, 9, 5), (300, 64, 1, 1, 3),
+                                         (257, 0, 2, 4, 2), (1000, 30, 2, 16, 0), (129, 5, 1, 9, 1)])
+def test_bounce_and_adjoint_match_oracle(g, orc, n, k, Lt, K, nb):
+    rp, c, v = scenes.seeded_csr(n, k, seed=n + k)
+    F = sp.csr_matrix((v.astype(np.float64), c, rp), shape=(n, n))
+    rho = scenes.seeded_array((n, 3), seed=1, lo=0.1, hi=0.9)
+    E = scenes.seeded_array((n, Lt, K, 3), seed=2)
+    gB = scenes.seeded_array((n, Lt, K, 3), seed=3, lo=-1, hi=1)
+    ff = g.ff_from_csr(dev(rp), dev(c), dev(v))
+    B, tape = g.transport_solve(ff, dev(rho), dev(E), nb)
+    Bo, tp = orc.bounce(F, rho, E, nb, keep_tape=True)
+    assert rel_err(B.cpu().numpy(), Bo) < TOL
+    gE, gr, gF = g.transport_backward(ff, tape, dev(rho), dev(gB))
+    gEo, gro, gFo = orc.adjoint(F, rho, tp, gB)
+    assert rel_err(gE.cpu().numpy(), gEo) < TOL
+    if nb > 0:
+        assert rel_err(gr.cpu().numpy(), gro) < TOL
+        if F.nnz:
+            assert rel_err(gF.cpu().numpy(), gFo) < TOL
+    else:
+        assert np.all(gr.cpu().numpy() == 0)
+
+
+def test_solve_without_tape_and_determinism(g):
+    n = 2000
+    rp, c, v = scenes.seeded_csr(n, 50, seed=5)
+    ff = g.ff_from_csr(dev(rp), dev(c), dev(v))
+    rho = dev(scenes.seeded_array((n, 3), seed=1, lo=0.1, hi=0.9))
+    E = dev(scenes.seeded_array((n, 2, 9, 3), seed=2))
+    B1, _ = g.transport_solve(ff, rho, E, 6, keep_tape=False)
+    B2, _ = g.transport_solve(ff, rho, E, 6)
+    assert torch.equal(B1, B2)
+
+
+def test_check_residual_and_nan(g):
+    n = 800
+    rp, c, v = scenes.seeded_csr(n, 30, seed=8, row_sum=0.5)
+    ff = g.ff_from_csr(dev(rp), dev(c), dev(v))
+    rho = dev(scenes.seeded_array((n, 3), seed=1, lo=0.1, hi=0.9))
+    E = dev(scenes.seeded_array((n, 1, 4, 3), seed=2))
+    B, _ = g.transport_solve(ff, rho, E, 60, keep_tape=False)
+    res = g.check(ff, rho, E, B)
+    assert res["residual"] < 1e-6 and not res["non_finite"]
+    assert abs(res["max_row_sum"] - np.max(np.add.reduceat(v.astype(np.float64), rp[:-1])[np.diff(rp) > 0])) < 1e-6
+    E2 = E.clone()
+    E2[3, 0, 0, 1] = float("nan")
+    assert g.check(ff, rho, E2, B)["non_finite"]
+
+
+# ---------------------------------------------------------------------------
+# opacity gradient
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,kw,R,topk", [("fruit_bowl", dict(n=2500), 16, 0), ("fruit_bowl", dict(n=2500), 16, 24),
+                                            ("box_room", dict(n=1500), 16, 0)])
+def test_opacity_backward_matches_oracle(g, orc, name, kw, R, topk):
+    sc = _scene(name, **kw)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    ff = g.form_factors(bvh, R, sc.seed, t_min=1e-4, topk=topk)
+    Fg = gpu_csr(ff)
+    rng = np.random.default_rng(3)
+    gF = rng.standard_normal(Fg.nnz).astype(np.float32)
+    grho = rng.standard_normal((sc.n, 3)).astype(np.float32)
+    go, ga = g.opacity_backward(bvh, ff, dev(gF), dev(grho), dev(sc.albedo))
+    te = orc.default_t_eps(sc.surfels)
+    # the oracle gets the same dL/dF on its own F's pattern (entries present
+    # in both); the tiny cut-boundary entries carry no gradient
+    Fo, _ = orc.ff_matrix(sc.surfels, R, sc.seed, te, 1e-4, topk)
+    W = sp.csr_matrix((gF.astype(np.float64), Fg.indices, Fg.indptr), shape=Fg.shape)
+    Wo = W.multiply(Fo != 0).tocsr()
+    Wo.sort_indices()
+    goo, gao = orc.opacity_backward(sc.surfels, sc.albedo, R, sc.seed, te, 1e-4,
+                                    (Wo.indptr, Wo.indices, Wo.data), grad_rho=grho)
+    assert rel_err(go.cpu().numpy(), goo) < 5 * TOL
+    assert rel_err(ga.cpu().numpy(), gao) < TOL
+
+
+def test_autograd_function_chain(g, orc):
+    sc = _scene("fruit_bowl", n=2000)
+    R, nb = 16, 4
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    ff = g.form_factors(bvh, R, sc.seed, t_min=1e-4)
+    K = 4
+    E = dev(scenes.seeded_array((sc.n, 1, K, 3), seed=4)).requires_grad_(True)
+    op = dev(sc.surfels["opacity"]).requires_grad_(True)
+    alb = dev(sc.albedo).requires_grad_(True)
+    B = g.RadiosityFn.apply(op, alb, E, bvh, ff, nb)
+    target = dev(scenes.seeded_array((sc.n, 1, K, 3), seed=5))
+    loss = ((B - target) ** 2).mean()
+    loss.backward()
+    # oracle chain on the GPU's F pattern values from the oracle itself
+    te = orc.default_t_eps(sc.surfels)
+    Fo, _ = orc.ff_matrix(sc.surfels, R, sc.seed, te, 1e-4, 0)
+    rho = orc.rho(sc.surfels["opacity"], sc.albedo)
+    Eo = E.detach().cpu().numpy().astype(np.float64)
+    Bo, tp = orc.bounce(Fo, rho, Eo, nb, keep_tape=True)
+    gB = 2 * (Bo - target.cpu().numpy()) / Bo.size
+    gEo, gro, gFo = orc.adjoint(Fo, rho, tp, gB)
+    goo, gao = orc.opacity_backward(sc.surfels, sc.albedo, R, sc.seed, te, 1e-4,
+                                    (Fo.indptr, Fo.indices, gFo), grad_rho=gro)
+    assert rel_err(B.detach().cpu().numpy(), Bo) < TOL
+    assert rel_err(E.grad.cpu().numpy(), gEo) < TOL
+    assert rel_err(alb.grad.cpu().numpy(), gao) < TOL
+    assert rel_err(op.grad.cpu().numpy(), goo) < 5 * TOL
+
+
+# ---------------------------------------------------------------------------
+# errors
+# ---------------------------------------------------------------------------
+def test_errors_surface_as_status(g):
+    sc = _scene("furnace")
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    with pytest.raises(g.GsradError) as ei:
+        g.form_factors(bvh, 0, 1)
+    assert ei.value.status == g.gsrad.EINVAL
+    ff = g.form_factors(bvh, 16, 1)
+    E = dev(scenes.seeded_array((sc.n, 1, 3, 3), seed=2))
+    with pytest.raises(g.GsradError):
+        g.transport_solve(ff, dev(sc.albedo), E, 2)   # K = 3 is not a valid SH size
