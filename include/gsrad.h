@@ -78,13 +78,19 @@ typedef struct gsrad_surfels {
  *                    1e-5 * diagonal of the bounding box of the centres.
  *   topk             keep the topk largest entries per row (value desc,
  *                    index asc), 0 = keep all.
+ *   flags            GSRAD_FF_NO_RECORDS: do not keep the per-ray hit
+ *                    records (the opacity backward then recomputes every
+ *                    ray by traversal instead of reading them).
  */
+#define GSRAD_FF_NO_RECORDS 1
 typedef struct gsrad_ff_params {
     int32_t rays_per_surfel;
     int32_t topk;
     uint64_t seed;
     float t_min;
     float t_eps;
+    int32_t flags;
+    int32_t reserved;
 } gsrad_ff_params;
 
 typedef struct gsrad_bvh gsrad_bvh;   /* prepared surfels + LBVH            */
@@ -217,6 +223,9 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
  *                 gamma_q = exp(-1.7 (u_q^2 + v_q^2))
  * plus the receiver term dL/do_i += sum_c grad_rho_ic a_ic, and
  * dL/da = grad_rho * o (both zero where the opacity clamp is active).
+ * The hits are read from the records gsrad_form_factors kept (up to 128
+ * composited hits per ray, if all records fit in 40 GB); rays without
+ * complete records are recomputed by traversal, with identical results.
  * grad_F is [nnz] in F's CSR order; grad_rho and albedo [n][3];
  * grad_opacity [n], grad_albedo [n][3] (either may be NULL).  The hit
  * recomputation needs the ff handle made from this bvh.
@@ -252,8 +261,8 @@ gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, c
 /*
  * Timing of the library's phases with HIP events recorded on the caller's
  * stream around each kernel group (bvh_build, ff_trace, ff_aggregate,
- * ff_csr, direct_light, bounce, transpose, adjoint, sddmm, opacity_pass1,
- * opacity_pass2, opacity_finish).  gsrad_profile_enable(1) clears the record
+ * ff_csr, direct_light, bounce, transpose, adjoint, sddmm, opacity_records,
+ * opacity_pass1, opacity_pass2, opacity_finish).  gsrad_profile_enable(1) clears the record
  * and starts recording, 0 stops.  gsrad_profile_report waits for the events
  * and writes one line per phase into buf (host, len bytes):
  * "name<TAB>count<TAB>total_ms<TAB>min_ms<TAB>max_ms\n".  Not thread safe.

@@ -70,6 +70,8 @@ struct DevBuf {
 constexpr size_t kSlabBudget = size_t(6) << 30;
 constexpr int kHitsPerRay = 64;     // slab capacity per ray (average ~25 here)
 constexpr int kLog2Table = 12;      // 4096-entry aggregation table per receiver
+constexpr int kRecCap = 128;        // recorded hits per ray (composited: ~27 mean, ~100 max here)
+constexpr size_t kRecordBudget = size_t(40) << 30;   // records kept for the backward
 
 // ---------------------------------------------------------------------------
 // optional per-phase timing with HIP events on the caller's stream
@@ -162,6 +164,9 @@ struct gsrad_ff {
     int R = 0, topk = 0;
     uint64_t seed = 0;
     float t_eps = 0.0f, t_min = 0.0f;
+    // recorded hits (j, +-gamma) per ray for the backward, if they fit
+    bool has_records = false, rec_overflow = false;
+    DevBuf recs, rcnt;
     // scratch of the ray-cast path
     DevBuf slab, slab_cnt, ell_col, ell_val, row_len, err, scan_temp;
     Csr csr() const {
@@ -184,7 +189,7 @@ struct gsrad_ff {
     }
     ~gsrad_ff() {
         for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &slab_cnt, &ell_col,
-                          &ell_val, &row_len, &err, &scan_temp})
+                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt})
             b->release();
     }
 };
@@ -357,8 +362,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     hipStream_t st = S(stream);
     const int64_t n = bvh->n;
     const int R = p->rays_per_surfel;
-    const int64_t cap = (int64_t)kHitsPerRay * R;
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(kSlabBudget / ((size_t)cap * 8))));
+    int64_t cap = (int64_t)kHitsPerRay * R;
     const int64_t cap_row = p->topk > 0 ? p->topk : (1 << kLog2Table);
     gsrad_status e;
     float t_eps = p->t_eps;
@@ -369,48 +373,67 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
             return fail(e);
         t_eps = b[6];
     }
-#define ENS(buf, bytes, what) \
-    if ((e = h->buf.ensure((size_t)(bytes), what)) != GSRAD_OK) return fail(e);
-    ENS(slab, chunk * cap * 8, "hit slab");
-    ENS(slab_cnt, chunk * 4, "slab counts");
-    ENS(ell_col, n * cap_row * 4, "row staging");
-    ENS(ell_val, n * cap_row * 4, "row staging");
-    ENS(row_len, n * 4, "row lengths");
-    ENS(err, 128, "error flags");
-    ENS(row_ptr, (n + 1) * 8, "row_ptr");
-    ENS(scan_temp, scan_temp_bytes(n), "scan temp");
-#undef ENS
-    int *err = h->err.as<int>();
-    if ((e = check_hip(hipMemsetAsync(err, 0, 64, st), "ff flags")) != GSRAD_OK) return fail(e);
-    const BvhDev bv = bvh->dev();
-    for (int64_t s0 = 0; s0 < n; s0 += chunk) {
-        const int64_t cnt = std::min(chunk, n - s0);
-        {
-            ProfScope ps("ff_trace", st);
-            if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, h->slab.as<uint2>(), cap,
-                                     h->slab_cnt.as<uint32_t>(), err, st)) != GSRAD_OK)
-                return fail(e);
-        }
-        hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->slab_cnt.as<uint32_t>(), cnt, err + 2);
-        ProfScope ps("ff_aggregate", st);
-        if ((e = launch_ff_aggregate(bv, h->slab.as<uint2>(), h->slab_cnt.as<uint32_t>(), cap, s0, cnt, R, p->topk,
-                                     kLog2Table, cap_row, h->ell_col.as<int32_t>(), h->ell_val.as<float>(),
-                                     h->row_len.as<uint32_t>(), err, st)) != GSRAD_OK)
-            return fail(e);
-    }
-    hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->row_len.as<uint32_t>(), n, err + 1);
-    if ((e = exclusive_scan_u32_i64(h->row_len.as<uint32_t>(), h->row_ptr.as<int64_t>(), n, h->scan_temp.p,
-                                    h->scan_temp.bytes, st)) != GSRAD_OK)
-        return fail(e);
+    const size_t rec_bytes = (size_t)n * R * kRecCap * sizeof(uint2);
+    const bool records = rec_bytes <= kRecordBudget && !(p->flags & GSRAD_FF_NO_RECORDS);
     int flags[4];
     int64_t nnz = 0;
-    if ((e = check_hip(hipMemcpyAsync(flags, err, sizeof(flags), hipMemcpyDeviceToHost, st), "ff flags copy")) !=
-        GSRAD_OK)
-        return fail(e);
-    if ((e = check_hip(hipMemcpyAsync(&nnz, h->row_ptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st),
-                       "ff nnz copy")) != GSRAD_OK)
-        return fail(e);
-    if ((e = check_hip(hipStreamSynchronize(st), "ff sync")) != GSRAD_OK) return fail(e);
+    for (int attempt = 0;; ++attempt) {
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(kSlabBudget / ((size_t)cap * 8))));
+#define ENS(buf, bytes, what) \
+    if ((e = h->buf.ensure((size_t)(bytes), what)) != GSRAD_OK) return fail(e);
+        ENS(slab, chunk * cap * 8, "hit slab");
+        ENS(slab_cnt, chunk * 4, "slab counts");
+        ENS(ell_col, n * cap_row * 4, "row staging");
+        ENS(ell_val, n * cap_row * 4, "row staging");
+        ENS(row_len, n * 4, "row lengths");
+        ENS(err, 128, "error flags");
+        ENS(row_ptr, (n + 1) * 8, "row_ptr");
+        ENS(scan_temp, scan_temp_bytes(n), "scan temp");
+        if (records) {
+            ENS(recs, rec_bytes, "hit records");
+            ENS(rcnt, (size_t)n * R * 4, "hit record counts");
+        }
+#undef ENS
+        int *err = h->err.as<int>();
+        if ((e = check_hip(hipMemsetAsync(err, 0, 64, st), "ff flags")) != GSRAD_OK) return fail(e);
+        const BvhDev bv = bvh->dev();
+        for (int64_t s0 = 0; s0 < n; s0 += chunk) {
+            const int64_t cnt = std::min(chunk, n - s0);
+            {
+                ProfScope ps("ff_trace", st);
+                if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, h->slab.as<uint2>(), cap,
+                                         h->slab_cnt.as<uint32_t>(), records ? h->recs.as<uint2>() : nullptr,
+                                         records ? h->rcnt.as<uint32_t>() : nullptr, kRecCap, err, st)) != GSRAD_OK)
+                    return fail(e);
+            }
+            hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->slab_cnt.as<uint32_t>(), cnt, err + 2);
+            ProfScope ps("ff_aggregate", st);
+            if ((e = launch_ff_aggregate(bv, h->slab.as<uint2>(), h->slab_cnt.as<uint32_t>(), cap, s0, cnt, R,
+                                         p->topk, kLog2Table, cap_row, h->ell_col.as<int32_t>(), h->ell_val.as<float>(),
+                                         h->row_len.as<uint32_t>(), err, st)) != GSRAD_OK)
+                return fail(e);
+        }
+        hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->row_len.as<uint32_t>(), n, err + 1);
+        if ((e = exclusive_scan_u32_i64(h->row_len.as<uint32_t>(), h->row_ptr.as<int64_t>(), n, h->scan_temp.p,
+                                        h->scan_temp.bytes, st)) != GSRAD_OK)
+            return fail(e);
+        if ((e = check_hip(hipMemcpyAsync(flags, err, sizeof(flags), hipMemcpyDeviceToHost, st), "ff flags copy")) !=
+            GSRAD_OK)
+            return fail(e);
+        if ((e = check_hip(hipMemcpyAsync(&nnz, h->row_ptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st),
+                           "ff nnz copy")) != GSRAD_OK)
+            return fail(e);
+        if ((e = check_hip(hipStreamSynchronize(st), "ff sync")) != GSRAD_OK) return fail(e);
+        // a receiver produced more front hits than its slab holds: grow the
+        // slab to the measured maximum and run again
+        if ((flags[0] & kErrSlab) && attempt < 2) {
+            cap = std::max<int64_t>(2 * cap, ((int64_t)flags[2] + 1023) / 1024 * 1024);
+            continue;
+        }
+        break;
+    }
+    const bool rec_overflow = (flags[0] & kErrRecords) != 0;
+    flags[0] &= ~kErrRecords;
     if (flags[0] != 0) {
         set_error("gsrad_form_factors: overflow flags 0x%x (1 stack, 2 hit slab [max %d of %lld], 4 table, 8 row)",
                   flags[0], flags[2], (long long)cap);
@@ -433,6 +456,8 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     h->seed = p->seed;
     h->t_eps = t_eps;
     h->t_min = p->t_min;
+    h->has_records = records;
+    h->rec_overflow = records && rec_overflow;
     *ff = h;
     return GSRAD_OK;
 }
@@ -636,13 +661,23 @@ gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, co
     if (grad_F && f->nnz > 0) {
         if ((size_t)f->max_row * 8 + ff_stack_bytes(256) > 150 * 1024)
             return einval("gsrad_opacity_backward: row too long for the LDS row cache");
-        GS_TRY(f->slab.ensure(std::max(f->slab.bytes, (size_t)n * f->R * 4), "ray sums"));
-        GS_TRY(f->err.ensure(128, "flags"));
-        for (int pass = 0; pass < 2; ++pass) {
-            ProfScope ps(pass == 0 ? "opacity_pass1" : "opacity_pass2", st);
-            GS_TRY(launch_opacity_bwd(bvh->dev(), f->R, f->seed, f->t_eps, f->t_min, f->row_ptr.as<int64_t>(),
-                                      f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1), f->slab.as<float>(), gacc,
-                                      pass, f->err.as<int>() + 8, st));
+        if (f->has_records) {
+            ProfScope ps("opacity_records", st);
+            GS_TRY(launch_opacity_rec(bvh->dev(), f->R, f->recs.as<uint2>(), f->rcnt.as<uint32_t>(), kRecCap,
+                                      f->row_ptr.as<int64_t>(), f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1),
+                                      gacc, st));
+        }
+        if (!f->has_records || f->rec_overflow) {
+            // recompute the rays without (complete) records by traversal
+            GS_TRY(f->slab.ensure(std::max(f->slab.bytes, (size_t)n * f->R * 4), "ray sums"));
+            GS_TRY(f->err.ensure(128, "flags"));
+            for (int pass = 0; pass < 2; ++pass) {
+                ProfScope ps(pass == 0 ? "opacity_pass1" : "opacity_pass2", st);
+                GS_TRY(launch_opacity_bwd(bvh->dev(), f->R, f->seed, f->t_eps, f->t_min, f->row_ptr.as<int64_t>(),
+                                          f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1), f->slab.as<float>(),
+                                          gacc, pass, f->has_records ? f->rcnt.as<uint32_t>() : nullptr, kRecCap,
+                                          f->err.as<int>() + 8, st));
+            }
         }
     }
     ProfScope ps("opacity_finish", st);

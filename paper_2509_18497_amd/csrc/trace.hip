@@ -204,9 +204,15 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
 // ---------------------------------------------------------------------------
 // form factors
 // ---------------------------------------------------------------------------
+// Records (when recs != nullptr): every composited hit of ray r of receiver
+// i as (j, +-gamma) with the sign = front face, at recs[(i*rcap + q)*R + r]
+// (hit-major inside a receiver, so a wave reads one record per lane with
+// one coalesced access); rcnt[i*R + r] = number of composited hits (a count
+// above rcap means the ray's records are incomplete).
 __global__ void __launch_bounds__(256) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
                                                   int64_t s_begin, int64_t nblocks, uint2 *__restrict__ slab,
-                                                  int64_t cap, uint32_t *__restrict__ slab_cnt, int *err) {
+                                                  int64_t cap, uint32_t *__restrict__ slab_cnt, uint2 *__restrict__ recs,
+                                                  uint32_t *__restrict__ rcnt, int rcap, int *err) {
     extern __shared__ uint32_t stack_mem[];
     __shared__ uint32_t cnt;
     const int64_t b = xcd_block(blockIdx.x, nblocks);
@@ -220,12 +226,21 @@ __global__ void __launch_bounds__(256) k_ff_trace(BvhDev bv, int R, uint64_t see
         float dx, dy, dz;
         ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
                       (uint64_t)i, seed, 0, dx, dy, dz);
+        uint32_t q = 0;
+        uint2 *rec_out = recs ? recs + (int64_t)i * rcap * R + r : nullptr;
         trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x, err,
-                          [&](uint32_t j, float alpha, float T, bool front, float, float) {
+                          [&](uint32_t j, float alpha, float T, bool front, float g, float) {
+                              if (rec_out && q < (uint32_t)rcap)
+                                  rec_out[(int64_t)q * R] = make_uint2(j, __float_as_uint(front ? g : -g));
+                              ++q;
                               if (!front) return;
                               const uint32_t pos = atomicAdd(&cnt, 1u);
                               if (pos < cap) out[pos] = make_uint2(j, __float_as_uint(alpha * T));
                           });
+        if (rcnt) {
+            rcnt[(int64_t)i * R + r] = q;
+            if (q > (uint32_t)rcap) atomicOr(err, kErrRecords);
+        }
     }
     __syncthreads();
     if (tid == 0) slab_cnt[b] = cnt;
@@ -274,8 +289,14 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
     }
     if (tid == 0) m_sh = 0;
     __syncthreads();
+    // Each thread walks a contiguous chunk of the slab: the slab was filled
+    // by the lanes of a wave in lock-step, so neighbouring entries are
+    // mostly the same few surfels; striding them over the lanes of one
+    // insert batch would serialise the LDS atomics on one address.
     const uint2 *in = slab + b * cap;
-    for (uint32_t e = tid; e < count; e += 256) {
+    const uint32_t per = (count + 255u) / 256u;
+    const uint32_t e0 = tid * per, e1 = min(count, e0 + per);
+    for (uint32_t e = e0; e < e1; ++e) {
         const uint2 c = in[e];
         const unsigned long long fx = (unsigned long long)__float2ull_rn(__uint_as_float(c.y) * kFixScaleF);
         uint32_t h = hash_slot(c.x, log2h);
@@ -293,8 +314,13 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
     __syncthreads();
     const double scale = 1.0 / (kFixScale * (double)R);
     for (int k = tid; k < H; k += 256) {
-        if (hkey[k] != kEmpty) {
-            const uint32_t p = atomicAdd(&m_sh, 1u);
+        const bool full = hkey[k] != kEmpty;
+        const uint64_t bal = __ballot(full);
+        uint32_t base = 0;
+        if (__lane_id() == 0 && bal) base = atomicAdd(&m_sh, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (full) {
+            const uint32_t p = base + (uint32_t)__popcll(bal & ((1ull << __lane_id()) - 1ull));
             cj[p] = hkey[k];
             cv[p] = (float)((double)hval[k] * scale);
         }
@@ -341,9 +367,15 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
         if (tid == 0) m_sh = 0;
         __syncthreads();
         float *hv = reinterpret_cast<float *>(hval);
-        for (uint32_t e = tid; e < m; e += 256) {
-            if (badness(cj[e], cv[e]) <= prefix) {
-                const uint32_t p = atomicAdd(&m_sh, 1u);
+        for (uint32_t e0 = 0; e0 < m; e0 += 256) {
+            const uint32_t e = e0 + tid;
+            const bool keep = e < m && badness(cj[e], cv[e]) <= prefix;
+            const uint64_t bal = __ballot(keep);
+            uint32_t base = 0;
+            if (__lane_id() == 0 && bal) base = atomicAdd(&m_sh, (uint32_t)__popcll(bal));
+            base = __shfl(base, 0, 64);
+            if (keep) {
+                const uint32_t p = base + (uint32_t)__popcll(bal & ((1ull << __lane_id()) - 1ull));
                 hkey[p] = cj[e];
                 hv[p] = cv[e];
             }
@@ -452,7 +484,7 @@ __global__ void __launch_bounds__(256) k_opacity_bwd(BvhDev bv, int R, uint64_t 
                                                      int64_t nblocks, const int64_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, const float *__restrict__ gF,
                                                      int max_row, float *__restrict__ wbuf, double *gacc, int pass,
-                                                     int *err) {
+                                                     const uint32_t *__restrict__ rcnt, int rcap, int *err) {
     extern __shared__ uint32_t sm2[];
     uint32_t *lc = sm2;                                   // [max_row]
     float *lg = reinterpret_cast<float *>(lc + max_row);  // [max_row]
@@ -470,6 +502,8 @@ __global__ void __launch_bounds__(256) k_opacity_bwd(BvhDev bv, int R, uint64_t 
     }
     __syncthreads();
     for (int r = tid; r < R; r += blockDim.x) {
+        // with records, only rays whose records overflowed are recomputed here
+        if (rcnt && rcnt[(int64_t)i * R + r] <= (uint32_t)rcap) continue;
         float dx, dy, dz;
         ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
                       (uint64_t)i, seed, 0, dx, dy, dz);
@@ -493,9 +527,83 @@ __global__ void __launch_bounds__(256) k_opacity_bwd(BvhDev bv, int R, uint64_t 
                                   if (oraw > 0.0f && oraw < kOpacityMax) {
                                       const float dLda = G * T - S / (1.0f - alpha);
                                       const float dado = g * expf(bv.c[j] * (1.0f - g));
-                                      atomicAdd(&gacc[j], (double)(dLda * dado));
+                                      unsafeAtomicAdd(&gacc[j], (double)(dLda * dado));
                                   }
                               });
+        }
+    }
+}
+
+// Compositing backward from the recorded hits: the same FP32 alpha and T
+// sequence as the forward trace, G from an LDS hash of row i of dL/dF.
+__device__ __forceinline__ float row_hash_lookup(const uint32_t *hk, const float *hv, int log2h, uint32_t j) {
+    const uint32_t mask = (1u << log2h) - 1u;
+    uint32_t h = hash_slot(j, log2h);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const uint32_t k = hk[h];
+        if (k == j) return hv[h];
+        if (k == kEmpty) return 0.0f;
+        h = (h + 1) & mask;
+    }
+    return 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uint2 *__restrict__ recs,
+                                                     const uint32_t *__restrict__ rcnt, int rcap, int64_t nblocks,
+                                                     const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, const float *__restrict__ gF,
+                                                     int log2h, double *gacc) {
+    extern __shared__ uint32_t sm3[];
+    const int H = 1 << log2h;
+    uint32_t *hk = sm3;
+    float *hv = reinterpret_cast<float *>(sm3 + H);
+    const int64_t b = xcd_block(blockIdx.x, nblocks);
+    const int tid = threadIdx.x;
+    const uint32_t i = __float_as_uint(bv.rec[b].d.w);
+    for (int k = tid; k < H; k += blockDim.x) hk[k] = kEmpty;
+    __syncthreads();
+    const int64_t e0 = row_ptr[i];
+    const int len = (int)(row_ptr[i + 1] - e0);
+    const float invR = 1.0f / (float)R;
+    for (int k = tid; k < len; k += blockDim.x) {
+        const uint32_t j = (uint32_t)col[e0 + k];
+        uint32_t h = hash_slot(j, log2h);
+        while (atomicCAS(&hk[h], kEmpty, j) != kEmpty) h = (h + 1) & (uint32_t)(H - 1);
+        hv[h] = gF[e0 + k] * invR;
+    }
+    __syncthreads();
+    for (int r = tid; r < R; r += blockDim.x) {
+        const uint32_t m = rcnt[(int64_t)i * R + r];
+        if (m > (uint32_t)rcap) continue;
+        const uint2 *in = recs + (int64_t)i * rcap * R + r;
+        float W = 0.0f, T = 1.0f;
+        for (uint32_t q = 0; q < m; ++q) {
+            const uint2 h = in[(int64_t)q * R];
+            const float gs = __uint_as_float(h.y);
+            const float x = bv.c[h.x] * fabsf(gs);
+            if (gs > 0.0f) W += row_hash_lookup(hk, hv, log2h, h.x) * (-expm1f(-x)) * T;
+            T *= expf(-x);
+        }
+        float P = 0.0f;
+        T = 1.0f;
+        for (uint32_t q = 0; q < m; ++q) {
+            const uint2 h = in[(int64_t)q * R];
+            const float gs = __uint_as_float(h.y);
+            const float g = fabsf(gs);
+            const float c = bv.c[h.x];
+            const float x = c * g;
+            const float alpha = -expm1f(-x);
+            const float G = gs > 0.0f ? row_hash_lookup(hk, hv, log2h, h.x) : 0.0f;
+            const float gw = G * alpha * T;
+            const float S = W - P - gw;
+            P += gw;
+            const float oraw = bv.raw_op[h.x];
+            if (oraw > 0.0f && oraw < kOpacityMax) {
+                const float dLda = G * T - S / (1.0f - alpha);
+                const float dado = g * expf(c * (1.0f - g));
+                unsafeAtomicAdd(&gacc[h.x], (double)(dLda * dado));
+            }
+            T *= expf(-x);
         }
     }
 }
@@ -569,10 +677,11 @@ __global__ void __launch_bounds__(256) k_reflectance(BvhDev bv, const float *__r
 size_t ff_stack_bytes(int threads) { return (size_t)kStack * threads * sizeof(uint32_t); }
 
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, int *err, hipStream_t st) {
+                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, uint2 *recs, uint32_t *rcnt,
+                             int rcap, int *err, hipStream_t st) {
     const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
     hipLaunchKernelGGL(k_ff_trace, dim3((unsigned)count), dim3(threads), ff_stack_bytes(threads), st, bv, R, seed,
-                       t_eps, t_min, s_begin, count, slab, cap, slab_cnt, err);
+                       t_eps, t_min, s_begin, count, slab, cap, slab_cnt, recs, rcnt, rcap, err);
     return check_hip(hipGetLastError(), "ff trace launch");
 }
 
@@ -610,7 +719,7 @@ gsrad_status launch_direct(const BvhDev &bv, const float *albedo, const float *l
 
 gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min,
                                 const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float *wbuf,
-                                double *gacc, int pass, int *err, hipStream_t st) {
+                                double *gacc, int pass, const uint32_t *rcnt, int rcap, int *err, hipStream_t st) {
     const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
     const size_t smem = (size_t)max_row * 8 + ff_stack_bytes(threads);
     static bool attr_set = false;
@@ -620,8 +729,30 @@ gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_
         attr_set = true;
     }
     hipLaunchKernelGGL(k_opacity_bwd, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, seed, t_eps, t_min, bv.n,
-                       row_ptr, col, gF, max_row, wbuf, gacc, pass, err);
+                       row_ptr, col, gF, max_row, wbuf, gacc, pass, rcnt, rcap, err);
     return check_hip(hipGetLastError(), "opacity backward launch");
+}
+
+gsrad_status launch_opacity_rec(const BvhDev &bv, int R, const uint2 *recs, const uint32_t *rcnt, int rcap,
+                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row,
+                                double *gacc, hipStream_t st) {
+    const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
+    int log2h = 4;
+    while ((1 << log2h) < 2 * max_row) ++log2h;
+    const size_t smem = (size_t)(1 << log2h) * 8;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_opacity_rec), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024 - 4096);
+        attr_set = true;
+    }
+    if (smem > 150 * 1024) {
+        set_error("opacity backward: row of %d entries is too long for the LDS row table", max_row);
+        return GSRAD_EINVAL;
+    }
+    hipLaunchKernelGGL(k_opacity_rec, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, recs, rcnt, rcap, bv.n,
+                       row_ptr, col, gF, log2h, gacc);
+    return check_hip(hipGetLastError(), "opacity records launch");
 }
 
 gsrad_status launch_opacity_finish(const BvhDev &bv, const double *gacc, const float *grad_rho, const float *albedo,

@@ -11,11 +11,13 @@ constexpr int kErrStack = 1;   // traversal stack overflow
 constexpr int kErrSlab = 2;    // a receiver produced more hits than its slab holds
 constexpr int kErrTable = 4;   // more distinct senders than the aggregation table holds
 constexpr int kErrRow = 8;     // row longer than the ELL capacity
+constexpr int kErrRecords = 16; // a ray composited more hits than its record slots (recomputed later)
 
 size_t ff_stack_bytes(int threads);
 size_t ff_aggregate_smem(int log2h);
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, int *err, hipStream_t st);
+                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, uint2 *recs, uint32_t *rcnt,
+                             int rcap, int *err, hipStream_t st);
 gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *slab, const uint32_t *slab_cnt, int64_t cap,
                                  int64_t s_begin, int64_t count, int R, int topk, int log2h, int64_t cap_row,
                                  int32_t *ell_col, float *ell_val, uint32_t *row_len, int *err, hipStream_t st);
@@ -25,7 +27,10 @@ gsrad_status launch_direct(const BvhDev &bv, const float *albedo, const float *l
                            float *E, int *err, hipStream_t st);
 gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min,
                                 const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float *wbuf,
-                                double *gacc, int pass, int *err, hipStream_t st);
+                                double *gacc, int pass, const uint32_t *rcnt, int rcap, int *err, hipStream_t st);
+gsrad_status launch_opacity_rec(const BvhDev &bv, int R, const uint2 *recs, const uint32_t *rcnt, int rcap,
+                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row,
+                                double *gacc, hipStream_t st);
 gsrad_status launch_opacity_finish(const BvhDev &bv, const double *gacc, const float *grad_rho, const float *albedo,
                                    float *grad_o, float *grad_a, hipStream_t st);
 gsrad_status launch_ray_hits(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, const int64_t *recv,

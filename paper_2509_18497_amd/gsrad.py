@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libgsrad.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENAN, EOVERFLOW, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP32 = 0
+FF_NO_RECORDS = 1
 SOA = ("px", "py", "pz", "tux", "tuy", "tuz", "tvx", "tvy", "tvz", "nx", "ny", "nz", "su", "sv", "opacity")
 
 EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_info", "gsrad_bvh_height",
@@ -39,7 +40,8 @@ class _Surfels(ctypes.Structure):
 
 class _FFParams(ctypes.Structure):
     _fields_ = [("rays_per_surfel", ctypes.c_int32), ("topk", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("t_min", ctypes.c_float), ("t_eps", ctypes.c_float)]
+                ("t_min", ctypes.c_float), ("t_eps", ctypes.c_float), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -195,8 +197,9 @@ def reflectance(bvh: BVH, albedo: torch.Tensor, stream=None) -> torch.Tensor:
 
 
 def form_factors(bvh: BVH, rays_per_surfel: int, seed: int, t_min: float = 1e-4, t_eps: float = 0.0,
-                 topk: int = 0, ff: Optional[FF] = None, stream=None) -> FF:
-    p = _FFParams(int(rays_per_surfel), int(topk), int(seed) & 0xFFFFFFFFFFFFFFFF, float(t_min), float(t_eps))
+                 topk: int = 0, ff: Optional[FF] = None, records: bool = True, stream=None) -> FF:
+    p = _FFParams(int(rays_per_surfel), int(topk), int(seed) & 0xFFFFFFFFFFFFFFFF, float(t_min), float(t_eps),
+                  0 if records else FF_NO_RECORDS, 0)
     out = ff if ff is not None else FF()
     _check(lib().gsrad_form_factors(bvh.h, ctypes.byref(p), ctypes.byref(out.h), _stream(stream)),
            "gsrad_form_factors")
@@ -269,7 +272,7 @@ def ray_hits(bvh: BVH, receivers: torch.Tensor, rays_per_surfel: int, seed: int,
              t_eps: float = 0.0, max_hits: int = 256, stream=None) -> dict:
     """Directions and composited hit lists of every ray of the listed
     receivers (same decisions as form_factors)."""
-    p = _FFParams(int(rays_per_surfel), 0, int(seed) & 0xFFFFFFFFFFFFFFFF, float(t_min), float(t_eps))
+    p = _FFParams(int(rays_per_surfel), 0, int(seed) & 0xFFFFFFFFFFFFFFFF, float(t_min), float(t_eps), 0, 0)
     m = int(receivers.shape[0])
     R = int(rays_per_surfel)
     dev = torch.device("cuda")

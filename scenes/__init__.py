@@ -362,6 +362,31 @@ def random_frame_surfels(n: int, seed: int, extent: float = 1.0, scale=(0.05, 0.
     return sur
 
 
+def layer_stack(n_layers: int = 160, per_layer: int = 3, spacing: float = 0.01, scale: float = 0.2,
+                opacity: float = 0.02, seed: int = 0) -> Dict[str, np.ndarray]:
+    """Receivers on the plane z = 0 below a stack of nearly transparent,
+    slightly jittered horizontal layers: upward rays composite well over a
+    hundred hits each (transmittance never reaches the cut-off)."""
+    rng = np.random.default_rng(seed)
+    m = n_layers * per_layer
+    p = np.zeros((m + 4, 3))
+    p[:4, :2] = rng.uniform(-0.05, 0.05, (4, 2))
+    k = np.arange(m)
+    p[4:, 0] = rng.uniform(-0.05, 0.05, m)
+    p[4:, 1] = rng.uniform(-0.05, 0.05, m)
+    p[4:, 2] = spacing * (1 + k // per_layer) + rng.uniform(0, 0.2 * spacing, m)
+    nrm = np.tile([0.0, 0.0, 1.0], (m + 4, 1))
+    nrm[4:] = -nrm[4:]
+    nrm[4:, :2] += rng.uniform(-0.05, 0.05, (m, 2))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    tu, tv = onb_from_normal(nrm)
+    su = np.full(m + 4, scale)
+    op = np.full(m + 4, opacity)
+    op[:4] = 0.9
+    sur, _ = _pack(p, nrm, tu, tv, su, su, op, np.zeros((m + 4, 3)))
+    return sur
+
+
 def surfels_from_arrays(p, nrm, tu, tv, su, sv, op) -> Dict[str, np.ndarray]:
     """Pack explicit geometry (used by analytic two-surfel set-ups)."""
     sur, _ = _pack(np.asarray(p, float), np.asarray(nrm, float), np.asarray(tu, float),

@@ -293,3 +293,29 @@ def test_errors_surface_as_status(g):
     E = dev(scenes.seeded_array((sc.n, 1, 3, 3), seed=2))
     with pytest.raises(g.GsradError):
         g.transport_solve(ff, dev(sc.albedo), E, 2)   # K = 3 is not a valid SH size
+
+
+# ---------------------------------------------------------------------------
+# dense stacks: rays with hundreds of composited hits (slab growth, record
+# overflow and the traversal fallback of the backward)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("records", [True, False])
+def test_layer_stack_forward_and_opacity_backward(g, orc, records):
+    sur = scenes.layer_stack()
+    n = sur["px"].shape[0]
+    R, seed = 24, 5
+    bvh = g.build_bvh(dev_surfels(sur))
+    ff = g.form_factors(bvh, R, seed, t_min=1e-4, records=records)
+    Fg = gpu_csr(ff)
+    te = orc.default_t_eps(sur)
+    Fo, _ = orc.ff_matrix(sur, R, seed, te, 1e-4, 0)
+    assert rel_err(Fg.toarray(), Fo.toarray()) < TOL
+    rng = np.random.default_rng(1)
+    gF = rng.standard_normal(Fg.nnz).astype(np.float32)
+    alb = np.full((n, 3), 0.5, np.float32)
+    grho = rng.standard_normal((n, 3)).astype(np.float32)
+    go, ga = g.opacity_backward(bvh, ff, dev(gF), dev(grho), dev(alb))
+    W = sp.csr_matrix((gF.astype(np.float64), Fg.indices, Fg.indptr), shape=Fg.shape).multiply(Fo != 0).tocsr()
+    W.sort_indices()
+    goo, _ = orc.opacity_backward(sur, alb, R, seed, te, 1e-4, (W.indptr, W.indices, W.data), grad_rho=grho)
+    assert rel_err(go.cpu().numpy(), goo) < 5 * TOL
