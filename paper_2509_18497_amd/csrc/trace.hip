@@ -246,7 +246,20 @@ __global__ void __launch_bounds__(256) k_ff_trace(BvhDev bv, int R, uint64_t see
     if (tid == 0) slab_cnt[b] = cnt;
 }
 
-__device__ __forceinline__ uint32_t hash_slot(uint32_t j, int log2h) { return (j * 0x9E3779B1u) >> (32 - log2h); }
+// Slot of surfel j in an open-addressing table of 2^log2h entries.  A full
+// avalanche mixer (the 32-bit finaliser of "lowbias32"), not a single
+// golden-ratio multiply: surfels laid out on Fibonacci lattices have index
+// differences that are Fibonacci numbers, which golden-ratio hashing sends
+// to nearly the same slot.
+__device__ __forceinline__ uint32_t hash_slot(uint32_t j, int log2h) {
+    uint32_t h = j;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h >> (32 - log2h);
+}
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
     const int lane = __lane_id();
