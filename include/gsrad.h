@@ -145,8 +145,10 @@ gsrad_status gsrad_reflectance(const gsrad_bvh *bvh, const float *albedo, float 
  * with columns ascending in each row, values FP32, deterministic (bit
  * identical between runs).
  * EINVAL: null arguments, R < 1, topk < 0, t_min < 0.
- * EOVERFLOW: a receiver produced more composited hits or distinct senders
- * than the per-receiver buffers hold (the message says how many).
+ * Per-ray hit records (8 bytes per composited hit) and per-receiver
+ * aggregation tables grow automatically (the call is then repeated) up to
+ * 2048 composited hits per ray and 8192 distinct senders per row.
+ * EOVERFLOW: beyond those limits, or a traversal stack overflow.
  */
 gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, gsrad_ff **ff, void *stream);
 
@@ -223,9 +225,10 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
  *                 gamma_q = exp(-1.7 (u_q^2 + v_q^2))
  * plus the receiver term dL/do_i += sum_c grad_rho_ic a_ic, and
  * dL/da = grad_rho * o (both zero where the opacity clamp is active).
- * The hits are read from the records gsrad_form_factors kept (up to 128
- * composited hits per ray, if all records fit in 40 GB); rays without
- * complete records are recomputed by traversal, with identical results.
+ * The hits are read from the per-ray records gsrad_form_factors kept (it
+ * keeps them when the records of all receivers fit in 40 GB of device
+ * memory and GSRAD_FF_NO_RECORDS is not set); otherwise every ray is
+ * recomputed by traversal, with identical decisions.
  * grad_F is [nnz] in F's CSR order; grad_rho and albedo [n][3];
  * grad_opacity [n], grad_albedo [n][3] (either may be NULL).  The hit
  * recomputation needs the ff handle made from this bvh.

@@ -65,13 +65,11 @@ struct DevBuf {
     }
 };
 
-// Maximum receivers traced per launch, so the hit slabs stay within a fixed
-// budget however large the scene is.
-constexpr size_t kSlabBudget = size_t(6) << 30;
-constexpr int kHitsPerRay = 64;     // slab capacity per ray (average ~25 here)
 constexpr int kLog2Table = 12;      // 4096-entry aggregation table per receiver
-constexpr int kRecCap = 128;        // recorded hits per ray (composited: ~27 mean, ~100 max here)
-constexpr size_t kRecordBudget = size_t(40) << 30;   // records kept for the backward
+constexpr int kLog2TableMax = 13;   // 8192 entries: rows with more distinct senders
+constexpr int kRecCap = 256;        // recorded hits per ray to start with (composited: ~27 mean here)
+constexpr size_t kRecordBudget = size_t(40) << 30;       // records kept for the backward
+constexpr size_t kChunkRecordBudget = size_t(4) << 30;   // records of one chunk otherwise
 
 // ---------------------------------------------------------------------------
 // optional per-phase timing with HIP events on the caller's stream
@@ -165,10 +163,11 @@ struct gsrad_ff {
     uint64_t seed = 0;
     float t_eps = 0.0f, t_min = 0.0f;
     // recorded hits (j, +-gamma) per ray for the backward, if they fit
-    bool has_records = false, rec_overflow = false;
+    bool has_records = false;
+    int rec_cap = 0;
     DevBuf recs, rcnt;
     // scratch of the ray-cast path
-    DevBuf slab, slab_cnt, ell_col, ell_val, row_len, err, scan_temp;
+    DevBuf slab, ell_col, ell_val, row_len, err, scan_temp;
     Csr csr() const {
         Csr c;
         c.n = n;
@@ -188,7 +187,7 @@ struct gsrad_ff {
         return c;
     }
     ~gsrad_ff() {
-        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &slab_cnt, &ell_col,
+        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col,
                           &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt})
             b->release();
     }
@@ -362,8 +361,9 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     hipStream_t st = S(stream);
     const int64_t n = bvh->n;
     const int R = p->rays_per_surfel;
-    int64_t cap = (int64_t)kHitsPerRay * R;
-    const int64_t cap_row = p->topk > 0 ? p->topk : (1 << kLog2Table);
+    int rcap = kRecCap;
+    int log2h = kLog2Table;
+    const int64_t cap_row = p->topk > 0 ? p->topk : (1 << kLog2TableMax);
     gsrad_status e;
     float t_eps = p->t_eps;
     if (!(t_eps > 0.0f)) {
@@ -373,26 +373,27 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
             return fail(e);
         t_eps = b[6];
     }
-    const size_t rec_bytes = (size_t)n * R * kRecCap * sizeof(uint2);
-    const bool records = rec_bytes <= kRecordBudget && !(p->flags & GSRAD_FF_NO_RECORDS);
     int flags[4];
     int64_t nnz = 0;
+    bool keep = false;
     for (int attempt = 0;; ++attempt) {
-        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(kSlabBudget / ((size_t)cap * 8))));
+        // Records of every receiver are kept for the backward when they fit;
+        // otherwise receivers are traced in chunks whose records are only
+        // used to build F (the backward then recomputes the rays).
+        const size_t per_recv = (size_t)R * rcap * sizeof(uint2);
+        keep = (size_t)n * per_recv <= kRecordBudget && !(p->flags & GSRAD_FF_NO_RECORDS);
+        const int64_t chunk =
+            keep ? n : std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(kChunkRecordBudget / per_recv)));
 #define ENS(buf, bytes, what) \
     if ((e = h->buf.ensure((size_t)(bytes), what)) != GSRAD_OK) return fail(e);
-        ENS(slab, chunk * cap * 8, "hit slab");
-        ENS(slab_cnt, chunk * 4, "slab counts");
+        ENS(recs, (size_t)chunk * per_recv, "hit records");
+        ENS(rcnt, (size_t)chunk * R * 4, "hit record counts");
         ENS(ell_col, n * cap_row * 4, "row staging");
         ENS(ell_val, n * cap_row * 4, "row staging");
         ENS(row_len, n * 4, "row lengths");
         ENS(err, 128, "error flags");
         ENS(row_ptr, (n + 1) * 8, "row_ptr");
         ENS(scan_temp, scan_temp_bytes(n), "scan temp");
-        if (records) {
-            ENS(recs, rec_bytes, "hit records");
-            ENS(rcnt, (size_t)n * R * 4, "hit record counts");
-        }
 #undef ENS
         int *err = h->err.as<int>();
         if ((e = check_hip(hipMemsetAsync(err, 0, 64, st), "ff flags")) != GSRAD_OK) return fail(e);
@@ -401,15 +402,13 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
             const int64_t cnt = std::min(chunk, n - s0);
             {
                 ProfScope ps("ff_trace", st);
-                if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, h->slab.as<uint2>(), cap,
-                                         h->slab_cnt.as<uint32_t>(), records ? h->recs.as<uint2>() : nullptr,
-                                         records ? h->rcnt.as<uint32_t>() : nullptr, kRecCap, err, st)) != GSRAD_OK)
+                if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, keep ? 1 : 0, h->recs.as<uint2>(),
+                                         h->rcnt.as<uint32_t>(), rcap, err, st)) != GSRAD_OK)
                     return fail(e);
             }
-            hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->slab_cnt.as<uint32_t>(), cnt, err + 2);
             ProfScope ps("ff_aggregate", st);
-            if ((e = launch_ff_aggregate(bv, h->slab.as<uint2>(), h->slab_cnt.as<uint32_t>(), cap, s0, cnt, R,
-                                         p->topk, kLog2Table, cap_row, h->ell_col.as<int32_t>(), h->ell_val.as<float>(),
+            if ((e = launch_ff_aggregate(bv, h->recs.as<uint2>(), h->rcnt.as<uint32_t>(), rcap, s0, cnt, keep ? 1 : 0,
+                                         R, p->topk, log2h, cap_row, h->ell_col.as<int32_t>(), h->ell_val.as<float>(),
                                          h->row_len.as<uint32_t>(), err, st)) != GSRAD_OK)
                 return fail(e);
         }
@@ -424,19 +423,23 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
                            "ff nnz copy")) != GSRAD_OK)
             return fail(e);
         if ((e = check_hip(hipStreamSynchronize(st), "ff sync")) != GSRAD_OK) return fail(e);
-        // a receiver produced more front hits than its slab holds: grow the
-        // slab to the measured maximum and run again
-        if ((flags[0] & kErrSlab) && attempt < 2) {
-            cap = std::max<int64_t>(2 * cap, ((int64_t)flags[2] + 1023) / 1024 * 1024);
+        // a ray composited more hits than its record slots: the rows are
+        // incomplete, so run again with twice the slots
+        if ((flags[0] & kErrRecords) && attempt < 4) {
+            while (rcap < flags[3]) rcap *= 2;
+            continue;
+        }
+        // more distinct senders than the aggregation table holds: run again
+        // with the largest table
+        if ((flags[0] & kErrTable) && log2h < kLog2TableMax && attempt < 4) {
+            log2h = kLog2TableMax;
             continue;
         }
         break;
     }
-    const bool rec_overflow = (flags[0] & kErrRecords) != 0;
-    flags[0] &= ~kErrRecords;
     if (flags[0] != 0) {
-        set_error("gsrad_form_factors: overflow flags 0x%x (1 stack, 2 hit slab [max %d of %lld], 4 table, 8 row)",
-                  flags[0], flags[2], (long long)cap);
+        set_error("gsrad_form_factors: overflow flags 0x%x (1 traversal stack, 4 aggregation table of %d, 8 row, "
+                  "16 hit records of %d per ray)", flags[0], 1 << log2h, rcap);
         if (created) delete h;
         return GSRAD_EOVERFLOW;
     }
@@ -456,8 +459,8 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     h->seed = p->seed;
     h->t_eps = t_eps;
     h->t_min = p->t_min;
-    h->has_records = records;
-    h->rec_overflow = records && rec_overflow;
+    h->has_records = keep;
+    h->rec_cap = rcap;
     *ff = h;
     return GSRAD_OK;
 }
@@ -663,11 +666,10 @@ gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, co
             return einval("gsrad_opacity_backward: row too long for the LDS row cache");
         if (f->has_records) {
             ProfScope ps("opacity_records", st);
-            GS_TRY(launch_opacity_rec(bvh->dev(), f->R, f->recs.as<uint2>(), f->rcnt.as<uint32_t>(), kRecCap,
+            GS_TRY(launch_opacity_rec(bvh->dev(), f->R, f->recs.as<uint2>(), f->rcnt.as<uint32_t>(), f->rec_cap,
                                       f->row_ptr.as<int64_t>(), f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1),
                                       gacc, st));
-        }
-        if (!f->has_records || f->rec_overflow) {
+        } else {
             // recompute the rays without (complete) records by traversal
             GS_TRY(f->slab.ensure(std::max(f->slab.bytes, (size_t)n * f->R * 4), "ray sums"));
             GS_TRY(f->err.ensure(128, "flags"));
@@ -675,8 +677,7 @@ gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, co
                 ProfScope ps(pass == 0 ? "opacity_pass1" : "opacity_pass2", st);
                 GS_TRY(launch_opacity_bwd(bvh->dev(), f->R, f->seed, f->t_eps, f->t_min, f->row_ptr.as<int64_t>(),
                                           f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1), f->slab.as<float>(),
-                                          gacc, pass, f->has_records ? f->rcnt.as<uint32_t>() : nullptr, kRecCap,
-                                          f->err.as<int>() + 8, st));
+                                          gacc, pass, nullptr, 0, f->err.as<int>() + 8, st));
             }
         }
     }

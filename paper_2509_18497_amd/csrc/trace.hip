@@ -3,12 +3,11 @@
 // k_ff_trace      one workgroup per receiver surfel, one thread per ray:
 //                 multi-round k-buffer traversal (the KB nearest hits beyond
 //                 the last composited key per round, keys (t, j)), front-to-
-//                 back compositing, front-face weights appended to the
-//                 receiver's slab in HBM.
-// k_ff_aggregate  one workgroup per receiver: LDS hash table with 2^-40
-//                 fixed-point sums (integer adds are order independent, so F
-//                 is bit-deterministic), radix select of the top-k entries,
-//                 bitonic sort by column, one ELL row out.
+//                 back compositing, every composited hit recorded per ray.
+// k_ff_aggregate  one workgroup per receiver: replays the records, LDS hash
+//                 table with 2^-40 fixed-point sums (integer adds are order
+//                 independent, so F is bit-deterministic), radix select of
+//                 the top-k entries, bitonic sort by column, one ELL row.
 // k_direct        one thread per (surfel, light): shadow-ray transmittance.
 // k_opacity_bwd   compositing backward, two recomputing passes.
 #include "gsrad_internal.h"
@@ -204,46 +203,40 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
 // ---------------------------------------------------------------------------
 // form factors
 // ---------------------------------------------------------------------------
-// Records (when recs != nullptr): every composited hit of ray r of receiver
-// i as (j, +-gamma) with the sign = front face, at recs[(i*rcap + q)*R + r]
-// (hit-major inside a receiver, so a wave reads one record per lane with
-// one coalesced access); rcnt[i*R + r] = number of composited hits (a count
-// above rcap means the ray's records are incomplete).
+// Every composited hit of ray r of the receiver in slot `slot` is recorded
+// as (j, +-gamma), the sign being the front face, at
+// recs[(slot*rcap + q)*R + r] (hit-major inside a receiver, so a wave
+// touches one record per lane with one coalesced access); rcnt[slot*R + r]
+// is the number of composited hits (more than rcap: records incomplete).
+// slot = original index i when the records of all receivers are kept,
+// else the receiver's position in the current chunk.
 __global__ void __launch_bounds__(256) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
-                                                  int64_t s_begin, int64_t nblocks, uint2 *__restrict__ slab,
-                                                  int64_t cap, uint32_t *__restrict__ slab_cnt, uint2 *__restrict__ recs,
-                                                  uint32_t *__restrict__ rcnt, int rcap, int *err) {
+                                                  int64_t s_begin, int64_t nblocks, int by_orig,
+                                                  uint2 *__restrict__ recs, uint32_t *__restrict__ rcnt, int rcap,
+                                                  int *err) {
     extern __shared__ uint32_t stack_mem[];
-    __shared__ uint32_t cnt;
     const int64_t b = xcd_block(blockIdx.x, nblocks);
     const int tid = threadIdx.x;
-    if (tid == 0) cnt = 0;
-    __syncthreads();
     const SurfRec rr = bv.rec[s_begin + b];
     const uint32_t i = __float_as_uint(rr.d.w);
-    uint2 *out = slab + b * cap;
+    const int64_t slot = by_orig ? (int64_t)i : b;
     for (int r = tid; r < R; r += blockDim.x) {
         float dx, dy, dz;
         ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
                       (uint64_t)i, seed, 0, dx, dy, dz);
         uint32_t q = 0;
-        uint2 *rec_out = recs ? recs + (int64_t)i * rcap * R + r : nullptr;
+        uint2 *rec_out = recs + slot * rcap * R + r;
         trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x, err,
-                          [&](uint32_t j, float alpha, float T, bool front, float g, float) {
-                              if (rec_out && q < (uint32_t)rcap)
-                                  rec_out[(int64_t)q * R] = make_uint2(j, __float_as_uint(front ? g : -g));
+                          [&](uint32_t j, float, float, bool front, float g, float) {
+                              if (q < (uint32_t)rcap) rec_out[(int64_t)q * R] = make_uint2(j, __float_as_uint(front ? g : -g));
                               ++q;
-                              if (!front) return;
-                              const uint32_t pos = atomicAdd(&cnt, 1u);
-                              if (pos < cap) out[pos] = make_uint2(j, __float_as_uint(alpha * T));
                           });
-        if (rcnt) {
-            rcnt[(int64_t)i * R + r] = q;
-            if (q > (uint32_t)rcap) atomicOr(err, kErrRecords);
+        rcnt[slot * R + r] = q;
+        if (q > (uint32_t)rcap) {
+            atomicOr(err, kErrRecords);
+            atomicMax(err + 3, (int)q);
         }
     }
-    __syncthreads();
-    if (tid == 0) slab_cnt[b] = cnt;
 }
 
 // Slot of surfel j in an open-addressing table of 2^log2h entries.  A full
@@ -276,70 +269,113 @@ __device__ __forceinline__ uint64_t badness(uint32_t j, float v) {
     return ((uint64_t)(~__float_as_uint(v)) << 32) | (uint64_t)j;
 }
 
-__global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__restrict__ slab,
-                                                      const uint32_t *__restrict__ slab_cnt, int64_t cap,
-                                                      int64_t s_begin, int R, int topk, int log2h, int64_t cap_row,
+// Block-wide exclusive scan of one count per thread (256 threads).
+__device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t *wsum, uint32_t &total) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan_u32(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < w) off += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+constexpr int kAggMaxPer = 32;   // table slots (or entries) per thread: H <= 8192
+
+// One workgroup per receiver.  The rays' records are replayed with the same
+// FP32 alpha/T sequence as the trace; front-hit weights are summed per
+// sender in an LDS hash table in 2^-40 fixed point (integer adds commute, so
+// the sums do not depend on the order of the atomics).  The distinct senders
+// are compacted, the topk largest (value desc, column asc) kept by a radix
+// select on the FP32 values, and the row sorted by column (bitonic).
+__global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__restrict__ recs,
+                                                      const uint32_t *__restrict__ rcnt, int rcap, int64_t s_begin,
+                                                      int by_orig, int R, int topk, int log2h, int64_t cap_row,
                                                       int32_t *__restrict__ ell_col, float *__restrict__ ell_val,
                                                       uint32_t *__restrict__ row_len, int *err) {
     extern __shared__ __align__(16) unsigned char sm[];
     const int H = 1 << log2h;
     unsigned long long *hval = reinterpret_cast<unsigned long long *>(sm);   // [H]
     uint32_t *hkey = reinterpret_cast<uint32_t *>(hval + H);                  // [H]
-    uint32_t *cj = hkey + H;                                                  // [H]
-    float *cv = reinterpret_cast<float *>(cj + H);                            // [H]
-    __shared__ uint32_t m_sh, hist[256], dsel, before_sh;
+    // after compaction the same memory holds the entries: columns in the
+    // key region, FP32 values in the first half of the value region
+    uint32_t *cj = hkey;
+    float *cv = reinterpret_cast<float *>(hval);
+    __shared__ uint32_t hist[256], wsum[4], dsel, before_sh;
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     const uint32_t i = __float_as_uint(bv.rec[s_begin + b].d.w);
-    uint32_t count = slab_cnt[b];
-    if (count > cap) {
-        if (tid == 0) atomicOr(err, kErrSlab);
-        count = (uint32_t)cap;
-    }
+    const int64_t slot = by_orig ? (int64_t)i : b;
     for (int k = tid; k < H; k += 256) {
         hkey[k] = kEmpty;
         hval[k] = 0ull;
     }
-    if (tid == 0) m_sh = 0;
     __syncthreads();
-    // Each thread walks a contiguous chunk of the slab: the slab was filled
-    // by the lanes of a wave in lock-step, so neighbouring entries are
-    // mostly the same few surfels; striding them over the lanes of one
-    // insert batch would serialise the LDS atomics on one address.
-    const uint2 *in = slab + b * cap;
-    const uint32_t per = (count + 255u) / 256u;
-    const uint32_t e0 = tid * per, e1 = min(count, e0 + per);
-    for (uint32_t e = e0; e < e1; ++e) {
-        const uint2 c = in[e];
-        const unsigned long long fx = (unsigned long long)__float2ull_rn(__uint_as_float(c.y) * kFixScaleF);
-        uint32_t h = hash_slot(c.x, log2h);
-        int probe = 0;
-        for (; probe < H; ++probe) {
-            const uint32_t prev = atomicCAS(&hkey[h], kEmpty, c.x);
-            if (prev == kEmpty || prev == c.x) {
-                atomicAdd(&hval[h], fx);
-                break;
+    for (int r = tid; r < R; r += 256) {
+        const uint32_t m = min(rcnt[slot * R + r], (uint32_t)rcap);
+        const uint2 *in = recs + slot * rcap * R + r;
+        float T = 1.0f;
+        for (uint32_t q = 0; q < m; ++q) {
+            const uint2 h = in[(int64_t)q * R];
+            const float gs = __uint_as_float(h.y);
+            const float x = bv.c[h.x] * fabsf(gs);
+            if (gs > 0.0f) {
+                const float w = -expm1f(-x) * T;
+                const unsigned long long fx = (unsigned long long)__float2ull_rn(w * kFixScaleF);
+                uint32_t hs = hash_slot(h.x, log2h);
+                int probe = 0;
+                for (; probe < H; ++probe) {
+                    const uint32_t prev = atomicCAS(&hkey[hs], kEmpty, h.x);
+                    if (prev == kEmpty || prev == h.x) {
+                        atomicAdd(&hval[hs], fx);
+                        break;
+                    }
+                    hs = (hs + 1) & (uint32_t)(H - 1);
+                }
+                if (probe == H) atomicOr(err, kErrTable);
             }
-            h = (h + 1) & (uint32_t)(H - 1);
+            T *= expf(-x);
         }
-        if (probe == H) atomicOr(err, kErrTable);
     }
     __syncthreads();
+    // compact the table in place: each thread stages its own slots
     const double scale = 1.0 / (kFixScale * (double)R);
-    for (int k = tid; k < H; k += 256) {
-        const bool full = hkey[k] != kEmpty;
-        const uint64_t bal = __ballot(full);
-        uint32_t base = 0;
-        if (__lane_id() == 0 && bal) base = atomicAdd(&m_sh, (uint32_t)__popcll(bal));
-        base = __shfl(base, 0, 64);
-        if (full) {
-            const uint32_t p = base + (uint32_t)__popcll(bal & ((1ull << __lane_id()) - 1ull));
-            cj[p] = hkey[k];
-            cv[p] = (float)((double)hval[k] * scale);
+    const int per = H >> 8;
+    // staged by static index so the arrays stay in registers
+    uint32_t sj[kAggMaxPer];
+    float sv[kAggMaxPer];
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kAggMaxPer; ++k) {
+        sj[k] = kEmpty;
+        sv[k] = 0.0f;
+        if (k < per) {
+            const int sl = tid * per + k;
+            const uint32_t key = hkey[sl];
+            if (key != kEmpty) {
+                sj[k] = key;
+                sv[k] = (float)((double)hval[sl] * scale);
+                ++c;
+            }
+        }
+    }
+    uint32_t m;
+    uint32_t pos = block_scan_u32(c, wsum, m);
+#pragma unroll
+    for (int k = 0; k < kAggMaxPer; ++k) {
+        if (sj[k] != kEmpty) {
+            cj[pos] = sj[k];
+            cv[pos] = sv[k];
+            ++pos;
         }
     }
     __syncthreads();
-    uint32_t m = m_sh;
     if (topk > 0 && m > (uint32_t)topk) {
         // radix select of the topk-th smallest badness key, MSB first
         uint64_t prefix = 0, pmask = 0;
@@ -354,13 +390,13 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
             }
             __syncthreads();
             if (tid < 64) {
-                uint32_t c4[4], s = 0;
+                uint32_t c4[4], s4 = 0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     c4[q] = hist[4 * tid + q];
-                    s += c4[q];
+                    s4 += c4[q];
                 }
-                uint32_t run = wave_incl_scan_u32(s) - s;
+                uint32_t run = wave_incl_scan_u32(s4) - s4;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (run < need && need <= run + c4[q]) {
@@ -376,29 +412,36 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
             need -= before_sh;
             __syncthreads();
         }
-        // keep badness <= prefix (exactly topk entries: keys are unique)
-        if (tid == 0) m_sh = 0;
-        __syncthreads();
-        float *hv = reinterpret_cast<float *>(hval);
-        for (uint32_t e0 = 0; e0 < m; e0 += 256) {
-            const uint32_t e = e0 + tid;
-            const bool keep = e < m && badness(cj[e], cv[e]) <= prefix;
-            const uint64_t bal = __ballot(keep);
-            uint32_t base = 0;
-            if (__lane_id() == 0 && bal) base = atomicAdd(&m_sh, (uint32_t)__popcll(bal));
-            base = __shfl(base, 0, 64);
-            if (keep) {
-                const uint32_t p = base + (uint32_t)__popcll(bal & ((1ull << __lane_id()) - 1ull));
-                hkey[p] = cj[e];
-                hv[p] = cv[e];
+        // keep badness <= prefix (exactly topk entries: keys are unique),
+        // compacted in place through registers
+        const uint32_t pe = (m + 255u) >> 8;
+        uint32_t kc = 0;
+#pragma unroll
+        for (int k = 0; k < kAggMaxPer; ++k) {
+            const uint32_t e = (uint32_t)tid * pe + (uint32_t)k;
+            sj[k] = kEmpty;
+            sv[k] = 0.0f;
+            if ((uint32_t)k < pe && e < m) {
+                const uint32_t jj = cj[e];
+                const float vv = cv[e];
+                if (badness(jj, vv) <= prefix) {
+                    sj[k] = jj;
+                    sv[k] = vv;
+                    ++kc;
+                }
             }
         }
-        __syncthreads();
-        m = m_sh;
-        for (uint32_t e = tid; e < m; e += 256) {
-            cj[e] = hkey[e];
-            cv[e] = hv[e];
+        uint32_t kept;
+        uint32_t kpos = block_scan_u32(kc, wsum, kept);
+#pragma unroll
+        for (int k = 0; k < kAggMaxPer; ++k) {
+            if (sj[k] != kEmpty) {
+                cj[kpos] = sj[k];
+                cv[kpos] = sv[k];
+                ++kpos;
+            }
         }
+        m = kept;
         __syncthreads();
     }
     // bitonic sort of the m entries by column
@@ -412,9 +455,9 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
                 const uint32_t idx = 2 * stride * (t / stride) + (t % stride);
                 const uint32_t par = idx + stride;
                 const bool asc = (idx & size) == 0;
-                const uint32_t a = cj[idx], c = cj[par];
-                if ((a > c) == asc) {
-                    cj[idx] = c;
+                const uint32_t a = cj[idx], cc = cj[par];
+                if ((a > cc) == asc) {
+                    cj[idx] = cc;
                     cj[par] = a;
                     const float va = cv[idx];
                     cv[idx] = cv[par];
@@ -690,28 +733,28 @@ __global__ void __launch_bounds__(256) k_reflectance(BvhDev bv, const float *__r
 size_t ff_stack_bytes(int threads) { return (size_t)kStack * threads * sizeof(uint32_t); }
 
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, uint2 *recs, uint32_t *rcnt,
-                             int rcap, int *err, hipStream_t st) {
+                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int *err,
+                             hipStream_t st) {
     const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
     hipLaunchKernelGGL(k_ff_trace, dim3((unsigned)count), dim3(threads), ff_stack_bytes(threads), st, bv, R, seed,
-                       t_eps, t_min, s_begin, count, slab, cap, slab_cnt, recs, rcnt, rcap, err);
+                       t_eps, t_min, s_begin, count, by_orig, recs, rcnt, rcap, err);
     return check_hip(hipGetLastError(), "ff trace launch");
 }
 
-size_t ff_aggregate_smem(int log2h) { return (size_t)(1 << log2h) * (8 + 4 + 4 + 4); }
+size_t ff_aggregate_smem(int log2h) { return (size_t)(1 << log2h) * 12; }
 
-gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *slab, const uint32_t *slab_cnt, int64_t cap,
-                                 int64_t s_begin, int64_t count, int R, int topk, int log2h, int64_t cap_row,
+gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *recs, const uint32_t *rcnt, int rcap, int64_t s_begin,
+                                 int64_t count, int by_orig, int R, int topk, int log2h, int64_t cap_row,
                                  int32_t *ell_col, float *ell_val, uint32_t *row_len, int *err, hipStream_t st) {
-    const size_t smem = ff_aggregate_smem(log2h);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_aggregate),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
-        attr_set = true;
+    if (log2h < 8 || log2h > 13) {
+        set_error("aggregation table size out of range");
+        return GSRAD_EINVAL;
     }
-    hipLaunchKernelGGL(k_ff_aggregate, dim3((unsigned)count), dim3(256), smem, st, bv, slab, slab_cnt, cap, s_begin, R,
-                       topk, log2h, cap_row, ell_col, ell_val, row_len, err);
+    const size_t smem = ff_aggregate_smem(log2h);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_aggregate),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    hipLaunchKernelGGL(k_ff_aggregate, dim3((unsigned)count), dim3(256), smem, st, bv, recs, rcnt, rcap, s_begin,
+                       by_orig, R, topk, log2h, cap_row, ell_col, ell_val, row_len, err);
     return check_hip(hipGetLastError(), "ff aggregate launch");
 }
 

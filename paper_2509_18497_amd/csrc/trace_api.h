@@ -8,7 +8,7 @@ namespace gsrad {
 
 // device error flag bits
 constexpr int kErrStack = 1;   // traversal stack overflow
-constexpr int kErrSlab = 2;    // a receiver produced more hits than its slab holds
+constexpr int kErrSlab = 2;    // (unused)
 constexpr int kErrTable = 4;   // more distinct senders than the aggregation table holds
 constexpr int kErrRow = 8;     // row longer than the ELL capacity
 constexpr int kErrRecords = 16; // a ray composited more hits than its record slots (recomputed later)
@@ -16,10 +16,10 @@ constexpr int kErrRecords = 16; // a ray composited more hits than its record sl
 size_t ff_stack_bytes(int threads);
 size_t ff_aggregate_smem(int log2h);
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, uint2 *slab, int64_t cap, uint32_t *slab_cnt, uint2 *recs, uint32_t *rcnt,
-                             int rcap, int *err, hipStream_t st);
-gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *slab, const uint32_t *slab_cnt, int64_t cap,
-                                 int64_t s_begin, int64_t count, int R, int topk, int log2h, int64_t cap_row,
+                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int *err,
+                             hipStream_t st);
+gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *recs, const uint32_t *rcnt, int rcap, int64_t s_begin,
+                                 int64_t count, int by_orig, int R, int topk, int log2h, int64_t cap_row,
                                  int32_t *ell_col, float *ell_val, uint32_t *row_len, int *err, hipStream_t st);
 gsrad_status launch_ell_to_csr(const int32_t *ell_col, const float *ell_val, int64_t cap_row, const int64_t *row_ptr,
                                int64_t n, int32_t *col, float *val, hipStream_t st);
