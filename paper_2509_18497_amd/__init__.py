@@ -5,5 +5,5 @@ The HIP library libgsrad.so (C ABI in include/gsrad.h) holds every kernel;
 """
 from . import gsrad  # noqa: F401
 from .gsrad import (BVH, FF, GsradError, RadiosityFn, Tape, build_bvh, check, direct_light,  # noqa: F401
-                    effective_area, ff_from_csr, form_factors, opacity_backward, ray_hits, reflectance, transport_backward,
-                    transport_solve, version)
+                    effective_area, ff_from_csr, form_factors, opacity_backward, profile_enable, profile_report,
+                    ray_hits, reflectance, transport_backward, transport_solve, version)

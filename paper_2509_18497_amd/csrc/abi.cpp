@@ -363,6 +363,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     const int R = p->rays_per_surfel;
     int rcap = kRecCap;
     int log2h = kLog2Table;
+    int deep = 0;
     const int64_t cap_row = p->topk > 0 ? p->topk : (1 << kLog2TableMax);
     gsrad_status e;
     float t_eps = p->t_eps;
@@ -403,7 +404,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
             {
                 ProfScope ps("ff_trace", st);
                 if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, keep ? 1 : 0, h->recs.as<uint2>(),
-                                         h->rcnt.as<uint32_t>(), rcap, err, st)) != GSRAD_OK)
+                                         h->rcnt.as<uint32_t>(), rcap, deep, err, st)) != GSRAD_OK)
                     return fail(e);
             }
             ProfScope ps("ff_aggregate", st);
@@ -423,6 +424,12 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
                            "ff nnz copy")) != GSRAD_OK)
             return fail(e);
         if ((e = check_hip(hipStreamSynchronize(st), "ff sync")) != GSRAD_OK) return fail(e);
+        // a tree deeper than the shallow traversal stack: trace again with
+        // the deep one
+        if ((flags[0] & kErrStack) && !deep) {
+            deep = 1;
+            continue;
+        }
         // a ray composited more hits than its record slots: the rows are
         // incomplete, so run again with twice the slots
         if ((flags[0] & kErrRecords) && attempt < 4) {

@@ -17,7 +17,12 @@ namespace gsrad {
 
 namespace {
 
-constexpr int kStack = 48;
+// Traversal stack entries per lane (LDS).  The form-factor trace first runs
+// with the shallow stack (it keeps three workgroups per CU resident); a
+// tree deep enough to overflow it is traced again with the deep one, which
+// covers any LBVH of 30-bit Morton codes plus 32 index bits.
+constexpr int kStackShallow = 32;
+constexpr int kStackDeep = 64;
 constexpr int kKB = 16;
 constexpr uint32_t kEmpty = 0xffffffffu;
 
@@ -65,7 +70,7 @@ __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int 
 // transmittance drops below t_min; on_hit(j, alpha, T_before, front, gamma)
 // is called for every composited hit (plus its depth t).  Returns the final
 // transmittance.
-template <int KB, typename OnHit>
+template <int KB, int STK = kStackDeep, typename OnHit>
 __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float oy, float oz, float dx, float dy,
                                               float dz, uint32_t self, float t_eps, float t_min,
                                               uint32_t *stack, int stride, int *err, OnHit &&on_hit) {
@@ -103,7 +108,7 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
                     h1 = false;
                 }
                 if (h0 && h1) {
-                    if (sp >= kStack) {
+                    if (sp >= STK) {
                         atomicOr(err, kErrStack);
                         return T;
                     }
@@ -180,7 +185,7 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
             h1 = false;
         }
         if (h0 && h1) {
-            if (sp >= kStack) {
+            if (sp >= kStackDeep) {
                 atomicOr(err, kErrStack);
                 return T;
             }
@@ -203,6 +208,27 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
 // ---------------------------------------------------------------------------
 // form factors
 // ---------------------------------------------------------------------------
+// Octahedral 2 x 8-bit Morton key of a direction: rays with close keys
+// leave in close directions.
+__device__ __forceinline__ uint32_t dir_key(float dx, float dy, float dz) {
+    const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
+    float px = dx / l1, py = dy / l1;
+    if (dz < 0.0f) {
+        const float qx = (1.0f - fabsf(py)) * (px >= 0.0f ? 1.0f : -1.0f);
+        const float qy = (1.0f - fabsf(px)) * (py >= 0.0f ? 1.0f : -1.0f);
+        px = qx;
+        py = qy;
+    }
+    const uint32_t ux = min(255u, (uint32_t)((px * 0.5f + 0.5f) * 256.0f));
+    const uint32_t uy = min(255u, (uint32_t)((py * 0.5f + 0.5f) * 256.0f));
+    uint32_t k = 0;
+#pragma unroll
+    for (int bt = 0; bt < 8; ++bt) k |= (((ux >> bt) & 1u) << (2 * bt)) | (((uy >> bt) & 1u) << (2 * bt + 1));
+    return k;
+}
+
+constexpr int kPoolRays = 1024;   // rays sorted and pooled per batch
+
 // Every composited hit of ray r of the receiver in slot `slot` is recorded
 // as (j, +-gamma), the sign being the front face, at
 // recs[(slot*rcap + q)*R + r] (hit-major inside a receiver, so a wave
@@ -210,32 +236,89 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
 // is the number of composited hits (more than rcap: records incomplete).
 // slot = original index i when the records of all receivers are kept,
 // else the receiver's position in the current chunk.
+//
+// One workgroup traces the rays of `group` consecutive receivers (Morton
+// order).  Per batch of up to 1024 rays the directions are generated, the
+// rays sorted by direction key, and the lanes pull rays from the sorted
+// pool through an LDS counter: neighbouring lanes trace rays that leave
+// close origins in close directions, and a lane whose ray ends early takes
+// the next one instead of idling until its wave's longest ray is done.
+template <int STK>
 __global__ void __launch_bounds__(256) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
-                                                  int64_t s_begin, int64_t nblocks, int by_orig,
-                                                  uint2 *__restrict__ recs, uint32_t *__restrict__ rcnt, int rcap,
-                                                  int *err) {
+                                                  int64_t s_begin, int64_t count, int group, int64_t nblocks,
+                                                  int by_orig, uint2 *__restrict__ recs,
+                                                  uint32_t *__restrict__ rcnt, int rcap, int *err) {
     extern __shared__ uint32_t stack_mem[];
-    const int64_t b = xcd_block(blockIdx.x, nblocks);
+    __shared__ uint32_t pool_key[kPoolRays];
+    __shared__ float pool_d[kPoolRays][3];
+    __shared__ uint32_t next;
+    const int64_t gb = xcd_block(blockIdx.x, nblocks);
     const int tid = threadIdx.x;
-    const SurfRec rr = bv.rec[s_begin + b];
-    const uint32_t i = __float_as_uint(rr.d.w);
-    const int64_t slot = by_orig ? (int64_t)i : b;
-    for (int r = tid; r < R; r += blockDim.x) {
-        float dx, dy, dz;
-        ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
-                      (uint64_t)i, seed, 0, dx, dy, dz);
-        uint32_t q = 0;
-        uint2 *rec_out = recs + slot * rcap * R + r;
-        trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x, err,
-                          [&](uint32_t j, float, float, bool front, float g, float) {
-                              if (q < (uint32_t)rcap) rec_out[(int64_t)q * R] = make_uint2(j, __float_as_uint(front ? g : -g));
-                              ++q;
-                          });
-        rcnt[slot * R + r] = q;
-        if (q > (uint32_t)rcap) {
-            atomicOr(err, kErrRecords);
-            atomicMax(err + 3, (int)q);
+    const int64_t r0 = gb * group;                                 // first receiver (chunk-relative)
+    const int g = (int)min<int64_t>(group, count - r0);            // receivers in this group
+    const int64_t total = (int64_t)g * R;
+    for (int64_t base = 0; base < total; base += kPoolRays) {
+        const int nb = (int)min<int64_t>(kPoolRays, total - base);
+        int P = 1;
+        while (P < nb) P <<= 1;
+        for (int k = tid; k < P; k += blockDim.x) {
+            uint32_t key = 0xffffffffu;
+            if (k < nb) {
+                const int64_t id = base + k;
+                const SurfRec rr = bv.rec[s_begin + r0 + id / R];
+                const int r = (int)(id % R);
+                float dx, dy, dz;
+                ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
+                              (uint64_t)__float_as_uint(rr.d.w), seed, 0, dx, dy, dz);
+                pool_d[k][0] = dx;
+                pool_d[k][1] = dy;
+                pool_d[k][2] = dz;
+                key = (dir_key(dx, dy, dz) << 10) | (uint32_t)k;
+            }
+            pool_key[k] = key;
         }
+        if (tid == 0) next = 0;
+        __syncthreads();
+        for (int size = 2; size <= P; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = tid; t < P / 2; t += blockDim.x) {
+                    const int idx = 2 * stride * (t / stride) + (t % stride);
+                    const int par = idx + stride;
+                    const bool asc = (idx & size) == 0;
+                    const uint32_t x = pool_key[idx], y = pool_key[par];
+                    if ((x > y) == asc) {
+                        pool_key[idx] = y;
+                        pool_key[par] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (;;) {
+            const uint32_t p = atomicAdd(&next, 1u);
+            if (p >= (uint32_t)nb) break;
+            const int k = (int)(pool_key[p] & 1023u);
+            const int64_t id = base + k;
+            const int64_t recv = r0 + id / R;                        // chunk-relative receiver
+            const int r = (int)(id % R);
+            const SurfRec rr = bv.rec[s_begin + recv];
+            const uint32_t i = __float_as_uint(rr.d.w);
+            const int64_t slot = by_orig ? (int64_t)i : recv;
+            uint32_t q = 0;
+            uint2 *rec_out = recs + slot * rcap * R + r;
+            trace_sorted<kKB, STK>(bv, rr.a.x, rr.a.y, rr.a.z, pool_d[k][0], pool_d[k][1], pool_d[k][2], i, t_eps, t_min,
+                              stack_mem + tid, blockDim.x, err, [&](uint32_t j, float, float, bool front, float gg, float) {
+                                  if (q < (uint32_t)rcap)
+                                      rec_out[(int64_t)q * R] = make_uint2(j, __float_as_uint(front ? gg : -gg));
+                                  ++q;
+                              });
+            rcnt[slot * R + r] = q;
+            if (q > (uint32_t)rcap) {
+                atomicOr(err, kErrRecords);
+                atomicMax(err + 3, (int)q);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -730,14 +813,24 @@ __global__ void __launch_bounds__(256) k_reflectance(BvhDev bv, const float *__r
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-size_t ff_stack_bytes(int threads) { return (size_t)kStack * threads * sizeof(uint32_t); }
+size_t ff_stack_bytes(int threads) { return (size_t)kStackDeep * threads * sizeof(uint32_t); }
 
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int *err,
+                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, int *err,
                              hipStream_t st) {
-    const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
-    hipLaunchKernelGGL(k_ff_trace, dim3((unsigned)count), dim3(threads), ff_stack_bytes(threads), st, bv, R, seed,
-                       t_eps, t_min, s_begin, count, by_orig, recs, rcnt, rcap, err);
+    const int group = R >= kPoolRays ? 1 : kPoolRays / R;
+    const int64_t nblocks = (count + group - 1) / group;
+    if (deep) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_trace<kStackDeep>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kStackDeep * 256 * 4);
+        hipLaunchKernelGGL(k_ff_trace<kStackDeep>, dim3((unsigned)nblocks), dim3(256),
+                           (size_t)kStackDeep * 256 * sizeof(uint32_t), st, bv, R, seed, t_eps, t_min, s_begin, count,
+                           group, nblocks, by_orig, recs, rcnt, rcap, err);
+    } else {
+        hipLaunchKernelGGL(k_ff_trace<kStackShallow>, dim3((unsigned)nblocks), dim3(256),
+                           (size_t)kStackShallow * 256 * sizeof(uint32_t), st, bv, R, seed, t_eps, t_min, s_begin,
+                           count, group, nblocks, by_orig, recs, rcnt, rcap, err);
+    }
     return check_hip(hipGetLastError(), "ff trace launch");
 }
 

@@ -16,7 +16,7 @@ constexpr int kErrRecords = 16; // a ray composited more hits than its record sl
 size_t ff_stack_bytes(int threads);
 size_t ff_aggregate_smem(int log2h);
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int *err,
+                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, int *err,
                              hipStream_t st);
 gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *recs, const uint32_t *rcnt, int rcap, int64_t s_begin,
                                  int64_t count, int by_orig, int R, int topk, int log2h, int64_t cap_row,

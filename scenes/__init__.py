@@ -387,6 +387,33 @@ def layer_stack(n_layers: int = 160, per_layer: int = 3, spacing: float = 0.01, 
     return sur
 
 
+def deep_chain(copies: int = 16, scale: float = 3.0, opacity: float = 0.3, seed: int = 0) -> Dict[str, np.ndarray]:
+    """Centres whose 30-bit Morton codes are 0, every single bit and all
+    ones: with the scene box [0, 4]^3 the quantised coordinates of the axis
+    points are powers of two, so an LBVH over the sorted codes peels one code
+    per level (a chain of 31 internal nodes) and the `copies` surfels sharing
+    each centre add a balanced subtree below.  Surfels far larger than the
+    scene make every box cover every ray origin, so a depth-first traversal
+    keeps a far child pending at every level of the chain."""
+    rng = np.random.default_rng(seed)
+    cen = [np.zeros(3), np.full(3, 4.0)]
+    for k in range(10):
+        for a in range(3):
+            c = np.zeros(3)
+            c[a] = (2.0 ** k + 0.25) / 256.0
+            cen.append(c)
+    p = np.repeat(np.asarray(cen), copies, axis=0)
+    m = p.shape[0]
+    g = rng.standard_normal((m, 3))
+    nrm = g / np.linalg.norm(g, axis=1, keepdims=True)
+    tu, tv = onb_from_normal(nrm)
+    tu, tv = _spin(tu, tv, rng)
+    su = np.full(m, scale)
+    op = np.full(m, opacity)
+    sur, _ = _pack(p, nrm, tu, tv, su, su, op, np.zeros((m, 3)))
+    return sur
+
+
 def surfels_from_arrays(p, nrm, tu, tv, su, sv, op) -> Dict[str, np.ndarray]:
     """Pack explicit geometry (used by analytic two-surfel set-ups)."""
     sur, _ = _pack(np.asarray(p, float), np.asarray(nrm, float), np.asarray(tu, float),

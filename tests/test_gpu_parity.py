@@ -319,3 +319,33 @@ def test_layer_stack_forward_and_opacity_backward(g, orc, records):
     W.sort_indices()
     goo, _ = orc.opacity_backward(sur, alb, R, seed, te, 1e-4, (W.indptr, W.indices, W.data), grad_rho=grho)
     assert rel_err(go.cpu().numpy(), goo) < 5 * TOL
+
+
+# ---------------------------------------------------------------------------
+# a tree deeper than the shallow traversal stack: the form-factor trace is
+# run again with the deep stack and still matches the oracle
+# ---------------------------------------------------------------------------
+def test_deep_tree_retraces_with_deep_stack(g, orc):
+    sur = scenes.deep_chain()
+    n = sur["px"].shape[0]
+    R, seed = 8, 3
+    bvh = g.build_bvh(dev_surfels(sur))
+    assert bvh.height() >= 34
+    g.profile_enable(True)
+    try:
+        ff = g.form_factors(bvh, R, seed, t_min=1e-4)
+        torch.cuda.synchronize()
+        rep = g.profile_report()
+    finally:
+        g.profile_enable(False)
+    assert rep["ff_trace"]["count"] >= 2, rep   # shallow attempt, then deep (and record growth)
+    Fg = gpu_csr(ff)
+    te = orc.default_t_eps(sur)
+    Fo, _ = orc.ff_matrix(sur, R, seed, te, 1e-4, 0)
+    assert rel_err(Fg.toarray(), Fo.toarray()) < TOL
+    # the shadow rays and the backward traversal use the deep stack directly
+    alb = np.full((n, 3), 0.5, np.float32)
+    E = g.direct_light(bvh, dev(alb), dev(np.array([[2.0, 2.0, 2.0]], np.float32)),
+                       dev(np.array([3.0], np.float32)), 1)
+    Eo = orc.direct_light(sur, alb, np.array([[2.0, 2.0, 2.0]]), np.array([3.0]), 1, te)
+    assert rel_err(E.cpu().numpy(), Eo) < TOL
