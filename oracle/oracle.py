@@ -282,7 +282,7 @@ def bounce(F, rho_arr, E, n_bounces: int, keep_tape: bool = False):
     return (B.reshape(shape), tape) if keep_tape else B.reshape(shape)
 
 
-def adjoint(F, rho_arr, tape, g, chunk: int = 4096):
+def adjoint(F, rho_arr, tape, g, chunk: int = 4096, want_grad_F: bool = True):
     """Exact adjoint of ``bounce`` for a loss with dL/dB^(n) = g:
       lambda^(n) = g,  lambda^(k) = F^T (rho * lambda^(k+1))   (Eq. final_dL_dE,
                                                                division-free)
@@ -291,7 +291,8 @@ def adjoint(F, rho_arr, tape, g, chunk: int = 4096):
                    truncated counterpart of Eq. final-dl-dbrdf)
       grad_F_ij  = sum_{k<n} <rho_i * lambda_i^(k+1), B_j^(k)>             (decay
                    term of Eq. dl-dgeo-0 per recorded pair (i, j))
-    grad_F is returned aligned with F's CSR entries (F.indices order)."""
+    grad_F is returned aligned with F's CSR entries (F.indices order), or
+    as None when not wanted."""
     shape = np.shape(g)
     N = shape[0]
     lam = np.asarray(g, np.float64).reshape(N, -1).copy()
@@ -308,12 +309,12 @@ def adjoint(F, rho_arr, tape, g, chunk: int = 4096):
         Q = F @ Bk
         grad_rho += (lam * Q).reshape(N, -1, 3).sum(axis=1)
         rl = rc * lam
-        for s in range(0, F.nnz, chunk * 64):
+        for s in range(0, F.nnz if want_grad_F else 0, chunk * 64):
             e = min(F.nnz, s + chunk * 64)
             gF[s:e] += np.einsum("ec,ec->e", rl[rows[s:e]], Bk[F.indices[s:e]])
         lam = FT @ rl
         grad_E += lam
-    return grad_E.reshape(shape), grad_rho, gF
+    return grad_E.reshape(shape), grad_rho, (gF if want_grad_F else None)
 
 
 def opacity_backward(surfels, albedo, R: int, seed: int, t_eps: float, t_min: float, gF_rows, grad_rho=None,
