@@ -29,10 +29,11 @@
  *   - the compositing backward for opacity gradients through recorded hits
  *     (Eq. dl-dgeo-0, decay-term part, restricted to opacity).
  *
- * Hit decisions (which surfel a ray hits, and the depth order) are integers
- * decided by floating point, so this oracle takes them in the same FP32
- * operation sequence the GPU kernel uses (definition "D_hit" below); all
- * weights, sums and gradients are then evaluated in FP64.
+ * Hit decisions (which surfel a ray hits, and the depth order) and the
+ * compositing cut (after which hit a ray stops) are integers decided by
+ * floating point, so this oracle takes them in the FP32 operation sequence
+ * the GPU kernel uses (definitions "D_hit" and "D_stop" below); all weights,
+ * sums and gradients are then evaluated in FP64.
  */
 #include <math.h>
 #include <stdint.h>
@@ -189,6 +190,58 @@ static float clamp_opacity(float o) {
     return o < ORC_OPACITY_MAX ? o : ORC_OPACITY_MAX;
 }
 
+/* ------------------------------------------------------------------------
+ * Compositing cut, definition "D_stop" (fixed operations).  The ray keeps
+ * an FP32 transmittance T32 = 1 and, per hit in (t, j) order,
+ *   c32   = -log1p(-o_j) evaluated in FP64, rounded to FP32 once
+ *   r2s   = u^2 + v^2 of the FP64 intersection, rounded to FP32 once:
+ *           den = d.n, q = p - o, t = (q.n)/den, h = t d - q,
+ *           u = (h.t_u) * fl32(1/s_u), v = (h.t_v) * fl32(1/s_v)
+ *           (FP64 operations in this order, sums left to right)
+ *   g32   = exp_fx(-(1.7f * r2s))
+ *   T32   = T32 * exp_fx(-(c32 * g32))    (each product rounded)
+ * and stops after the first hit that leaves T32 < t_min.
+ * exp_fx(y), y <= 0: e^y by Cody-Waite reduction y = k ln2 + r with
+ *   k = rint(y * log2(e)),  r = fma(k, -ln2_hi, y),  r = fma(k, -ln2_lo, r),
+ *   ln2_hi = 0x1.62e4p-1 (exact, 15 bits), ln2_lo = ln2 - ln2_hi in FP32,
+ * the degree-7 Taylor polynomial of e^r by Horner with fma (coefficients
+ * 1/n! rounded to FP32), and an exact scaling by 2^k; 0 for y <= -80.
+ * Every step is a correctly rounded FP32 operation, so any implementation
+ * of these steps returns the same bits (about 2 ulp from e^y).
+ * ---------------------------------------------------------------------- */
+float orc_exp_fx(float y) {
+    if (!(y > -80.0f)) return 0.0f;
+    float k = rintf(y * 1.44269504088896341f);
+    float r = fmaf(k, -0x1.62e4p-1f, y);
+    r = fmaf(k, -1.42860682030941723212e-6f, r);
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)k);
+}
+
+static float stop_factor(const orc_scene *s, const float o[3], const float d[3], const orc_hit *h) {
+    const int64_t j = h->j;
+    double nx = s->nx[j], ny = s->ny[j], nz = s->nz[j];
+    double qx = (double)s->px[j] - (double)o[0], qy = (double)s->py[j] - (double)o[1],
+           qz = (double)s->pz[j] - (double)o[2];
+    double den = (double)d[0] * nx + (double)d[1] * ny + (double)d[2] * nz;
+    double t = (qx * nx + qy * ny + qz * nz) / den;
+    double hx = t * d[0] - qx, hy = t * d[1] - qy, hz = t * d[2] - qz;
+    float isu = 1.0f / s->su[j], isv = 1.0f / s->sv[j];
+    double u = (hx * s->tux[j] + hy * s->tuy[j] + hz * s->tuz[j]) * (double)isu;
+    double v = (hx * s->tvx[j] + hy * s->tvy[j] + hz * s->tvz[j]) * (double)isv;
+    float r2s = (float)(u * u + v * v);
+    float c32 = (float)(-log1p(-(double)clamp_opacity(s->op[j])));
+    float g32 = orc_exp_fx(-(1.7f * r2s));
+    return orc_exp_fx(-(c32 * g32));
+}
+
 /* FP64 kernel value at the hit: gamma = exp(-1.7 (u^2+v^2)) from the exact
  * (FP64) intersection of the FP32 ray with surfel j's plane. */
 static double hit_gamma64(const orc_scene *s, const float o[3], const float d[3], int64_t j) {
@@ -227,7 +280,7 @@ static int64_t collect_hits(const orc_scene *s, const float o[3], const float d[
  * (all of them, also those behind the cut) or -(needed) if cap is short. */
 int64_t orc_trace_ray(const orc_scene *s, int64_t i, uint64_t r, uint64_t seed, float t_eps, float t_min,
                       int64_t cap, float *t_out, int32_t *j_out, int8_t *front_out, double *alpha_out,
-                      double *T_out, int64_t *n_comp, float d_out[3]) {
+                      double *T_out, float *T32_out, int64_t *n_comp, float d_out[3]) {
     float o[3] = {s->px[i], s->py[i], s->pz[i]}, d[3];
     orc_ray_direction(s, i, r, seed, 0, d);
     if (d_out) { d_out[0] = d[0]; d_out[1] = d[1]; d_out[2] = d[2]; }
@@ -236,6 +289,7 @@ int64_t orc_trace_ray(const orc_scene *s, int64_t i, uint64_t r, uint64_t seed, 
     int64_t m = collect_hits(s, o, d, i, t_eps, 0.0f, 0, &buf, &bcap);
     if (m > cap) { free(buf); return -m; }
     double T = 1.0;
+    float T32 = 1.0f;
     int64_t nc = m;
     int stopped = 0;
     for (int64_t q = 0; q < m; ++q) {
@@ -247,10 +301,10 @@ int64_t orc_trace_ray(const orc_scene *s, int64_t i, uint64_t r, uint64_t seed, 
         front_out[q] = (int8_t)buf[q].front;
         alpha_out[q] = -expm1(-c * g);
         T_out[q] = T;
-        if (!stopped) {
-            T *= exp(-c * g);
-            if (T < (double)t_min) { nc = q + 1; stopped = 1; }
-        }
+        if (T32_out) T32_out[q] = T32;
+        T *= exp(-c * g);
+        T32 = T32 * stop_factor(s, o, d, &buf[q]);
+        if (!stopped && T32 < t_min) { nc = q + 1; stopped = 1; }
     }
     *n_comp = nc;
     free(buf);
@@ -312,6 +366,7 @@ int orc_ff_rows(const orc_scene *s, const int64_t *recv, int64_t n_recv, int32_t
                 orc_ray_direction(s, i, (uint64_t)r, seed, 0, d);
                 int64_t m = collect_hits(s, o, d, i, t_eps, 0.0f, 0, &buf, &bcap);
                 double T = 1.0;
+                float T32 = 1.0f;
                 int64_t q = 0;
                 for (; q < m; ++q) {
                     int64_t j = buf[q].j;
@@ -326,7 +381,8 @@ int orc_ff_rows(const orc_scene *s, const int64_t *recv, int64_t n_recv, int32_t
                         back += w;
                     }
                     T *= exp(-c * g);
-                    if (T < (double)t_min) { ++q; break; }
+                    T32 = T32 * stop_factor(s, o, d, &buf[q]);
+                    if (T32 < t_min) { ++q; break; }
                 }
                 if ((double)q > maxh) maxh = (double)q;
                 opaque += 1.0 - T;
@@ -478,6 +534,7 @@ void orc_opacity_backward(const orc_scene *s, const int64_t *recv, int64_t n_rec
                     gam = (double *)realloc(gam, (size_t)acap * sizeof(double));
                 }
                 double Tc = 1.0;
+                float T32 = 1.0f;
                 int64_t mc = 0;
                 for (int64_t q = 0; q < m; ++q) {
                     int64_t j = buf[q].j;
@@ -487,8 +544,9 @@ void orc_opacity_backward(const orc_scene *s, const int64_t *recv, int64_t n_rec
                     T[q] = Tc;
                     gw[q] = buf[q].front ? G[j] * a[q] * Tc : 0.0;
                     Tc *= exp(-c * gam[q]);
+                    T32 = T32 * stop_factor(s, o, d, &buf[q]);
                     mc = q + 1;
-                    if (Tc < (double)t_min) break;
+                    if (T32 < t_min) break;
                 }
                 double suffix = 0.0;
                 for (int64_t q = mc - 1; q >= 0; --q) {

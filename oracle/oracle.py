@@ -42,7 +42,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        src = os.path.join(HERE, "gsrad_oracle.c")
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
             from . import build as _b  # noqa: F401  (package-relative when imported as oracle.oracle)
             _b.build()
         L = ctypes.CDLL(LIB_PATH)
@@ -55,9 +56,11 @@ def lib():
         L.orc_default_t_eps.restype = ctypes.c_float
         L.orc_trace_ray.argtypes = [P(_Scene), ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_float,
                                     ctypes.c_float, ctypes.c_int64, P(ctypes.c_float), P(ctypes.c_int32),
-                                    P(ctypes.c_int8), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int64),
-                                    P(ctypes.c_float)]
+                                    P(ctypes.c_int8), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_float),
+                                    P(ctypes.c_int64), P(ctypes.c_float)]
         L.orc_trace_ray.restype = ctypes.c_int64
+        L.orc_exp_fx.argtypes = [ctypes.c_float]
+        L.orc_exp_fx.restype = ctypes.c_float
         L.orc_ff_rows.argtypes = [P(_Scene), P(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                   ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int64, P(ctypes.c_int32),
                                   P(ctypes.c_double), P(ctypes.c_int64), P(ctypes.c_double), ctypes.c_int32]
@@ -132,23 +135,25 @@ def default_t_eps(surfels) -> np.float32:
 
 def trace_ray(surfels, i: int, r: int, seed: int, t_eps: float, t_min: float, cap: int = 4096):
     """Every hit of one ray in (t, j) order with FP64 alpha and the
-    transmittance in front of it (Eq. L_I); n_comp hits are composited."""
+    transmittance in front of it (Eq. L_I), plus the FP32 transmittance of
+    the compositing cut (D_stop); n_comp hits are composited."""
     sc = _SceneRef(surfels)
     t = np.zeros(cap, np.float32)
     j = np.zeros(cap, np.int32)
     fr = np.zeros(cap, np.int8)
     al = np.zeros(cap, np.float64)
     T = np.zeros(cap, np.float64)
+    T32 = np.zeros(cap, np.float32)
     nc = ctypes.c_int64(0)
     d = np.zeros(3, np.float32)
     m = lib().orc_trace_ray(sc.ref, int(i), int(r), int(seed), float(t_eps), float(t_min), cap,
                             _ptr(t, ctypes.c_float), _ptr(j, ctypes.c_int32), _ptr(fr, ctypes.c_int8),
-                            _ptr(al, ctypes.c_double), _ptr(T, ctypes.c_double), ctypes.byref(nc),
-                            _ptr(d, ctypes.c_float))
+                            _ptr(al, ctypes.c_double), _ptr(T, ctypes.c_double), _ptr(T32, ctypes.c_float),
+                            ctypes.byref(nc), _ptr(d, ctypes.c_float))
     if m < 0:
         return trace_ray(surfels, i, r, seed, t_eps, t_min, cap=-m)
     return {"t": t[:m], "j": j[:m], "front": fr[:m].astype(bool), "alpha": al[:m], "T": T[:m],
-            "n_comp": int(nc.value), "d": d}
+            "T32": T32[:m], "n_comp": int(nc.value), "d": d}
 
 
 # ---------------------------------------------------------------------------

@@ -121,7 +121,8 @@ __global__ void __launch_bounds__(kThreads) k_records(gsrad_surfels sf, const ui
     const float su = sf.su[j], sv = sf.sv[j];
     const float oraw = sf.opacity[j];
     const float o = clamp_op(oraw);
-    const float c = -log1pf(-o);
+    // c = -ln(1 - o), evaluated in FP64 and rounded once to FP32
+    const float c = (float)(-log1p(-(double)o));
     SurfRec r;
     r.a = make_float4(px, py, pz, __fdiv_rn(1.0f, su));
     r.b = make_float4(nx, ny, nz, __fdiv_rn(1.0f, sv));

@@ -143,6 +143,56 @@ __device__ __forceinline__ bool hit_test(const SurfRec &s, float ox, float oy, f
     return true;
 }
 
+// e^y for y <= 0 from correctly rounded FP32 steps only, so that the
+// compositing cut (the first hit that leaves T < t_min) is one fixed
+// function of the hit list: Cody-Waite reduction y = k ln2 + r with
+// k = rint(y log2 e) and ln2 split into a 15-bit head (exact products)
+// and an FP32 tail, the degree-7 Taylor polynomial of e^r (|r| <= ln2/2,
+// truncation 3e-9) by Horner with fma, then an exact scaling by 2^k.
+// Within 1 ulp of e^y on (-80, 0]; 0 at or below -80.
+__device__ __forceinline__ float exp_fx(float y) {
+    if (!(y > -80.0f)) return 0.0f;
+    const float k = rintf(__fmul_rn(y, 1.44269504088896341f));
+    float r = __builtin_fmaf(k, -0x1.62e4p-1f, y);
+    r = __builtin_fmaf(k, -1.42860682030941723212e-6f, r);
+    float p = 1.0f / 5040.0f;
+    p = __builtin_fmaf(p, r, 1.0f / 720.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 120.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 24.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 6.0f);
+    p = __builtin_fmaf(p, r, 0.5f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    return __builtin_ldexpf(p, (int)k);
+}
+
+// u^2 + v^2 at a composited hit from the FP64 intersection of the FP32 ray
+// with the surfel's plane, rounded once to FP32.  The FP32 hit decision
+// loses the hit point's offset from the centre to cancellation when the
+// centre is many radii away (h = t d - q with |q| >> |h|); the kernel
+// value that weights the hit is taken from this exact evaluation instead.
+// Fixed operation order, scales by the stored FP32 reciprocals 1/s:
+//   den = d.n, q = p - o, t = (q.n)/den, h = t d - q,
+//   u = (h.t_u)(1/s_u), v = (h.t_v)(1/s_v), r2 = u u + v v.
+__device__ __forceinline__ float hit_r2_exact(const SurfRec &s, float ox, float oy, float oz, float dx, float dy,
+                                              float dz) {
+    const double nx = s.b.x, ny = s.b.y, nz = s.b.z;
+    const double qx = (double)s.a.x - (double)ox, qy = (double)s.a.y - (double)oy, qz = (double)s.a.z - (double)oz;
+    const double den = (double)dx * nx + (double)dy * ny + (double)dz * nz;
+    const double t = (qx * nx + qy * ny + qz * nz) / den;
+    const double hx = t * dx - qx, hy = t * dy - qy, hz = t * dz - qz;
+    const double u = (hx * s.c.x + hy * s.c.y + hz * s.c.z) * (double)s.a.w;
+    const double v = (hx * s.d.x + hy * s.d.y + hz * s.d.z) * (double)s.b.w;
+    return (float)(u * u + v * v);
+}
+
+// Kernel value at a hit: gamma = e^(-1.7 r2), App. E (product rounded once).
+__device__ __forceinline__ float kernel_gamma(float r2) { return exp_fx(-__fmul_rn(kKernelExp, r2)); }
+
+// Transmittance factor of one composited hit with opacity constant c and
+// kernel value g: e^(-c g), the product c g rounded once.
+__device__ __forceinline__ float transmit(float c, float g) { return exp_fx(-__fmul_rn(c, g)); }
+
 // Ray / box slab test with slack so that every hit point the FP32 surfel
 // test can accept lies inside the tested interval.
 __device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix, float hiy, float hiz, float ox,

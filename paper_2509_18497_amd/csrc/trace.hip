@@ -35,7 +35,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t g) {
 
 // Leaf visit of the sorted traversal: FP32 hit decision, then insertion
 // into the ascending k-buffer (keys (t bits, j), payload +-gamma with the
-// sign = front face).
+// sign = front face; gamma from the FP64 kernel argument).
 template <int KB>
 __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int s, uint32_t self, float ox, float oy,
                                            float oz, float dx, float dy, float dz, float t_eps, uint64_t last,
@@ -50,7 +50,7 @@ __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int 
     if (kk <= last) return;
     ++found;
     if (kk >= key[KB - 1]) return;
-    const float g = expf(-kKernelExp * r2);
+    const float g = kernel_gamma(hit_r2_exact(r, ox, oy, oz, dx, dy, dz));
     uint64_t x = kk;
     float y = front ? g : -g;
 #pragma unroll
@@ -134,10 +134,10 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
                 const uint32_t j = (uint32_t)key[k];
                 const float g = fabsf(gam[k]);
                 const bool front = gam[k] > 0.0f;
-                const float x = bv.c[j] * g;
+                const float x = __fmul_rn(bv.c[j], g);
                 const float alpha = -expm1f(-x);
                 on_hit(j, alpha, T, front, g, __uint_as_float((uint32_t)(key[k] >> 32)));
-                T *= expf(-x);
+                T = __fmul_rn(T, exp_fx(-x));
                 if (T < t_min) return T;
             }
         }
@@ -243,8 +243,11 @@ constexpr int kPoolRays = 1024;   // rays sorted and pooled per batch
 // pool through an LDS counter: neighbouring lanes trace rays that leave
 // close origins in close directions, and a lane whose ray ends early takes
 // the next one instead of idling until its wave's longest ray is done.
+// Three waves per SIMD (at most 168 VGPRs): without the bound the FP64
+// kernel argument in the leaf visit pushes the kernel to 181 VGPRs and two
+// waves, a third slower.
 template <int STK>
-__global__ void __launch_bounds__(256) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
                                                   int64_t s_begin, int64_t count, int group, int64_t nblocks,
                                                   int by_orig, uint2 *__restrict__ recs,
                                                   uint32_t *__restrict__ rcnt, int rcap, int *err) {
@@ -423,7 +426,7 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
                 }
                 if (probe == H) atomicOr(err, kErrTable);
             }
-            T *= expf(-x);
+            T = __fmul_rn(T, exp_fx(-x));
         }
     }
     __syncthreads();
@@ -721,7 +724,7 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
             const float gs = __uint_as_float(h.y);
             const float x = bv.c[h.x] * fabsf(gs);
             if (gs > 0.0f) W += row_hash_lookup(hk, hv, log2h, h.x) * (-expm1f(-x)) * T;
-            T *= expf(-x);
+            T = __fmul_rn(T, exp_fx(-x));
         }
         float P = 0.0f;
         T = 1.0f;
@@ -742,7 +745,7 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
                 const float dado = g * expf(c * (1.0f - g));
                 unsafeAtomicAdd(&gacc[h.x], (double)(dLda * dado));
             }
-            T *= expf(-x);
+            T = __fmul_rn(T, exp_fx(-x));
         }
     }
 }

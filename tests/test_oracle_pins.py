@@ -177,11 +177,13 @@ def test_transmittance_cut(orc):
             h = orc.trace_ray(sur, i, r, seed=1, t_eps=te, t_min=1e-3)
             m = h["n_comp"]
             T_after = h["T"] * (1.0 - h["alpha"])
+            # the cut is decided on the FP32 transmittance (D_stop), which
+            # follows the FP64 one to a few 1e-7 relative
             if m < len(h["t"]):
                 seen_cut += 1
-                assert T_after[m - 1] < 1e-3 and np.all(T_after[: m - 1] >= 1e-3)
+                assert T_after[m - 1] < 1e-3 * (1 + 1e-5) and np.all(T_after[: m - 1] >= 1e-3 * (1 - 1e-5))
             else:
-                assert np.all(T_after[: max(m - 1, 0)] >= 1e-3)
+                assert np.all(T_after[: max(m - 1, 0)] >= 1e-3 * (1 - 1e-5))
     assert seen_cut > 5
 
 
@@ -512,3 +514,35 @@ def test_raycast_furnace_bounds(orc):
     # on a sphere the cosine-weighted rays land uniformly by area: the
     # expected row sum is close to the transmittance-limited fill factor
     assert 0.4 < s.mean() < 0.9
+
+
+def test_exp_fx_is_within_three_ulp_of_exp(orc):
+    """D_stop's exp_fx against the FP64 exponential over its whole range
+    (dense grid plus the reduction boundaries k ln2 +- ln2/2)."""
+    L = orc.lib()
+    ys = np.concatenate([np.linspace(-80.0, 0.0, 200_001), -np.arange(0, 116) * np.log(2.0),
+                         -(np.arange(0, 115) + 0.5) * np.log(2.0)]).astype(np.float32)
+    ys = ys[ys > -80.0]
+    got = np.array([L.orc_exp_fx(float(y)) for y in ys[::7]], np.float64)
+    ref = np.exp(ys[::7].astype(np.float64))
+    ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
+    assert np.max(np.abs(got - ref) / ulp) <= 3.0
+    assert L.orc_exp_fx(0.0) == 1.0 and L.orc_exp_fx(-80.0) == 0.0 and L.orc_exp_fx(-100.0) == 0.0
+
+
+def test_cut_transmittance_tracks_fp64(orc):
+    """The FP32 transmittance of the cut (D_stop) follows the FP64 product
+    of (1 - alpha) to FP32 accuracy along every ray."""
+    worst = 0.0
+    for sur, step in ((scenes.random_frame_surfels(300, seed=8, extent=0.4, scale=(0.1, 0.25), opacity=(0.3, 0.99)),
+                       11),
+                      (scenes.make_config("fruit_bowl", n=20000).surfels, 1999)):
+        te = orc.default_t_eps(sur)
+        for i in range(0, sur["px"].shape[0], step):
+            for r in range(6):
+                h = orc.trace_ray(sur, i, r, seed=4, t_eps=te, t_min=0.0)
+                T64 = h["T"]
+                keep = T64 > 1e-30
+                if keep.any():
+                    worst = max(worst, float(np.max(np.abs(h["T32"][keep] - T64[keep]) / T64[keep])))
+    assert worst < 1e-5
