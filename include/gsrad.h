@@ -47,6 +47,7 @@ typedef int32_t gsrad_status;
 #define GSRAD_ESTATE (-6)    /* handle used in the wrong state                 */
 
 #define GSRAD_FP32 0         /* precision argument of gsrad_transport_solve    */
+#define GSRAD_BF16 1         /* dense BF16 matrix-core bounces (gsrad_ff_dense) */
 
 /*
  * Gaussian surfels, structure of arrays, device FP32, length n
@@ -173,6 +174,17 @@ gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, c
                                const float *val, gsrad_ff **ff, void *stream);
 
 /*
+ * Dense BF16 copies of F for gsrad_transport_solve with GSRAD_BF16 (the
+ * same operator B = E + rho F B of Eq. final-radiosity, evaluated as dense
+ * matrix products on the matrix cores).  F and F^T are stored as
+ * [Np][Np] BF16, Np = n rounded up to 256, each twice: the value rounded to
+ * BF16 (hi) and the rounded remainder (lo), 4 * Np^2 * 2 bytes in all
+ * (8.6 GB at n = 32768), owned by the handle.  Call again after F changes.
+ * GSRAD_ENOMEM if the copies do not fit.
+ */
+gsrad_status gsrad_ff_dense(gsrad_ff *ff, void *stream);
+
+/*
  * Direct light from isotropic point lights (Eq. forward rendering equation,
  * direct illumination; lights are infinitesimal emitters, Sec. 5.1):
  *   E_i,l,00,c = o_i a_i,c (2/sqrt(pi)) I_l max(0, n_i . w_il) / r_il^2 * T_il
@@ -191,9 +203,18 @@ gsrad_status gsrad_direct_light(const gsrad_bvh *bvh, const float *albedo, const
  *   B^(0) = E,   B^(k+1) = E + rho * (F B^(k)),   k = 0 .. n_bounces-1
  * B_out = B^(n_bounces) (n_bounces = 0 copies E: direct light only).  If
  * tape is non-NULL the iterates B^(0..n-1) are kept in *tape (created or
- * re-used) for gsrad_transport_backward.  precision must be GSRAD_FP32.
- * The accumulation order is fixed, so results are bit identical between
- * runs.
+ * re-used) for gsrad_transport_backward.  The accumulation order is fixed,
+ * so results are bit identical between runs.
+ *
+ * precision GSRAD_FP32: sparse products on the CSR F in FP32.
+ * precision GSRAD_BF16: dense products on the BF16 copies made by
+ *   gsrad_ff_dense, FP32 accumulation: the first n_bounces - 1 bounces use
+ *   F_hi and B rounded to BF16; the last one is the correction sweep
+ *   F B ~ F_hi B_hi + F_hi B_lo + F_lo B_hi (16-bit operands, FP32
+ *   accumulation), so that the result is B^(n) of the same recurrence with
+ *   only the first n - 1 applications in BF16.  Error vs FP64 within 1e-3
+ *   relative max-norm.  The tape then keeps F B^(k) (FP32) and B^(k)
+ *   (BF16) for the backward.
  */
 gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const float *E, int32_t n_lights,
                                    int32_t K, int32_t n_bounces, int32_t precision, float *B_out,
@@ -210,10 +231,25 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
  *                stored entry e = (i, j) (decay term of Eq. dl-dgeo-0)
  * grad_E [n][Lt][K][3], grad_rho [n][3], grad_F [nnz] in F's CSR order
  * (may be NULL).  rho must be the rho of the forward call.
+ * A tape made with GSRAD_BF16 runs the adjoint of that forward (its first
+ * step the correction sweep on F^T, the others BF16 on F^T) and forms
+ * grad_F as the dense product sum_k (rho lambda^(k+1)) (B^(k))^T on the
+ * matrix cores (both operands split into BF16 hi + lo, the three leading
+ * products accumulated in FP32: the sum cancels, so plain BF16 operands
+ * would leave errors near 4e-3) into an [n][n] FP32
+ * array held by the tape (gsrad_tape_grad_F_dense copies it out), from
+ * which the stored entries are copied to grad_F.
  */
 gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape, const float *rho,
                                       const float *grad_B, float *grad_E, float *grad_rho, float *grad_F,
                                       void *stream);
+
+/*
+ * Copy of the dense dL/dF [n][n] FP32 (row-major, caller-owned device
+ * buffer) computed by the last gsrad_transport_backward with grad_F != NULL
+ * on a GSRAD_BF16 tape; GSRAD_ESTATE if there is none.
+ */
+gsrad_status gsrad_tape_grad_F_dense(const gsrad_tape *tape, float *grad_F_out, void *stream);
 
 /*
  * Opacity and albedo gradients (Eq. dl-dgeo-0, decay term, restricted to

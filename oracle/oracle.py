@@ -287,7 +287,7 @@ def bounce(F, rho_arr, E, n_bounces: int, keep_tape: bool = False):
     return (B.reshape(shape), tape) if keep_tape else B.reshape(shape)
 
 
-def adjoint(F, rho_arr, tape, g, chunk: int = 4096, want_grad_F: bool = True):
+def adjoint(F, rho_arr, tape, g, chunk: int = 4096, want_grad_F: bool = True, dense_grad_F: bool = False):
     """Exact adjoint of ``bounce`` for a loss with dL/dB^(n) = g:
       lambda^(n) = g,  lambda^(k) = F^T (rho * lambda^(k+1))   (Eq. final_dL_dE,
                                                                division-free)
@@ -297,7 +297,9 @@ def adjoint(F, rho_arr, tape, g, chunk: int = 4096, want_grad_F: bool = True):
       grad_F_ij  = sum_{k<n} <rho_i * lambda_i^(k+1), B_j^(k)>             (decay
                    term of Eq. dl-dgeo-0 per recorded pair (i, j))
     grad_F is returned aligned with F's CSR entries (F.indices order), or
-    as None when not wanted."""
+    as None when not wanted.  With dense_grad_F the same sum is returned for
+    every pair (i, j) as an [N][N] array (the gradient with respect to a
+    dense F) in place of the stored-entry vector."""
     shape = np.shape(g)
     N = shape[0]
     lam = np.asarray(g, np.float64).reshape(N, -1).copy()
@@ -308,17 +310,22 @@ def adjoint(F, rho_arr, tape, g, chunk: int = 4096, want_grad_F: bool = True):
     grad_E = lam.copy()
     grad_rho = np.zeros((N, 3))
     gF = np.zeros(F.nnz)
+    gFd = np.zeros((N, N)) if dense_grad_F else None
     rows = np.repeat(np.arange(N), np.diff(F.indptr))
     for k in range(len(tape) - 1, -1, -1):
         Bk = tape[k]
         Q = F @ Bk
         grad_rho += (lam * Q).reshape(N, -1, 3).sum(axis=1)
         rl = rc * lam
-        for s in range(0, F.nnz if want_grad_F else 0, chunk * 64):
+        if dense_grad_F:
+            gFd += rl @ Bk.T
+        for s in range(0, F.nnz if (want_grad_F and not dense_grad_F) else 0, chunk * 64):
             e = min(F.nnz, s + chunk * 64)
             gF[s:e] += np.einsum("ec,ec->e", rl[rows[s:e]], Bk[F.indices[s:e]])
         lam = FT @ rl
         grad_E += lam
+    if dense_grad_F:
+        return grad_E.reshape(shape), grad_rho, gFd
     return grad_E.reshape(shape), grad_rho, (gF if want_grad_F else None)
 
 

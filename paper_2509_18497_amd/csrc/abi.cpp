@@ -14,6 +14,7 @@
 #include "bvh_build.h"
 #include "gsrad_internal.h"
 #include "trace_api.h"
+#include "dense_api.h"
 
 namespace gsrad {
 
@@ -168,6 +169,11 @@ struct gsrad_ff {
     DevBuf recs, rcnt;
     // scratch of the ray-cast path
     DevBuf slab, ell_col, ell_val, row_len, err, scan_temp;
+    // dense BF16 copies (gsrad_ff_dense): F and F^T, hi and lo parts
+    bool has_dense = false;
+    int64_t Np = 0;
+    DevBuf d_hi, d_lo, dt_hi, dt_lo;
+    DevBuf xa, xb, xl;   // transposed BF16 operands of the dense products
     Csr csr() const {
         Csr c;
         c.n = n;
@@ -188,7 +194,7 @@ struct gsrad_ff {
     }
     ~gsrad_ff() {
         for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col,
-                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt})
+                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl})
             b->release();
     }
 };
@@ -196,13 +202,17 @@ struct gsrad_ff {
 struct gsrad_tape {
     int64_t n = 0;
     int C = 0, nb = 0, Lt = 0, K = 0;
+    int precision = GSRAD_FP32;
     const gsrad_ff *ff = nullptr;
     DevBuf B, L, lam0, pp;
+    // GSRAD_BF16: Q^(k) = F B^(k) (FP32 [nb][n][C]), B^(k) in BF16 as
+    // [Np][Kp] rows (k-major columns), the adjoint's BF16 rows
+    // rho lambda^(k+1), its FP32 iterates, and the dense dL/dF [n][n]
+    int64_t Kp = 0;
+    bool has_G = false;
+    DevBuf Q, bb, bb_lo, pb, pb_lo, lam_a, lam_b, G;
     ~gsrad_tape() {
-        B.release();
-        L.release();
-        lam0.release();
-        pp.release();
+        for (DevBuf *b : {&B, &L, &lam0, &pp, &Q, &bb, &bb_lo, &pb, &pb_lo, &lam_a, &lam_b, &G}) b->release();
     }
 };
 
@@ -460,6 +470,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     h->nnz = nnz;
     h->max_row = flags[1];
     h->has_t = false;
+    h->has_dense = false;
     h->bvh = bvh;
     h->R = R;
     h->topk = p->topk;
@@ -536,8 +547,28 @@ gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, c
     h->nnz = nnz;
     h->max_row = mx;
     h->has_t = false;
+    h->has_dense = false;
     h->bvh = nullptr;
     *ff = h;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_ff_dense(gsrad_ff *ff, void *stream) {
+    if (!ff) return einval("gsrad_ff_dense: null handle");
+    if (ff->n < 1) return einval("gsrad_ff_dense: empty operator");
+    hipStream_t st = S(stream);
+    const int64_t Np = dense_pad(ff->n);
+    const size_t bytes = (size_t)Np * (size_t)Np * sizeof(__bf16);
+    ff->has_dense = false;
+    for (DevBuf *b : {&ff->d_hi, &ff->d_lo, &ff->dt_hi, &ff->dt_lo}) {
+        GS_TRY(b->ensure(bytes, "dense BF16 operator"));
+        GS_TRY(check_hip(hipMemsetAsync(b->p, 0, bytes, st), "dense operator zero"));
+    }
+    ProfScope ps("dense_scatter", st);
+    GS_TRY(launch_dense_scatter(ff->csr(), Np, ff->d_hi.as<__bf16>(), ff->d_lo.as<__bf16>(), ff->dt_hi.as<__bf16>(),
+                                ff->dt_lo.as<__bf16>(), st));
+    ff->Np = Np;
+    ff->has_dense = true;
     return GSRAD_OK;
 }
 
@@ -553,6 +584,146 @@ gsrad_status gsrad_direct_light(const gsrad_bvh *bvh, const float *albedo, const
     return launch_direct(bvh->dev(), albedo, light_pos, light_I, n_lights, K, E_out, h->height.as<int>() + 4, st);
 }
 
+namespace {
+
+// Forward bounces on the dense BF16 copies: n_bounces - 1 BF16 products,
+// then the correction sweep (split operands).  The transposed BF16 operand
+// of B^(k) alternates between two buffers; the low part is made only for
+// the input of the correction sweep.
+gsrad_status dense_solve(const gsrad_ff *ff, const float *rho, const float *E, int C, int nb, float *B_out,
+                         gsrad_tape *tp, hipStream_t st) {
+    const int64_t n = ff->n, Np = ff->Np, Cp = dense_pad(C);
+    const size_t xbytes = (size_t)Cp * Np * sizeof(__bf16);
+    gsrad_ff *m = const_cast<gsrad_ff *>(ff);
+    // the operand buffers are scratch of the handle (like the FP32 ping-pong)
+    DevBuf &xa = m->xa, &xb = m->xb, &xl = m->xl;
+    for (DevBuf *b : {&xa, &xb, &xl}) {
+        GS_TRY(b->ensure(xbytes, "BF16 bounce operand"));
+        GS_TRY(check_hip(hipMemsetAsync(b->p, 0, xbytes, st), "operand zero"));
+    }
+    int64_t Kp = 0;
+    if (tp) {
+        Kp = ((int64_t)nb * C + 63) / 64 * 64;
+        GS_TRY(tp->Q.ensure((size_t)nb * n * C * sizeof(float), "F B tape"));
+        for (DevBuf *b : {&tp->bb, &tp->bb_lo}) {
+            GS_TRY(b->ensure((size_t)Np * Kp * sizeof(__bf16), "BF16 B tape"));
+            GS_TRY(check_hip(hipMemsetAsync(b->p, 0, (size_t)Np * Kp * sizeof(__bf16), st), "B tape zero"));
+        }
+        GS_TRY(launch_to_bf16_rows(E, nullptr, n, C, tp->bb.as<__bf16>(), tp->bb_lo.as<__bf16>(), Kp, 0, st));
+        tp->Kp = Kp;
+    }
+    GS_TRY(launch_to_bf16_t(E, nullptr, n, C, xa.as<__bf16>(), nb == 1 ? xl.as<__bf16>() : nullptr, Np, st));
+    for (int k = 0; k < nb; ++k) {
+        DenseBounce a;
+        a.f_hi = ff->d_hi.as<__bf16>();
+        a.f_lo = ff->d_lo.as<__bf16>();
+        a.ld = Np;
+        a.x_hi = (k & 1 ? xb : xa).as<__bf16>();
+        a.x_lo = xl.as<__bf16>();
+        a.ldx = Np;
+        a.split = k == nb - 1;
+        a.E = E;
+        a.rho = rho;
+        a.n = n;
+        a.C = C;
+        a.Bout = k == nb - 1 ? B_out : nullptr;
+        a.Q = tp ? tp->Q.as<float>() + (size_t)k * n * C : nullptr;
+        a.xt_hi = k < nb - 1 ? (k & 1 ? xa : xb).as<__bf16>() : nullptr;
+        a.xt_lo = k == nb - 2 ? xl.as<__bf16>() : nullptr;
+        a.bb = tp && k + 1 < nb ? tp->bb.as<__bf16>() : nullptr;
+        a.bb_lo = tp && k + 1 < nb ? tp->bb_lo.as<__bf16>() : nullptr;
+        a.ldbb = Kp;
+        a.boff = (int64_t)(k + 1) * C;
+        ProfScope ps(a.split ? "dense_bounce_fix" : "dense_bounce", st);
+        GS_TRY(launch_dense_bounce(a, st));
+    }
+    return GSRAD_OK;
+}
+
+// Adjoint of dense_solve: the first step (k = nb-1) on the split F^T, the
+// others BF16; dL/drho from the tape's F B^(k); the dense dL/dF product
+// when grad_F is wanted.
+gsrad_status dense_backward(const gsrad_ff *ff, gsrad_tape *tp, const float *rho, const float *grad_B,
+                            float *grad_E, float *grad_rho, float *grad_F, hipStream_t st) {
+    const int64_t n = ff->n, Np = ff->Np;
+    const int C = tp->C, nb = tp->nb;
+    const int64_t Cp = dense_pad(C), Kp = tp->Kp;
+    const size_t xbytes = (size_t)Cp * Np * sizeof(__bf16);
+    const size_t row_bytes = (size_t)n * C * sizeof(float);
+    gsrad_ff *m = const_cast<gsrad_ff *>(ff);
+    for (DevBuf *b : {&m->xa, &m->xb, &m->xl}) {
+        GS_TRY(b->ensure(xbytes, "BF16 adjoint operand"));
+        GS_TRY(check_hip(hipMemsetAsync(b->p, 0, xbytes, st), "operand zero"));
+    }
+    GS_TRY(tp->lam_a.ensure(row_bytes, "adjoint iterate"));
+    GS_TRY(tp->lam_b.ensure(row_bytes, "adjoint iterate"));
+    const bool want_F = grad_F != nullptr;
+    if (want_F) {
+        for (DevBuf *b : {&tp->pb, &tp->pb_lo}) {
+            GS_TRY(b->ensure((size_t)Np * Kp * sizeof(__bf16), "BF16 adjoint tape"));
+            GS_TRY(check_hip(hipMemsetAsync(b->p, 0, (size_t)Np * Kp * sizeof(__bf16), st), "adjoint tape zero"));
+        }
+        GS_TRY(launch_to_bf16_rows(grad_B, rho, n, C, tp->pb.as<__bf16>(), tp->pb_lo.as<__bf16>(), Kp,
+                                   (int64_t)(nb - 1) * C, st));
+    }
+    float *gr = grad_rho;
+    if (gr) {
+        GS_TRY(check_hip(hipMemsetAsync(gr, 0, (size_t)n * 12, st), "grad_rho zero"));
+        GS_TRY(launch_grad_rho_acc(grad_B, tp->Q.as<float>() + (size_t)(nb - 1) * n * C, n, C, gr, st));
+    }
+    GS_TRY(launch_to_bf16_t(grad_B, rho, n, C, m->xa.as<__bf16>(), m->xl.as<__bf16>(), Np, st));
+    for (int k = nb - 1, s = 0; k >= 0; --k, ++s) {
+        DenseAdjoint a;
+        a.ft_hi = ff->dt_hi.as<__bf16>();
+        a.ft_lo = ff->dt_lo.as<__bf16>();
+        a.ld = Np;
+        a.y_hi = (s & 1 ? m->xb : m->xa).as<__bf16>();
+        a.y_lo = m->xl.as<__bf16>();
+        a.ldx = Np;
+        a.split = k == nb - 1;
+        a.rho = rho;
+        a.n = n;
+        a.C = C;
+        a.lam = (s & 1 ? tp->lam_b : tp->lam_a).as<float>();
+        a.gE = grad_E;
+        a.yt_hi = k >= 1 ? (s & 1 ? m->xa : m->xb).as<__bf16>() : nullptr;
+        a.p = want_F && k >= 1 ? tp->pb.as<__bf16>() : nullptr;
+        a.p_lo = want_F && k >= 1 ? tp->pb_lo.as<__bf16>() : nullptr;
+        a.ldp = Kp;
+        a.poff = (int64_t)(k - 1) * C;
+        {
+            ProfScope ps(a.split ? "dense_adjoint_fix" : "dense_adjoint", st);
+            GS_TRY(launch_dense_adjoint(a, st));
+        }
+        if (gr && k >= 1) GS_TRY(launch_grad_rho_acc(a.lam, tp->Q.as<float>() + (size_t)(k - 1) * n * C, n, C, gr, st));
+    }
+    tp->has_G = false;
+    if (want_F) {
+        GS_TRY(tp->G.ensure((size_t)n * n * sizeof(float), "dense dL/dF"));
+        {
+            ProfScope ps("dense_grad_F", st);
+            GS_TRY(launch_dense_grad_F(tp->pb.as<__bf16>(), tp->pb_lo.as<__bf16>(), tp->bb.as<__bf16>(),
+                                       tp->bb_lo.as<__bf16>(), Kp, Kp, n, Np, tp->G.as<float>(), n, st));
+        }
+        GS_TRY(launch_gather_csr(ff->csr(), tp->G.as<float>(), n, grad_F, st));
+        tp->has_G = true;
+    }
+    return GSRAD_OK;
+}
+
+}  // namespace
+
+gsrad_status gsrad_tape_grad_F_dense(const gsrad_tape *tape, float *grad_F_out, void *stream) {
+    if (!tape || !grad_F_out) return einval("gsrad_tape_grad_F_dense: null argument");
+    if (!tape->has_G) {
+        set_error("gsrad_tape_grad_F_dense: no dense dL/dF on this tape");
+        return GSRAD_ESTATE;
+    }
+    return check_hip(hipMemcpyAsync(grad_F_out, tape->G.p, (size_t)tape->n * tape->n * sizeof(float),
+                                    hipMemcpyDeviceToDevice, S(stream)),
+                     "dense dL/dF copy");
+}
+
 gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const float *E, int32_t n_lights, int32_t K,
                                    int32_t n_bounces, int32_t precision, float *B_out, gsrad_tape **tape,
                                    void *stream) {
@@ -560,7 +731,10 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
     if (n_lights < 1) return einval("gsrad_transport_solve: n_lights must be >= 1");
     if (!valid_K(K)) return einval("gsrad_transport_solve: K must be 1, 4, 9 or 16");
     if (n_bounces < 0 || n_bounces > 4096) return einval("gsrad_transport_solve: n_bounces must be in [0, 4096]");
-    if (precision != GSRAD_FP32) return einval("gsrad_transport_solve: only GSRAD_FP32 is supported");
+    if (precision != GSRAD_FP32 && precision != GSRAD_BF16)
+        return einval("gsrad_transport_solve: precision must be GSRAD_FP32 or GSRAD_BF16");
+    if (precision == GSRAD_BF16 && !ff->has_dense)
+        return einval("gsrad_transport_solve: GSRAD_BF16 needs the dense copies of gsrad_ff_dense");
     hipStream_t st = S(stream);
     const int C = n_lights * K * 3;
     const int64_t n = ff->n;
@@ -577,7 +751,9 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
     };
     gsrad_status e;
     const Csr F = ff->csr();
-    if (n_bounces == 0) {
+    if (precision == GSRAD_BF16 && n_bounces > 0) {
+        if ((e = dense_solve(ff, rho, E, C, n_bounces, B_out, tp, st)) != GSRAD_OK) return fail(e);
+    } else if (n_bounces == 0) {
         if ((e = check_hip(hipMemcpyAsync(B_out, E, row_bytes, hipMemcpyDeviceToDevice, st), "solve copy")) !=
             GSRAD_OK)
             return fail(e);
@@ -610,6 +786,8 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
         tp->nb = n_bounces;
         tp->Lt = n_lights;
         tp->K = K;
+        tp->precision = precision;
+        tp->has_G = false;
         tp->ff = ff;
         *tape = tp;
     }
@@ -633,6 +811,10 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
         if (grad_F && ff->nnz > 0)
             GS_TRY(check_hip(hipMemsetAsync(grad_F, 0, (size_t)ff->nnz * 4, st), "grad_F zero"));
         return GSRAD_OK;
+    }
+    if (tape->precision == GSRAD_BF16) {
+        if (!ff->has_dense) return einval("gsrad_transport_backward: the dense copies of F are gone");
+        return dense_backward(ff, tp, rho, grad_B, grad_E, grad_rho, grad_F, st);
     }
     {
         ProfScope ps("transpose", st);

@@ -18,14 +18,16 @@ LIB_PATH = os.path.join(HERE, "libgsrad.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENAN, EOVERFLOW, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP32 = 0
+BF16 = 1
 FF_NO_RECORDS = 1
 SOA = ("px", "py", "pz", "tux", "tuy", "tuz", "tvx", "tvy", "tvz", "nx", "ny", "nz", "su", "sv", "opacity")
 
 EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_info", "gsrad_bvh_height",
            "gsrad_effective_area", "gsrad_reflectance", "gsrad_form_factors", "gsrad_ff_info", "gsrad_ff_view",
-           "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_direct_light", "gsrad_transport_solve",
-           "gsrad_transport_backward", "gsrad_opacity_backward", "gsrad_ray_hits", "gsrad_check", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy",
-           "gsrad_ff_destroy", "gsrad_tape_destroy")
+           "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
+           "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
+           "gsrad_check", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
+           "gsrad_tape_destroy")
 
 
 class GsradError(RuntimeError):
@@ -69,6 +71,8 @@ def lib():
             "gsrad_ff_view": ([vp, pvp, pvp, pvp], i32),
             "gsrad_ff_copy": ([vp, vp, vp, vp, vp], i32),
             "gsrad_ff_from_csr": ([i64, i64, vp, vp, vp, pvp, vp], i32),
+            "gsrad_ff_dense": ([vp, vp], i32),
+            "gsrad_tape_grad_F_dense": ([vp, vp, vp], i32),
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
             "gsrad_transport_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
@@ -228,16 +232,32 @@ def direct_light(bvh: BVH, albedo: torch.Tensor, light_pos: torch.Tensor, light_
     return E
 
 
+def ff_dense(ff: FF, stream=None) -> FF:
+    """Make the dense BF16 copies of F (and F^T) used by precision=BF16."""
+    _check(lib().gsrad_ff_dense(ff.h, _stream(stream)), "gsrad_ff_dense")
+    return ff
+
+
+def tape_grad_F_dense(tape: Tape, n: int, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The dense dL/dF [n, n] of the last backward on a BF16 tape."""
+    G = out if out is not None else torch.empty((n, n), dtype=torch.float32, device="cuda")
+    _check(lib().gsrad_tape_grad_F_dense(tape.h, _ptr(G, name="grad_F_dense"), _stream(stream)),
+           "gsrad_tape_grad_F_dense")
+    return G
+
+
 def transport_solve(ff: FF, rho: torch.Tensor, E: torch.Tensor, n_bounces: int, tape: Optional[Tape] = None,
-                    keep_tape: bool = True, out: Optional[torch.Tensor] = None, stream=None):
+                    keep_tape: bool = True, out: Optional[torch.Tensor] = None, stream=None, precision: int = FP32):
     """B = E + rho*(F B) iterated n_bounces times from B^(0) = E.  E is
-    [n, Lt, K, 3].  Returns (B, tape)."""
+    [n, Lt, K, 3].  precision FP32 (sparse CSR products) or BF16 (dense
+    matrix-core products on the copies made by ff_dense).  Returns (B, tape)."""
     if E.dim() != 4 or E.shape[3] != 3:
         raise ValueError("E must be [n, Lt, K, 3]")
     n, Lt, K = int(E.shape[0]), int(E.shape[1]), int(E.shape[2])
     B = out if out is not None else torch.empty_like(E)
     tp = tape if tape is not None else (Tape() if keep_tape else None)
-    _check(lib().gsrad_transport_solve(ff.h, _ptr(rho, name="rho"), _ptr(E, name="E"), Lt, K, int(n_bounces), FP32,
+    _check(lib().gsrad_transport_solve(ff.h, _ptr(rho, name="rho"), _ptr(E, name="E"), Lt, K, int(n_bounces),
+                                       int(precision),
                                        _ptr(B, name="B"), ctypes.byref(tp.h) if tp is not None else None,
                                        _stream(stream)), "gsrad_transport_solve")
     return B, tp

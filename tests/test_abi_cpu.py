@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2509_18497_amd", "libgsrad.so")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gsrad_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gsrad_[A-Za-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")

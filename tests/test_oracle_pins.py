@@ -437,6 +437,34 @@ def test_adjoint_matches_central_differences(orc):
         assert abs(fd - gE[idx]) < 1e-6 * max(1.0, abs(fd))
 
 
+def test_dense_grad_F_matches_central_differences(orc):
+    """The dense dL/dF (every pair, stored or not) against central
+    differences of the loss in F_ij, and equal to the stored-entry vector on
+    the stored entries."""
+    n, Lt, K, nb = 30, 1, 4, 4
+    F = _random_operator(n, 6, density=0.25)
+    rho = np.random.default_rng(19).uniform(0.1, 0.9, (n, 3))
+    E = np.random.default_rng(20).uniform(0, 1, (n, Lt, K, 3))
+    g = np.random.default_rng(21).standard_normal((n, Lt, K, 3))
+    B, tape = orc.bounce(F, rho, E, nb, keep_tape=True)
+    _, _, gF = orc.adjoint(F, rho, tape, g)
+    gE, grho, G = orc.adjoint(F, rho, tape, g, dense_grad_F=True)
+    assert G.shape == (n, n)
+    rows = np.repeat(np.arange(n), np.diff(F.indptr))
+    assert np.allclose(G[rows, F.indices], gF, rtol=1e-12, atol=1e-14)
+    Fd = F.toarray()
+    L = lambda Fm: np.sum(g * orc.bounce(sp.csr_matrix(Fm), rho, E, nb))
+    rng = np.random.default_rng(22)
+    h = 1e-6
+    for _ in range(20):
+        i, j = rng.integers(n), rng.integers(n)
+        Fp, Fm = Fd.copy(), Fd.copy()
+        Fp[i, j] += h
+        Fm[i, j] -= h
+        fd = (L(Fp) - L(Fm)) / (2 * h)
+        assert abs(fd - G[i, j]) < 1e-6 * max(1.0, abs(fd))
+
+
 def test_paper_brdf_gradient_closed_form_at_fixed_point(orc):
     """Eq. final-dl-dbrdf: at the fixed point dL/df = dL/dE * (B - E) / f,
     per colour summed over coefficients and lights."""
