@@ -69,6 +69,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=24)
+    ap.add_argument("--workload", default="fruit_bowl", choices=["fruit_bowl", "multi_light"],
+                    help="fruit_bowl: the 100k sparse path (default); multi_light: the 32k box room with 100 "
+                         "lights on the dense BF16 path")
+    ap.add_argument("--fp32-lights", type=int, default=10,
+                    help="multi_light: lights timed on the plain FP32 per-light path (scaled to all lights)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain FP32 copy kernel of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -77,8 +82,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this path "
-              "is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this path is not sharded over "
+              "several GPUs.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -87,6 +92,8 @@ def main():
     import scenes
 
     torch.cuda.set_device(0)
+    if args.workload == "multi_light":
+        return multi_light(args, g, scenes, torch, np)
     sc = scenes.make_config("fruit_bowl", n=args.n)
     N, R, K, nb, topk, Lt = sc.n, sc.R, sc.K, sc.n_bounces, sc.topk, sc.n_lights
     dev = torch.device("cuda")
@@ -326,6 +333,193 @@ def cpu_baseline(sc, n_recv, nnz, np):
                       f"light, brute force) scaled x{sc.n / n_recv:.0f}, plus bounces+adjoint on a {m}-row operator "
                       f"with {sc.topk} entries/row scaled to nnz={nnz}",
             "seconds_measured": t_ff + t_ob + t_dl + t_lin * F.nnz / max(nnz, 1)}
+
+
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def multi_light(args, g, scenes, torch, np):
+    """The 32,768-surfel box room lit by 100 point lights: one F, 100
+    right-hand sides (C = 100 * 9 * 3 = 2700 columns).  A step is the whole
+    path: BVH, ray-cast F (256 rays, all entries), dense BF16 copies, direct
+    light, 8 bounces on the matrix cores (7 BF16 + the correction sweep) and
+    the backward with the dense dL/dF.  The plain FP32 per-light path (one
+    sparse solve and backward per light) is timed on a sample of lights."""
+    sc = scenes.make_config("multi_light")
+    N, R, K, nb, Lt = sc.n, sc.R, sc.K, sc.n_bounces, sc.n_lights
+    dev = torch.device("cuda")
+    sur = {k: torch.from_numpy(v).to(dev) for k, v in sc.surfels.items()}
+    alb = torch.from_numpy(sc.albedo).to(dev)
+    lpos = torch.from_numpy(sc.light_pos).to(dev)
+    lI = torch.from_numpy(sc.light_I).to(dev)
+    gB = torch.from_numpy(scenes.seeded_array((N, Lt, K, 3), seed=99, lo=-1e-3, hi=1e-3)).to(dev)
+    E = torch.empty((N, Lt, K, 3), dtype=torch.float32, device=dev)
+    B = torch.empty_like(E)
+    state = {"bvh": None, "ff": None, "tape": None}
+
+    def step():
+        bvh = g.build_bvh(sur, state["bvh"])
+        state["bvh"] = bvh
+        rho = g.reflectance(bvh, alb)
+        ff = g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, topk=0, ff=state["ff"], records=False)
+        state["ff"] = ff
+        g.ff_dense(ff)
+        g.direct_light(bvh, alb, lpos, lI, K, out=E)
+        _, tape = g.transport_solve(ff, rho, E, nb, tape=state["tape"], out=B, precision=g.BF16)
+        state["tape"] = tape
+        gE, grho, gF = g.transport_backward(ff, tape, rho, gB)
+        state["rho"] = rho
+        return gE, grho, gF
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.gsrad.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.gsrad.profile_report()
+    g.gsrad.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    ff = state["ff"]
+    _, nnz = ff.info()
+
+    def avg(name):
+        return prof[name]["total_ms"] / args.steps if name in prof else 0.0
+
+    t_transport = sum(avg(k) for k in ("dense_bounce", "dense_bounce_fix", "dense_adjoint", "dense_adjoint_fix",
+                                       "dense_grad_F"))
+    # plain FP32: one sparse solve + backward per light, on a sample of lights
+    rho = state["rho"]
+    nl = max(1, min(args.fp32_lights, Lt))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for l in range(nl):
+        El = E[:, l:l + 1].contiguous()
+        gl = gB[:, l:l + 1].contiguous()
+        _, tl = g.transport_solve(ff, rho, El, nb)
+        g.transport_backward(ff, tl, rho, gl)
+    torch.cuda.synchronize()
+    t_fp32 = (time.perf_counter() - t2) * Lt / nl
+    C = Lt * K * 3
+    Np = (N + 255) // 256 * 256
+    Cp = (C + 255) // 256 * 256
+    flop_bounce = 2.0 * N * N * C             # one product F B (algorithmic, dense)
+    flop_gF = 2.0 * N * N * nb * C            # dense dL/dF
+    phases = {k: v["total_ms"] / args.steps for k, v in prof.items()}
+    dom = max(("dense_grad_F", "dense_bounce"), key=lambda k: phases.get(k, 0.0))
+    dom_ms = prof[dom]["avg_ms"]
+    work = flop_gF if dom == "dense_grad_F" else flop_bounce
+    achieved = work / (dom_ms * 1e-3) / 1e12
+    issued = (3.0 * 2 * Np * Np * ((nb * C + 63) // 64 * 64)) if dom == "dense_grad_F" else 2.0 * Np * Np * Cp
+    roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+            "work_per_launch": {"algorithmic_flop": work, "issued_mfma_flop": issued,
+                                "issued_TFLOPs": issued / (dom_ms * 1e-3) / 1e12,
+                                "note": "dL/dF runs on split hi+lo operands: three BF16 products" if
+                                dom == "dense_grad_F" else "one BF16 product, padded to 256-wide tiles"}}
+    if "dense_bounce" in prof:
+        bt = prof["dense_bounce"]["avg_ms"]
+        roof["dense_bounce"] = {"avg_ms": bt, "achieved": flop_bounce / (bt * 1e-3) / 1e12,
+                                "frac": flop_bounce / (bt * 1e-3) / 1e12 / PEAK_BF16_TFLOPS}
+    result = {
+        "metric": "fwd+bwd transport solves/s, 100 lights as right-hand sides of one F (dense BF16 MFMA)",
+        "value": 1e3 / ms,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"box room: {N} surfels, {Lt} point lights on a radius-3 sphere, R={R}, all F "
+                               f"entries, SH K={K}, {nb} bounces (7 BF16 + correction sweep), fwd+bwd with dense "
+                               f"dL/dF",
+                   "surfels": N, "lights": Lt, "K": K, "bounces": nb, "columns": C, "nnz": nnz},
+        "transport_ms": t_transport,
+        "transport_solves_per_s": 1e3 / t_transport if t_transport > 0 else None,
+        "fp32_per_light_fwd_bwd_ms": t_fp32 * 1e3,
+        "fp32_lights_timed": nl,
+        "speedup_vs_fp32_per_light": (t_fp32 * 1e3) / t_transport if t_transport > 0 else None,
+        "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())},
+        "roofline": roof,
+    }
+    if not args.no_check:
+        # the dense launch does not depend on the operator's sparsity, so the
+        # check uses a shorter seeded row (256 entries) to keep the oracle fast
+        result["err_vs_fp64"] = dense_slice_errors(g, torch, np, N, 256, Lt, K, nb)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = dense_cpu_baseline(np, N, int(nnz // N), Lt, K, nb)
+    print(json.dumps(result))
+
+
+def _slice_inputs(scenes, np, N, Lt, K, lights):
+    E = np.zeros((N, Lt, K, 3), np.float32)
+    gB = np.zeros((N, Lt, K, 3), np.float32)
+    Es = scenes.seeded_array((N, len(lights), K, 3), seed=2)
+    gBs = scenes.seeded_array((N, len(lights), K, 3), seed=3, lo=-1, hi=1)
+    E[:, lights] = Es
+    gB[:, lights] = gBs
+    return E, gB, Es, gBs
+
+
+def dense_slice_errors(g, torch, np, N, k, Lt, K, nb, lights=(0, 57)):
+    """BF16 results of the full launch (N rows, Lt*K*3 columns) on a seeded
+    operator with k entries per row, E and grad_B non-zero for two lights
+    only: the transport is separable over columns, so the oracle's
+    FP64 run on those lights' columns gives B, dL/dE, dL/drho and dL/dF at
+    the stored entries of the whole launch."""
+    import oracle
+    import scenes
+    import scipy.sparse as sp
+    lights = list(lights)
+    rp, c, v = scenes.seeded_csr(N, k, seed=41)
+    F = sp.csr_matrix((v.astype(np.float64), c, rp), shape=(N, N))
+    rho = scenes.seeded_array((N, 3), seed=1, lo=0.1, hi=0.9)
+    E, gB, Es, gBs = _slice_inputs(scenes, np, N, Lt, K, lights)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()   # noqa: E731
+    ff = g.ff_dense(g.ff_from_csr(d(rp), d(c), d(v)))
+    B, tape = g.transport_solve(ff, d(rho), d(E), nb, precision=g.BF16)
+    gE, gr, gF = g.transport_backward(ff, tape, d(rho), d(gB))
+    B, gE, gr, gF = (x.cpu().numpy() for x in (B, gE, gr, gF))
+    Bo, tp = oracle.bounce(F, rho, Es, nb, keep_tape=True)
+    gEo, gro, gFo = oracle.adjoint(F, rho, tp, gBs)
+
+    def rel(x, ref):
+        return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+    return {"B": rel(B[:, lights], Bo), "grad_E": rel(gE[:, lights], gEo), "grad_rho": rel(gr, gro),
+            "grad_F": rel(gF, gFo),
+            "operator": f"seeded {N}-row CSR, {F.nnz} entries, lights {lights} of {Lt} non-zero"}
+
+
+def dense_cpu_baseline(np, N, k, Lt, K, nb):
+    """The FP64 oracle's bounces + adjoint (with dL/dF at the stored entries)
+    for one SH coefficient of one light (3 columns) on a seeded operator of
+    the workload's shape, scaled to all Lt*K*3 columns."""
+    import oracle
+    import scenes
+    import scipy.sparse as sp
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rp, c, v = scenes.seeded_csr(N, k, seed=41)
+    F = sp.csr_matrix((v.astype(np.float64), c, rp), shape=(N, N))
+    rho = scenes.seeded_array((N, 3), seed=1, lo=0.1, hi=0.9)
+    Es = scenes.seeded_array((N, 1, 1, 3), seed=2)
+    gBs = scenes.seeded_array((N, 1, 1, 3), seed=3, lo=-1, hi=1)
+    t0 = time.perf_counter()
+    Bo, tp = oracle.bounce(F, rho, Es, nb, keep_tape=True)
+    oracle.adjoint(F, rho, tp, gBs)
+    t = time.perf_counter() - t0
+    scale = Lt * K
+    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 bounces + adjoint for 3 of {Lt * K * 3} columns on a seeded {N}-row operator with "
+                      f"{F.nnz} entries (scipy sparse, one thread), scaled x{scale}",
+            "seconds_measured": t}
 
 
 if __name__ == "__main__":
