@@ -96,7 +96,8 @@ typedef struct gsrad_ff_params {
 
 typedef struct gsrad_bvh gsrad_bvh;   /* prepared surfels + LBVH            */
 typedef struct gsrad_ff gsrad_ff;     /* sparse transport matrix F (CSR)    */
-typedef struct gsrad_tape gsrad_tape; /* forward iterates for the backward  */
+typedef struct gsrad_tape gsrad_tape;   /* forward iterates for the backward  */
+typedef struct gsrad_batch gsrad_batch; /* scenes sharing one block-diagonal F */
 
 /* Library version string (static storage). */
 const char *gsrad_version(void);
@@ -250,6 +251,46 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
  * on a GSRAD_BF16 tape; GSRAD_ESTATE if there is none.
  */
 gsrad_status gsrad_tape_grad_F_dense(const gsrad_tape *tape, float *grad_F_out, void *stream);
+
+/*
+ * Batches of scenes of uneven size (many scenes, each lit by its own set of
+ * point lights, propagated together; Sec. 6 renders many images from one
+ * propagation).  gsrad_batch_create joins the scenes' transport operators
+ * (each from gsrad_form_factors or gsrad_ff_from_csr, n_s rows) into one
+ * block-diagonal F with global indices: scene s owns rows
+ * [row_off_s, row_off_s + n_s) in the order given.  Scene s has
+ * lights[s] >= 1 point lights and C_s = lights[s] * K * 3 columns, so rho
+ * is [sum n_s][3] and E, B and their gradients are ragged: scene s's rows
+ * are one [n_s][lights[s]][K][3] block, blocks concatenated in scene order
+ * (val_off_s = sum_{t<s} n_t C_t values before it).  lights is a host
+ * array of n_scenes entries; the scenes' handles may be destroyed after
+ * the call.
+ *
+ * gsrad_batch_transport_solve runs the bounces of Eq. final-radiosity on
+ * every scene at once: each bounce is one persistent launch in which
+ * groups of lanes take rows from a work counter, largest cost (entries x
+ * columns) first.  The lanes-per-row shape (16, 32 or 64) is chosen by
+ * timing each candidate on the batch's own rows at the first solve (every
+ * candidate adds each output in the same order, so the choice never
+ * changes a result).  The bounce loop is captured once into a HIP graph
+ * and replayed while the arguments stay the same.  The iterates are kept
+ * in the batch for gsrad_batch_transport_backward, the exact adjoint
+ * (same formulas as gsrad_transport_backward; grad_F in the block-diagonal
+ * F's CSR order, see gsrad_batch_ff).  Calls on one batch must not overlap.
+ */
+gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, const int32_t *lights, int32_t K,
+                                gsrad_batch **batch, void *stream);
+/* total rows, total values of the ragged arrays, and the lanes per row
+ * chosen for the bounce and the adjoint (0 before the first solve) */
+gsrad_status gsrad_batch_info(const gsrad_batch *batch, int64_t *rows, int64_t *vals, int32_t *lanes_bounce,
+                              int32_t *lanes_adjoint);
+/* the block-diagonal F (read-only; valid while the batch lives) */
+gsrad_status gsrad_batch_ff(const gsrad_batch *batch, const gsrad_ff **ff);
+gsrad_status gsrad_batch_transport_solve(gsrad_batch *batch, const float *rho, const float *E, int32_t n_bounces,
+                                         float *B_out, void *stream);
+gsrad_status gsrad_batch_transport_backward(gsrad_batch *batch, const float *rho, const float *grad_B,
+                                            float *grad_E, float *grad_rho, float *grad_F, void *stream);
+void gsrad_batch_destroy(gsrad_batch *batch);
 
 /*
  * Opacity and albedo gradients (Eq. dl-dgeo-0, decay term, restricted to

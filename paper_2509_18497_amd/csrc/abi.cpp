@@ -15,6 +15,7 @@
 #include "gsrad_internal.h"
 #include "trace_api.h"
 #include "dense_api.h"
+#include "batch_api.h"
 
 namespace gsrad {
 
@@ -213,6 +214,50 @@ struct gsrad_tape {
     DevBuf Q, bb, bb_lo, pb, pb_lo, lam_a, lam_b, G;
     ~gsrad_tape() {
         for (DevBuf *b : {&B, &L, &lam0, &pp, &Q, &bb, &bb_lo, &pb, &pb_lo, &lam_a, &lam_b, &G}) b->release();
+    }
+};
+
+struct gsrad_batch {
+    int32_t S = 0;
+    int K = 0;
+    int64_t rows = 0, vals = 0;
+    gsrad_ff *F = nullptr;   // block-diagonal, owned
+    DevBuf row_off, val_off, scene_C, row_scene, order, counter, temp;
+    // forward iterates B^(0..nb-1) and adjoint iterates lambda^(1..nb)
+    int nb = -1;
+    DevBuf Bt, Lt, lam0;
+    // lanes per row chosen by timing (0: not yet)
+    int lpr_fwd = 0, lpr_adj = 0;
+    // captured bounce loop and the arguments it was captured with
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *g_rho = nullptr, *g_E = nullptr, *g_B = nullptr, *g_tape = nullptr;
+    int g_nb = -1, g_lpr = 0;
+    gsrad::BatchDev dev() const {
+        gsrad::BatchDev d;
+        d.rows = rows;
+        d.scenes = S;
+        d.row_off = row_off.as<int64_t>();
+        d.val_off = val_off.as<int64_t>();
+        d.scene_C = scene_C.as<int32_t>();
+        d.row_scene = row_scene.as<int32_t>();
+        d.order = order.as<int64_t>();
+        return d;
+    }
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        g_nb = -1;
+    }
+    ~gsrad_batch() {
+        drop_graph();
+        if (cap) (void)hipStreamDestroy(cap);
+        delete F;
+        for (DevBuf *b : {&row_off, &val_off, &scene_C, &row_scene, &order, &counter, &temp, &Bt, &Lt, &lam0})
+            b->release();
     }
 };
 
@@ -948,5 +993,253 @@ gsrad_status gsrad_profile_report(char *buf, int64_t len) {
 void gsrad_bvh_destroy(gsrad_bvh *bvh) { delete bvh; }
 void gsrad_ff_destroy(gsrad_ff *ff) { delete ff; }
 void gsrad_tape_destroy(gsrad_tape *tape) { delete tape; }
+
+gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, const int32_t *lights, int32_t K,
+                                gsrad_batch **batch, void *stream) {
+    if (!ffs || !lights || !batch) return einval("gsrad_batch_create: null argument");
+    if (n_scenes < 1) return einval("gsrad_batch_create: n_scenes must be >= 1");
+    if (!valid_K(K)) return einval("gsrad_batch_create: K must be 1, 4, 9 or 16");
+    std::vector<int64_t> roff(n_scenes + 1, 0), voff(n_scenes + 1, 0), eoff(n_scenes + 1, 0);
+    std::vector<int32_t> Cs(n_scenes);
+    int max_row = 0;
+    for (int s = 0; s < n_scenes; ++s) {
+        if (!ffs[s] || ffs[s]->n < 1) {
+            set_error("gsrad_batch_create: scene %d has no operator", s);
+            return GSRAD_EINVAL;
+        }
+        if (lights[s] < 1) {
+            set_error("gsrad_batch_create: scene %d needs at least one light", s);
+            return GSRAD_EINVAL;
+        }
+        Cs[s] = lights[s] * K * 3;
+        roff[s + 1] = roff[s] + ffs[s]->n;
+        voff[s + 1] = voff[s] + ffs[s]->n * (int64_t)Cs[s];
+        eoff[s + 1] = eoff[s] + ffs[s]->nnz;
+        max_row = std::max(max_row, ffs[s]->max_row);
+    }
+    if (roff[n_scenes] >= ((int64_t)1 << 31) || eoff[n_scenes] >= ((int64_t)1 << 32))
+        return einval("gsrad_batch_create: batch too large (rows < 2^31, entries < 2^32)");
+    hipStream_t st = S(stream);
+    gsrad_batch *b = new gsrad_batch();
+    auto fail = [&](gsrad_status e) {
+        delete b;
+        return e;
+    };
+    gsrad_status e;
+    b->S = n_scenes;
+    b->K = K;
+    b->rows = roff[n_scenes];
+    b->vals = voff[n_scenes];
+    b->F = new gsrad_ff();
+    gsrad_ff *F = b->F;
+    const int64_t rows = b->rows, nnz = eoff[n_scenes];
+    if ((e = F->row_ptr.ensure((size_t)(rows + 1) * 8, "batch row_ptr")) != GSRAD_OK) return fail(e);
+    if ((e = F->col.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "batch col")) != GSRAD_OK) return fail(e);
+    if ((e = F->val.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "batch val")) != GSRAD_OK) return fail(e);
+    for (int s = 0; s < n_scenes; ++s) {
+        const gsrad_ff *f = ffs[s];
+        if ((e = launch_offset_copy_i64(f->row_ptr.as<int64_t>(), f->n, eoff[s], F->row_ptr.as<int64_t>() + roff[s],
+                                        st)) != GSRAD_OK)
+            return fail(e);
+        if ((e = launch_offset_copy_i32(f->col.as<int32_t>(), f->nnz, (int32_t)roff[s], F->col.as<int32_t>() + eoff[s],
+                                        st)) != GSRAD_OK)
+            return fail(e);
+        if (f->nnz > 0 && (e = check_hip(hipMemcpyAsync(F->val.as<float>() + eoff[s], f->val.p, (size_t)f->nnz * 4,
+                                                        hipMemcpyDeviceToDevice, st),
+                                         "batch val copy")) != GSRAD_OK)
+            return fail(e);
+    }
+    if ((e = check_hip(hipMemcpyAsync(F->row_ptr.as<int64_t>() + rows, &eoff[n_scenes], 8, hipMemcpyHostToDevice, st),
+                       "batch row_ptr end")) != GSRAD_OK)
+        return fail(e);
+    F->n = rows;
+    F->nnz = nnz;
+    F->max_row = max_row;
+    if ((e = b->row_off.ensure((size_t)(n_scenes + 1) * 8, "scene rows")) != GSRAD_OK) return fail(e);
+    if ((e = b->val_off.ensure((size_t)(n_scenes + 1) * 8, "scene values")) != GSRAD_OK) return fail(e);
+    if ((e = b->scene_C.ensure((size_t)n_scenes * 4, "scene columns")) != GSRAD_OK) return fail(e);
+    if ((e = b->row_scene.ensure((size_t)rows * 4, "row scenes")) != GSRAD_OK) return fail(e);
+    if ((e = b->order.ensure((size_t)rows * 8, "row order")) != GSRAD_OK) return fail(e);
+    if ((e = b->counter.ensure(256, "work counter")) != GSRAD_OK) return fail(e);
+    if ((e = b->temp.ensure(batch_order_temp_bytes(rows), "batch temp")) != GSRAD_OK) return fail(e);
+    if ((e = check_hip(hipMemcpyAsync(b->row_off.p, roff.data(), (size_t)(n_scenes + 1) * 8, hipMemcpyHostToDevice, st),
+                       "scene rows copy")) != GSRAD_OK)
+        return fail(e);
+    if ((e = check_hip(hipMemcpyAsync(b->val_off.p, voff.data(), (size_t)(n_scenes + 1) * 8, hipMemcpyHostToDevice, st),
+                       "scene values copy")) != GSRAD_OK)
+        return fail(e);
+    if ((e = check_hip(hipMemcpyAsync(b->scene_C.p, Cs.data(), (size_t)n_scenes * 4, hipMemcpyHostToDevice, st),
+                       "scene columns copy")) != GSRAD_OK)
+        return fail(e);
+    if ((e = batch_order_rows(b->dev(), F->row_ptr.as<int64_t>(), b->temp.p, b->temp.bytes, st)) != GSRAD_OK)
+        return fail(e);
+    // the host vectors above are sources of asynchronous copies
+    if ((e = check_hip(hipStreamSynchronize(st), "batch create sync")) != GSRAD_OK) return fail(e);
+    *batch = b;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_batch_info(const gsrad_batch *b, int64_t *rows, int64_t *vals, int32_t *lanes_bounce,
+                              int32_t *lanes_adjoint) {
+    if (!b) return einval("gsrad_batch_info: null handle");
+    if (rows) *rows = b->rows;
+    if (vals) *vals = b->vals;
+    if (lanes_bounce) *lanes_bounce = b->lpr_fwd;
+    if (lanes_adjoint) *lanes_adjoint = b->lpr_adj;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_batch_ff(const gsrad_batch *b, const gsrad_ff **ff) {
+    if (!b || !ff) return einval("gsrad_batch_ff: null argument");
+    *ff = b->F;
+    return GSRAD_OK;
+}
+
+namespace {
+
+// Lanes per row for a ragged product: each candidate runs once on the
+// batch's own rows (into scratch) and the fastest is kept.
+gsrad_status autotune_lanes(gsrad_batch *b, const Csr &F, bool adjoint, const float *in, const float *rho,
+                            float *scratch, float *scratch2, hipStream_t st, int *best) {
+    hipEvent_t e0, e1;
+    GS_TRY(check_hip(hipEventCreate(&e0), "tune event"));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return check_hip(hipErrorOutOfMemory, "tune event");
+    }
+    float best_ms = 0.0f;
+    gsrad_status e = GSRAD_OK;
+    for (int lpr : {64, 32, 16}) {
+        for (int rep = 0; rep < 2 && e == GSRAD_OK; ++rep) {   // the first run warms the caches
+            if ((e = check_hip(hipEventRecord(e0, st), "tune record")) != GSRAD_OK) break;
+            e = launch_ragged_spmm(b->dev(), F, lpr, adjoint, in, in, rho, scratch, scratch2, b->counter.as<uint32_t>(),
+                                   st);
+            if (e == GSRAD_OK) e = check_hip(hipEventRecord(e1, st), "tune record");
+        }
+        if (e != GSRAD_OK) break;
+        if ((e = check_hip(hipEventSynchronize(e1), "tune sync")) != GSRAD_OK) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (*best == 0 || ms < best_ms) {
+            best_ms = ms;
+            *best = lpr;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return e;
+}
+
+}  // namespace
+
+gsrad_status gsrad_batch_transport_solve(gsrad_batch *b, const float *rho, const float *E, int32_t n_bounces,
+                                         float *B_out, void *stream) {
+    if (!b || !rho || !E || !B_out) return einval("gsrad_batch_transport_solve: null argument");
+    if (n_bounces < 0 || n_bounces > 4096) return einval("gsrad_batch_transport_solve: n_bounces must be in [0, 4096]");
+    hipStream_t st = S(stream);
+    const int64_t vals = b->vals;
+    const Csr F = b->F->csr();
+    b->nb = -1;
+    if (n_bounces == 0) {
+        GS_TRY(check_hip(hipMemcpyAsync(B_out, E, (size_t)vals * 4, hipMemcpyDeviceToDevice, st), "batch copy"));
+        b->nb = 0;
+        return GSRAD_OK;
+    }
+    const size_t tape_bytes = (size_t)n_bounces * vals * 4;
+    if (b->Bt.bytes < tape_bytes) {
+        b->drop_graph();   // the captured loop writes into the old tape
+        GS_TRY(b->Bt.ensure(tape_bytes, "batch forward tape"));
+    }
+    if (b->lpr_fwd == 0) {
+        ProfScope ps("batch_tune", st);
+        GS_TRY(autotune_lanes(b, F, false, E, rho, B_out, nullptr, st, &b->lpr_fwd));
+    }
+    float *tape = b->Bt.as<float>();
+    const bool hit = b->exec && b->g_rho == rho && b->g_E == E && b->g_B == B_out && b->g_tape == tape &&
+                     b->g_nb == n_bounces && b->g_lpr == b->lpr_fwd;
+    if (!hit) {
+        b->drop_graph();
+        if (!b->cap) GS_TRY(check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream"));
+        GS_TRY(check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
+        gsrad_status e = launch_copy_f32(E, vals, tape, b->cap);
+        for (int k = 0; k < n_bounces && e == GSRAD_OK; ++k) {
+            const float *in = tape + (size_t)k * vals;
+            float *out = k == n_bounces - 1 ? B_out : tape + (size_t)(k + 1) * vals;
+            e = launch_ragged_spmm(b->dev(), F, b->lpr_fwd, false, in, E, rho, out, nullptr, b->counter.as<uint32_t>(),
+                                   b->cap);
+        }
+        hipGraph_t g = nullptr;
+        const gsrad_status ec = check_hip(hipStreamEndCapture(b->cap, &g), "end capture");
+        if (e != GSRAD_OK || ec != GSRAD_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return e != GSRAD_OK ? e : ec;
+        }
+        b->graph = g;
+        GS_TRY(check_hip(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate"));
+        b->g_rho = rho;
+        b->g_E = E;
+        b->g_B = B_out;
+        b->g_tape = tape;
+        b->g_nb = n_bounces;
+        b->g_lpr = b->lpr_fwd;
+    }
+    {
+        ProfScope ps("batch_bounces", st);
+        GS_TRY(check_hip(hipGraphLaunch(b->exec, st), "graph launch"));
+    }
+    b->nb = n_bounces;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, const float *grad_B, float *grad_E,
+                                            float *grad_rho, float *grad_F, void *stream) {
+    if (!b || !rho || !grad_B || !grad_E) return einval("gsrad_batch_transport_backward: null argument");
+    if (b->nb < 0) {
+        set_error("gsrad_batch_transport_backward: no forward solve on this batch");
+        return GSRAD_ESTATE;
+    }
+    hipStream_t st = S(stream);
+    const int64_t vals = b->vals, rows = b->rows;
+    const int nb = b->nb;
+    GS_TRY(check_hip(hipMemcpyAsync(grad_E, grad_B, (size_t)vals * 4, hipMemcpyDeviceToDevice, st), "grad_E init"));
+    if (nb == 0) {
+        if (grad_rho) GS_TRY(check_hip(hipMemsetAsync(grad_rho, 0, (size_t)rows * 12, st), "grad_rho zero"));
+        if (grad_F && b->F->nnz > 0)
+            GS_TRY(check_hip(hipMemsetAsync(grad_F, 0, (size_t)b->F->nnz * 4, st), "grad_F zero"));
+        return GSRAD_OK;
+    }
+    {
+        ProfScope ps("transpose", st);
+        GS_TRY(ensure_transpose(b->F, st));
+    }
+    GS_TRY(b->Lt.ensure((size_t)(nb + 1) * vals * 4, "batch adjoint tape"));   // + one scratch slot
+    GS_TRY(b->lam0.ensure((size_t)vals * 4, "batch adjoint scratch"));
+    float *L = b->Lt.as<float>();
+    GS_TRY(check_hip(hipMemcpyAsync(L + (size_t)(nb - 1) * vals, grad_B, (size_t)vals * 4, hipMemcpyDeviceToDevice, st),
+                     "adjoint seed"));
+    const Csr FT = b->F->csr_t();
+    if (b->lpr_adj == 0) {
+        // timing runs write only into scratch: lam0 and the slot past the tape
+        float *s2 = L + (size_t)nb * vals;
+        ProfScope ps("batch_tune", st);
+        GS_TRY(check_hip(hipMemsetAsync(s2, 0, (size_t)vals * 4, st), "tune scratch"));
+        GS_TRY(autotune_lanes(b, FT, true, grad_B, rho, b->lam0.as<float>(), s2, st, &b->lpr_adj));
+    }
+    for (int k = nb - 1; k >= 0; --k) {
+        const float *in = L + (size_t)k * vals;   // lambda^(k+1)
+        float *out = k >= 1 ? L + (size_t)(k - 1) * vals : b->lam0.as<float>();
+        ProfScope ps("batch_adjoint", st);
+        GS_TRY(launch_ragged_spmm(b->dev(), FT, b->lpr_adj, true, in, nullptr, rho, out, grad_E,
+                                  b->counter.as<uint32_t>(), st));
+    }
+    if (grad_F || grad_rho) {
+        ProfScope ps("batch_sddmm", st);
+        GS_TRY(launch_ragged_sddmm(b->dev(), b->F->csr(), nb, vals, b->Bt.as<float>(), L, rho, grad_F, grad_rho,
+                                   b->counter.as<uint32_t>(), st));
+    }
+    return GSRAD_OK;
+}
+
+void gsrad_batch_destroy(gsrad_batch *batch) { delete batch; }
 
 }  // extern "C"

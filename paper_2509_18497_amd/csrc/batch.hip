@@ -1,0 +1,275 @@
+// Batched transport over scenes of uneven size: the scenes' form factors
+// form one block-diagonal F (global row and column indices), scene s owns
+// rows [row_off[s], row_off[s+1]) and C_s = Lt_s * K * 3 columns, so B, E
+// and the gradients are ragged: scene s's rows are a [N_s][C_s] block at
+// val_off[s] of one array.
+//
+// Each bounce (and each adjoint step) is ONE persistent launch over all
+// scenes: groups of LPR lanes take rows from a global counter in an order
+// sorted by cost (entries x columns, largest first), so scenes of 2k and
+// 65k surfels and 8 or 100 lights share the chip without tail effects.
+// LPR (lanes per row: 64, 32 or 16) is the tile shape the autotuner picks;
+// every variant accumulates each output in the same order (the row's
+// entries in CSR order), so the choice never changes a result bit.
+#include "gsrad_internal.h"
+#include "batch_api.h"
+
+namespace gsrad {
+
+namespace {
+
+// Work-queue position -> row, for a group of LPR lanes: one lane takes the
+// next index and the group shares it.
+template <int LPR>
+__device__ __forceinline__ int64_t next_row(uint32_t *counter, int lane_in_group, int group_base) {
+    uint32_t idx = 0;
+    if (lane_in_group == 0) idx = atomicAdd(counter, 1u);
+    return (int64_t)__shfl((int)idx, group_base, 64);
+}
+
+// out = E + rho * (F in) on the rows of all scenes (bounce), or
+// out = F^T (rho in) and gE += out (adjoint, FT given as F, rho applied to
+// the gathered rows).
+template <int LPR, bool ADJ>
+__global__ void __launch_bounds__(256) k_ragged_spmm(BatchDev bd, const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                     const float *__restrict__ in, const float *__restrict__ E,
+                                                     const float *__restrict__ rho, float *__restrict__ out,
+                                                     float *__restrict__ gE, uint32_t *counter) {
+    const int lane = __lane_id();
+    const int lig = lane % LPR;                 // lane in group
+    const int gbase = lane - lig;               // first lane of the group
+    for (;;) {
+        const int64_t q = next_row<LPR>(counter, lig, gbase);
+        if (q >= bd.rows) break;
+        const int64_t row = bd.order[q];
+        const int s = bd.row_scene[row];
+        const int C = bd.scene_C[s];
+        const int64_t r0 = bd.row_off[s], base = bd.val_off[s];
+        const int64_t lr = row - r0;
+        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+        for (int c0 = 0; c0 < C; c0 += LPR) {
+            const int c = c0 + lig;
+            const bool on = c < C;
+            const int colour = c % 3;
+            float acc = 0.0f;
+            for (int64_t k0 = b; k0 < e; k0 += LPR) {
+                const int64_t kk = k0 + lig;
+                const int jv = kk < e ? col[kk] : 0;
+                const float vv = kk < e ? val[kk] : 0.0f;
+                const int m = (int)min<int64_t>(LPR, e - k0);
+                for (int t = 0; t < m; ++t) {
+                    const int64_t j = __shfl(jv, gbase + t, 64);
+                    const float v = __shfl(vv, gbase + t, 64);
+                    if (on) {
+                        const float x = in[base + (j - r0) * C + c];
+                        acc = ADJ ? __builtin_fmaf(v * rho[j * 3 + colour], x, acc) : __builtin_fmaf(v, x, acc);
+                    }
+                }
+            }
+            if (on) {
+                const int64_t o = base + lr * C + c;
+                if (ADJ) {
+                    out[o] = acc;
+                    gE[o] += acc;
+                } else {
+                    out[o] = __builtin_fmaf(rho[row * 3 + colour], acc, E[o]);
+                }
+            }
+        }
+    }
+}
+
+// grad_F[e] = sum_k sum_c rho_row,c%3 lam^(k+1)[row][c] B^(k)[j][c] and
+// grad_rho[row][colour] = sum_e F[e] sum_k sum_{c of colour} (same), one
+// wave per row (tapes [nb][vals]).
+__global__ void __launch_bounds__(256) k_ragged_sddmm(BatchDev bd, const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const float *__restrict__ val, int nb, int64_t vals,
+                                                      const float *__restrict__ Bt, const float *__restrict__ Lt,
+                                                      const float *__restrict__ rho, float *__restrict__ grad_F,
+                                                      float *__restrict__ grad_rho, uint32_t *counter) {
+    const int lane = __lane_id();
+    for (;;) {
+        const int64_t q = next_row<64>(counter, lane, 0);
+        if (q >= bd.rows) break;
+        const int64_t row = bd.order[q];
+        const int s = bd.row_scene[row];
+        const int C = bd.scene_C[s];
+        const int64_t r0 = bd.row_off[s], base = bd.val_off[s];
+        const int64_t lr = row - r0;
+        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+        const float rr0 = rho[row * 3 + 0], rr1 = rho[row * 3 + 1], rr2 = rho[row * 3 + 2];
+        float gr0 = 0.0f, gr1 = 0.0f, gr2 = 0.0f;
+        for (int64_t k = b; k < e; ++k) {
+            const int64_t j = col[k];
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+            for (int c = lane; c < C; c += 64) {
+                float sum = 0.0f;
+                for (int t = 0; t < nb; ++t)
+                    sum = __builtin_fmaf(Lt[t * vals + base + lr * C + c], Bt[t * vals + base + (j - r0) * C + c], sum);
+                const int colour = c % 3;
+                s0 += colour == 0 ? sum : 0.0f;
+                s1 += colour == 1 ? sum : 0.0f;
+                s2 += colour == 2 ? sum : 0.0f;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                s0 += __shfl_xor(s0, o, 64);
+                s1 += __shfl_xor(s1, o, 64);
+                s2 += __shfl_xor(s2, o, 64);
+            }
+            if (lane == 0 && grad_F) grad_F[k] = rr0 * s0 + rr1 * s1 + rr2 * s2;
+            const float f = val[k];
+            gr0 = __builtin_fmaf(f, s0, gr0);
+            gr1 = __builtin_fmaf(f, s1, gr1);
+            gr2 = __builtin_fmaf(f, s2, gr2);
+        }
+        if (lane == 0 && grad_rho) {
+            grad_rho[row * 3 + 0] = gr0;
+            grad_rho[row * 3 + 1] = gr1;
+            grad_rho[row * 3 + 2] = gr2;
+        }
+    }
+}
+
+__global__ void k_reset_counter(uint32_t *counter) {
+    if (threadIdx.x == 0) counter[0] = 0u;
+}
+
+// row -> scene and the per-row cost (entries x columns) used for ordering
+__global__ void __launch_bounds__(256) k_row_cost(BatchDev bd, const int64_t *__restrict__ row_ptr,
+                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ ids) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= bd.rows) return;
+    int lo = 0, hi = bd.scenes - 1;
+    while (lo < hi) {   // last scene with row_off <= r
+        const int mid = (lo + hi + 1) >> 1;
+        if (bd.row_off[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    bd.row_scene[r] = lo;
+    const uint64_t cost = (uint64_t)(row_ptr[r + 1] - row_ptr[r] + 1) * (uint64_t)bd.scene_C[lo];
+    // descending cost: sort ascending on the complement, saturated to 32 bits
+    keys[r] = ~(uint32_t)min<uint64_t>(cost, 0xffffffffull);
+    ids[r] = (uint32_t)r;
+}
+
+__global__ void __launch_bounds__(256) k_copy_u32_to_i64(const uint32_t *__restrict__ a, int64_t n,
+                                                         int64_t *__restrict__ b) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r < n) b[r] = a[r];
+}
+
+inline unsigned persistent_blocks() { return 256 * 8; }   // 8 workgroups of 4 waves per CU
+
+}  // namespace
+
+gsrad_status batch_order_rows(const BatchDev &bd, const int64_t *row_ptr, void *temp, size_t temp_bytes,
+                              hipStream_t st) {
+    const int64_t n = bd.rows;
+    if (n == 0) return GSRAD_OK;
+    char *p = static_cast<char *>(temp);
+    auto carve = [&](size_t bytes) {
+        char *r = p;
+        p += (bytes + 255) / 256 * 256;
+        return r;
+    };
+    uint32_t *keys = reinterpret_cast<uint32_t *>(carve((size_t)n * 4));
+    uint32_t *ids = reinterpret_cast<uint32_t *>(carve((size_t)n * 4));
+    uint32_t *skeys = reinterpret_cast<uint32_t *>(carve((size_t)n * 4));
+    uint32_t *sids = reinterpret_cast<uint32_t *>(carve((size_t)n * 4));
+    const size_t rbytes = radix_temp_bytes(n);
+    void *rtemp = carve(rbytes);
+    if ((size_t)(p - static_cast<char *>(temp)) > temp_bytes) {
+        set_error("batch ordering: temp too small");
+        return GSRAD_EINVAL;
+    }
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_row_cost, dim3(g), dim3(256), 0, st, bd, row_ptr, keys, ids);
+    gsrad_status s = radix_sort_pairs(keys, ids, skeys, sids, n, 32, rtemp, rbytes, st);
+    if (s != GSRAD_OK) return s;
+    hipLaunchKernelGGL(k_copy_u32_to_i64, dim3(g), dim3(256), 0, st, sids, n, const_cast<int64_t *>(bd.order));
+    return check_hip(hipGetLastError(), "batch ordering");
+}
+
+size_t batch_order_temp_bytes(int64_t n) { return 4 * ((size_t)n * 4 + 256) + radix_temp_bytes(n) + 256; }
+
+gsrad_status launch_ragged_spmm(const BatchDev &bd, const Csr &F, int lpr, bool adjoint, const float *in,
+                                const float *E, const float *rho, float *out, float *gE, uint32_t *counter,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    const dim3 grid(persistent_blocks()), block(256);
+#define RAGGED(L, A) \
+    hipLaunchKernelGGL((k_ragged_spmm<L, A>), grid, block, 0, st, bd, F.row_ptr, F.col, F.val, in, E, rho, out, gE, counter)
+    if (lpr == 64) {
+        if (adjoint) RAGGED(64, true);
+        else RAGGED(64, false);
+    } else if (lpr == 32) {
+        if (adjoint) RAGGED(32, true);
+        else RAGGED(32, false);
+    } else if (lpr == 16) {
+        if (adjoint) RAGGED(16, true);
+        else RAGGED(16, false);
+    } else {
+        set_error("ragged product: lanes per row must be 16, 32 or 64");
+        return GSRAD_EINVAL;
+    }
+#undef RAGGED
+    return check_hip(hipGetLastError(), "ragged product launch");
+}
+
+gsrad_status launch_ragged_sddmm(const BatchDev &bd, const Csr &F, int nb, int64_t vals, const float *Bt,
+                                 const float *Lt, const float *rho, float *grad_F, float *grad_rho, uint32_t *counter,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    hipLaunchKernelGGL(k_ragged_sddmm, dim3(persistent_blocks()), dim3(256), 0, st, bd, F.row_ptr, F.col, F.val, nb,
+                       vals, Bt, Lt, rho, grad_F, grad_rho, counter);
+    return check_hip(hipGetLastError(), "ragged sddmm launch");
+}
+
+}  // namespace gsrad
+
+namespace gsrad {
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_offset_copy_i32(const int32_t *__restrict__ in, int64_t n, int32_t add,
+                                                         int32_t *__restrict__ out) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+        out[k] = in[k] + add;
+}
+
+__global__ void __launch_bounds__(256) k_offset_copy_i64(const int64_t *__restrict__ in, int64_t n, int64_t add,
+                                                         int64_t *__restrict__ out) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+        out[k] = in[k] + add;
+}
+
+__global__ void __launch_bounds__(256) k_copy_f32(const float *__restrict__ in, int64_t n, float *__restrict__ out) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) out[k] = in[k];
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+gsrad_status launch_offset_copy_i32(const int32_t *in, int64_t n, int32_t add, int32_t *out, hipStream_t st) {
+    if (n <= 0) return GSRAD_OK;
+    hipLaunchKernelGGL(k_offset_copy_i32, dim3(grid_for(n)), dim3(256), 0, st, in, n, add, out);
+    return check_hip(hipGetLastError(), "offset copy launch");
+}
+
+gsrad_status launch_offset_copy_i64(const int64_t *in, int64_t n, int64_t add, int64_t *out, hipStream_t st) {
+    if (n <= 0) return GSRAD_OK;
+    hipLaunchKernelGGL(k_offset_copy_i64, dim3(grid_for(n)), dim3(256), 0, st, in, n, add, out);
+    return check_hip(hipGetLastError(), "offset copy launch");
+}
+
+gsrad_status launch_copy_f32(const float *in, int64_t n, float *out, hipStream_t st) {
+    if (n <= 0) return GSRAD_OK;
+    hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n)), dim3(256), 0, st, in, n, out);
+    return check_hip(hipGetLastError(), "copy launch");
+}
+
+}  // namespace gsrad

@@ -27,7 +27,8 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
-           "gsrad_tape_destroy")
+           "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
+           "gsrad_batch_transport_solve", "gsrad_batch_transport_backward", "gsrad_batch_destroy")
 
 
 class GsradError(RuntimeError):
@@ -72,6 +73,12 @@ def lib():
             "gsrad_ff_copy": ([vp, vp, vp, vp, vp], i32),
             "gsrad_ff_from_csr": ([i64, i64, vp, vp, vp, pvp, vp], i32),
             "gsrad_ff_dense": ([vp, vp], i32),
+            "gsrad_batch_create": ([vp, i32, vp, i32, pvp, vp], i32),
+            "gsrad_batch_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32)], i32),
+            "gsrad_batch_ff": ([vp, pvp], i32),
+            "gsrad_batch_transport_solve": ([vp, vp, vp, i32, vp, vp], i32),
+            "gsrad_batch_transport_backward": ([vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_tape_grad_F_dense": ([vp, vp, vp], i32),
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
@@ -84,6 +91,7 @@ def lib():
             "gsrad_bvh_destroy": ([vp], None),
             "gsrad_ff_destroy": ([vp], None),
             "gsrad_tape_destroy": ([vp], None),
+            "gsrad_batch_destroy": ([vp], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -122,7 +130,7 @@ class _Handle:
         self.h = ctypes.c_void_p(None)
 
     def __del__(self):
-        if self.h and self.h.value and _lib is not None:
+        if self._destroy and self.h and self.h.value and _lib is not None:
             getattr(_lib, self._destroy)(self.h)
             self.h = ctypes.c_void_p(None)
 
@@ -230,6 +238,80 @@ def direct_light(bvh: BVH, albedo: torch.Tensor, light_pos: torch.Tensor, light_
                                     _ptr(light_I, name="light_I"), Lt, int(K), _ptr(E, name="E"), _stream(stream)),
            "gsrad_direct_light")
     return E
+
+
+class Batch(_Handle):
+    """Scenes of uneven size sharing one block-diagonal F; E, B and their
+    gradients are flat arrays of the scenes' [n_s, Lt_s, K, 3] blocks in
+    scene order (see pack / unpack)."""
+    _destroy = "gsrad_batch_destroy"
+
+    def info(self):
+        r, v, lf, la = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().gsrad_batch_info(self.h, ctypes.byref(r), ctypes.byref(v), ctypes.byref(lf), ctypes.byref(la)),
+               "gsrad_batch_info")
+        return {"rows": int(r.value), "vals": int(v.value), "lanes_bounce": int(lf.value),
+                "lanes_adjoint": int(la.value)}
+
+    def ff(self) -> "FF":
+        """The block-diagonal F (owned by the batch)."""
+        out = _BorrowedFF()
+        _check(lib().gsrad_batch_ff(self.h, ctypes.byref(out.h)), "gsrad_batch_ff")
+        out.owner = self
+        return out
+
+    def pack(self, blocks) -> torch.Tensor:
+        """Concatenate per-scene [n_s, Lt_s, K, 3] tensors into the flat layout."""
+        return torch.cat([b.reshape(-1) for b in blocks]).contiguous()
+
+    def unpack(self, flat: torch.Tensor):
+        """Split a flat array back into per-scene [n_s, Lt_s, K, 3] views."""
+        out, off = [], 0
+        for n, lt in zip(self.scene_rows, self.lights):
+            m = n * lt * self.K * 3
+            out.append(flat[off:off + m].view(n, lt, self.K, 3))
+            off += m
+        return out
+
+
+class _BorrowedFF(FF):
+    _destroy = None
+
+
+def batch_create(ffs, lights, K: int, stream=None) -> Batch:
+    """Join the scenes' operators into one batch (scene s lit by lights[s] lights)."""
+    S = len(ffs)
+    arr = (ctypes.c_void_p * S)(*[f.h.value for f in ffs])
+    lt = (ctypes.c_int32 * S)(*[int(x) for x in lights])
+    b = Batch()
+    _check(lib().gsrad_batch_create(arr, S, lt, int(K), ctypes.byref(b.h), _stream(stream)), "gsrad_batch_create")
+    b.scene_rows = [f.info()[0] for f in ffs]
+    b.lights = [int(x) for x in lights]
+    b.K = int(K)
+    return b
+
+
+def batch_transport_solve(batch: Batch, rho: torch.Tensor, E: torch.Tensor, n_bounces: int,
+                          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """B = E + rho*(F B), n_bounces times, on every scene of the batch (flat E)."""
+    B = out if out is not None else torch.empty_like(E)
+    _check(lib().gsrad_batch_transport_solve(batch.h, _ptr(rho, name="rho"), _ptr(E, name="E"), int(n_bounces),
+                                             _ptr(B, name="B"), _stream(stream)), "gsrad_batch_transport_solve")
+    return B
+
+
+def batch_transport_backward(batch: Batch, rho: torch.Tensor, grad_B: torch.Tensor, want_grad_F: bool = True,
+                             stream=None):
+    """dL/dE (flat), dL/drho, dL/dF at the block-diagonal F's entries."""
+    grad_E = torch.empty_like(grad_B)
+    grad_rho = torch.empty_like(rho)
+    _, nnz = batch.ff().info()
+    grad_F = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda") if want_grad_F else None
+    _check(lib().gsrad_batch_transport_backward(batch.h, _ptr(rho, name="rho"), _ptr(grad_B, name="grad_B"),
+                                                _ptr(grad_E), _ptr(grad_rho),
+                                                _ptr(grad_F) if grad_F is not None else None, _stream(stream)),
+           "gsrad_batch_transport_backward")
+    return grad_E, grad_rho, (grad_F[:nnz] if grad_F is not None else None)
 
 
 def ff_dense(ff: FF, stream=None) -> FF:

@@ -1,0 +1,132 @@
+"""Batches of scenes of uneven size (one block-diagonal F, ragged right-hand
+sides, persistent launches, tuned lanes per row, captured bounce loop)
+against the unbatched FP32 path and the FP64 oracle.
+
+Every lanes-per-row variant adds each output in the entries' CSR order,
+exactly like the unbatched kernels, so a batch must reproduce the
+per-scene results bit for bit; the oracle bar is the FP32 1e-4.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from tests.gpu_common import dev, rel_err  # noqa: E402
+
+TOL = 1e-4
+SIZES = [300, 1200, 77, 2500, 640]
+ROWLEN = [20, 40, 5, 60, 30]
+LIGHTS = [3, 1, 8, 2, 5]
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_18497_amd as g
+    g.gsrad.lib()
+    return g
+
+
+def _scenes(g, K, sizes=SIZES, rowlen=ROWLEN, lights=LIGHTS):
+    out = []
+    for s, (n, k, lt) in enumerate(zip(sizes, rowlen, lights)):
+        rp, c, v = scenes.seeded_csr(n, k, seed=100 + s)
+        F = sp.csr_matrix((v.astype(np.float64), c, rp), shape=(n, n))
+        ff = g.ff_from_csr(dev(rp), dev(c), dev(v))
+        rho = scenes.seeded_array((n, 3), seed=200 + s, lo=0.1, hi=0.9)
+        E = scenes.seeded_array((n, lt, K, 3), seed=300 + s)
+        gB = scenes.seeded_array((n, lt, K, 3), seed=400 + s, lo=-1, hi=1)
+        out.append(dict(F=F, ff=ff, rho=rho, E=E, gB=gB, n=n, lt=lt))
+    return out
+
+
+def _flat(arrs):
+    return dev(np.concatenate([a.reshape(-1) for a in arrs]))
+
+
+@pytest.mark.parametrize("K,nb", [(9, 6), (4, 1), (16, 3)])
+def test_batch_matches_per_scene_and_oracle(g, orc, K, nb):
+    sc = _scenes(g, K)
+    batch = g.batch_create([x["ff"] for x in sc], [x["lt"] for x in sc], K)
+    info = batch.info()
+    assert info["rows"] == sum(SIZES)
+    assert info["vals"] == sum(n * lt * K * 3 for n, lt in zip(SIZES, LIGHTS))
+    rho = dev(np.concatenate([x["rho"] for x in sc]))
+    E = _flat([x["E"] for x in sc])
+    gB = _flat([x["gB"] for x in sc])
+    B = batch.unpack(g.batch_transport_solve(batch, rho, E, nb))
+    info = batch.info()
+    assert info["lanes_bounce"] in (16, 32, 64)
+    gE, gr, gF = g.batch_transport_backward(batch, rho, gB)
+    assert batch.info()["lanes_adjoint"] in (16, 32, 64)
+    gE = batch.unpack(gE)
+    gr = gr.cpu().numpy()
+    gF = gF.cpu().numpy()
+    r0 = e0 = 0
+    for x, Bb, gEb in zip(sc, B, gE):
+        n = x["n"]
+        Bs, tape = g.transport_solve(x["ff"], dev(x["rho"]), dev(x["E"]), nb)
+        gEs, grs, gFs = g.transport_backward(x["ff"], tape, dev(x["rho"]), dev(x["gB"]))
+        assert torch.equal(Bb, Bs)
+        assert torch.equal(gEb, gEs)
+        assert np.array_equal(gr[r0:r0 + n], grs.cpu().numpy())
+        nnz = x["F"].nnz
+        assert np.array_equal(gF[e0:e0 + nnz], gFs.cpu().numpy())
+        Bo, tp = orc.bounce(x["F"], x["rho"], x["E"], nb, keep_tape=True)
+        gEo, gro, gFo = orc.adjoint(x["F"], x["rho"], tp, x["gB"])
+        assert rel_err(Bb.cpu().numpy(), Bo) < TOL
+        assert rel_err(gEb.cpu().numpy(), gEo) < TOL
+        assert rel_err(gr[r0:r0 + n], gro) < TOL
+        assert rel_err(gF[e0:e0 + nnz], gFo) < TOL
+        r0 += n
+        e0 += nnz
+    # the block-diagonal F holds every scene's entries at shifted indices
+    rp, col, val = batch.ff().csr()
+    assert int(rp[-1]) == sum(x["F"].nnz for x in sc)
+
+
+def test_captured_loop_replays_with_new_values(g):
+    K, nb = 9, 4
+    sc = _scenes(g, K)
+    batch = g.batch_create([x["ff"] for x in sc], [x["lt"] for x in sc], K)
+    rho = dev(np.concatenate([x["rho"] for x in sc]))
+    E = _flat([x["E"] for x in sc])
+    B = torch.empty_like(E)
+    for rep in range(3):
+        g.batch_transport_solve(batch, rho, E, nb, out=B)      # same arguments: the graph is replayed
+        torch.cuda.synchronize()
+        parts = batch.unpack(B)
+        Es = batch.unpack(E)
+        for x, Bb, Eb in zip(sc, parts, Es):
+            Bs, _ = g.transport_solve(x["ff"], dev(x["rho"]), Eb.contiguous(), nb, keep_tape=False)
+            assert torch.equal(Bb, Bs), rep
+        E.mul_(0.5).add_(0.125)                                 # eager work between replays
+        rho.mul_(0.9)
+        for x in sc:
+            x["rho"] = (x["rho"] * np.float32(0.9)).astype(np.float32)
+        torch.cuda.synchronize()
+
+
+def test_batch_edges(g):
+    K = 1
+    sc = _scenes(g, K, sizes=[50], rowlen=[4], lights=[1])
+    batch = g.batch_create([sc[0]["ff"]], [1], K)
+    rho = dev(sc[0]["rho"])
+    E = _flat([sc[0]["E"]])
+    B = g.batch_transport_solve(batch, rho, E, 0)
+    assert torch.equal(B, E)
+    gE, gr, gF = g.batch_transport_backward(batch, rho, E)
+    assert torch.equal(gE, E) and not gr.any() and not gF.any()
+    with pytest.raises(g.GsradError):
+        g.batch_create([sc[0]["ff"]], [0], K)
+    with pytest.raises(g.GsradError):
+        g.batch_create([sc[0]["ff"]], [1], 3)
+    fresh = g.batch_create([sc[0]["ff"]], [1], K)
+    with pytest.raises(g.GsradError):
+        g.batch_transport_backward(fresh, rho, E)
