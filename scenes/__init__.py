@@ -323,6 +323,80 @@ def fruit_bowl(seed: int = 3, n: int = 100_000, n_fruit: int = 20, K: int = 16, 
 
 
 # --------------------------------------------------------------------------
+# 5. uneven batch
+# --------------------------------------------------------------------------
+def cluster_room(seed: int, n: int, n_lights: int, K: int = 9, R: int = 128, n_bounces: int = 8,
+                 half: float = 2.0) -> Scene:
+    """Room [-half, half]^3 with five walls (the +z side open, normals
+    inward) holding a cluster of 2-6 non-overlapping spheres of radius
+    U[0.2, 0.6] half; surfels per object proportional to area (jittered
+    grid on the walls, Fibonacci lattices on the spheres), s = h,
+    o ~ U[0.85, 1), albedo U[0.2, 0.8]^3, ``n_lights`` lights of intensity 4
+    drawn uniformly in the room outside the spheres."""
+    rng = np.random.default_rng(seed)
+    L, W = half, 2 * half
+    walls = [
+        _Face(np.array([-L, -L, -L]), np.array([W, 0, 0.]), np.array([0, 0, W]), np.array([0, 1., 0]), "floor"),
+        _Face(np.array([-L, L, -L]), np.array([W, 0, 0.]), np.array([0, 0, W]), np.array([0, -1., 0]), "ceiling"),
+        _Face(np.array([-L, -L, -L]), np.array([0, W, 0.]), np.array([0, 0, W]), np.array([1., 0, 0]), "left"),
+        _Face(np.array([L, -L, -L]), np.array([0, W, 0.]), np.array([0, 0, W]), np.array([-1., 0, 0]), "right"),
+        _Face(np.array([-L, -L, -L]), np.array([W, 0, 0.]), np.array([0, W, 0]), np.array([0, 0, 1.]), "back"),
+    ]
+    n_sph = int(rng.integers(2, 7))
+    centers, radii = [], []
+    while len(centers) < n_sph:
+        r = rng.uniform(0.2, 0.6) * half
+        c = rng.uniform(-L + r + 0.05, L - r - 0.05, size=3)
+        if any(np.linalg.norm(c - c2) < r + r2 + 0.05 for c2, r2 in zip(centers, radii)):
+            continue
+        centers.append(c)
+        radii.append(r)
+    a_walls = 5 * W * W
+    a_sph = np.array([4 * math.pi * r * r for r in radii])
+    h = math.sqrt((a_walls + a_sph.sum()) / n)
+    pts = np.concatenate([_face_points(f, h, rng) for f in walls])
+    nrm = np.concatenate([np.repeat(f.normal[None, :], _face_points(f, h, np.random.default_rng(0)).shape[0], axis=0)
+                          for f in walls])
+    n_w = min(pts.shape[0], int(round(n * a_walls / (a_walls + a_sph.sum()))))
+    keep = np.sort(rng.choice(pts.shape[0], size=n_w, replace=False))
+    P, Nn = [pts[keep]], [nrm[keep]]
+    counts = np.floor(a_sph / a_sph.sum() * (n - n_w)).astype(int)
+    counts[0] += (n - n_w) - counts.sum()
+    for c, r, m in zip(centers, radii, counts):
+        q = _fib_sphere(int(m), rng, jitter=0.25 * h / r)
+        P.append(c[None, :] + r * q)
+        Nn.append(q)
+    P, Nn = np.concatenate(P), np.concatenate(Nn)
+    tu, tv = onb_from_normal(Nn)
+    tu, tv = _spin(tu, tv, rng)
+    su = np.full(n, h)
+    op = rng.uniform(0.85, 1.0, size=n)
+    alb = rng.uniform(0.2, 0.8, size=(n, 3))
+    sur, alb = _pack(P, Nn, tu, tv, su, su, op, alb)
+    lps = []
+    while len(lps) < n_lights:
+        q = rng.uniform(-0.9 * L, 0.9 * L, size=3)
+        if any(np.linalg.norm(q - c) < r + 0.05 for c, r in zip(centers, radii)):
+            continue
+        lps.append(q)
+    return Scene("cluster_room", sur, alb, np.asarray(lps, np.float32), np.full(n_lights, 4.0, np.float32), K=K,
+                 R=R, n_bounces=n_bounces, topk=0, seed=seed, meta={"h": h})
+
+
+def uneven_batch(seed: int = 5, n_scenes: int = 64, n_range=(2048, 65536), lights=(8, 100), K: int = 9,
+                 R: int = 128, n_bounces: int = 8) -> List[Scene]:
+    """Scenes of log-uniform surfel counts in n_range, each a cluster room
+    lit by U{lights} point lights."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_scenes):
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        lt = int(rng.integers(lights[0], lights[1] + 1))
+        out.append(cluster_room(seed=1000 * seed + s, n=n, n_lights=lt, K=K, R=R, n_bounces=n_bounces))
+    return out
+
+
+# --------------------------------------------------------------------------
 # registry
 # --------------------------------------------------------------------------
 CONFIGS = {

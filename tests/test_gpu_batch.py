@@ -130,3 +130,43 @@ def test_batch_edges(g):
     fresh = g.batch_create([sc[0]["ff"]], [1], K)
     with pytest.raises(g.GsradError):
         g.batch_transport_backward(fresh, rho, E)
+
+
+def test_batch_of_ray_cast_cluster_rooms(g, orc):
+    """The whole batched path on ray-cast scenes of uneven size and light
+    count: per-scene BVH, form factors and direct light, then one batch
+    solve and backward, against the oracle's own per-scene F, E and FP64
+    transport."""
+    sizes, lights, K, R, nb = [400, 1500, 900, 2500, 700], [2, 5, 3, 1, 4], 9, 16, 4
+    rooms = [scenes.cluster_room(seed=70 + s, n=n, n_lights=lt, K=K, R=R, n_bounces=nb)
+             for s, (n, lt) in enumerate(zip(sizes, lights))]
+    ffs, Es, rhos, Fos, Eos = [], [], [], [], []
+    for sc in rooms:
+        bvh = g.build_bvh({k: dev(v) for k, v in sc.surfels.items()})
+        ff = g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, records=False)
+        alb = dev(sc.albedo)
+        Es.append(g.direct_light(bvh, alb, dev(sc.light_pos), dev(sc.light_I), K))
+        rhos.append(g.reflectance(bvh, alb))
+        ffs.append(ff)
+        te = orc.default_t_eps(sc.surfels)
+        Fo, _ = orc.ff_matrix(sc.surfels, R, sc.seed, te, sc.t_min, 0)
+        Fos.append(Fo)
+        Eos.append(orc.direct_light(sc.surfels, sc.albedo, sc.light_pos, sc.light_I, K))
+    batch = g.batch_create(ffs, lights, K)
+    rho = torch.cat(rhos)
+    E = batch.pack(Es)
+    gBs = [scenes.seeded_array((n, lt, K, 3), seed=500 + s, lo=-1, hi=1) for s, (n, lt) in
+           enumerate(zip(sizes, lights))]
+    B = batch.unpack(g.batch_transport_solve(batch, rho, E, nb))
+    gE, gr, gF = g.batch_transport_backward(batch, rho, _flat(gBs))
+    gE = batch.unpack(gE)
+    r0 = 0
+    for sc, Fo, Eo, Bb, gEb, gB in zip(rooms, Fos, Eos, B, gE, gBs):
+        n = sc.n
+        rho_o = orc.rho(sc.surfels["opacity"], sc.albedo)
+        Bo, tp = orc.bounce(Fo, rho_o, Eo, nb, keep_tape=True)
+        gEo, gro, _ = orc.adjoint(Fo, rho_o, tp, gB)
+        assert rel_err(Bb.cpu().numpy(), Bo) < TOL
+        assert rel_err(gEb.cpu().numpy(), gEo) < TOL
+        assert rel_err(gr[r0:r0 + n].cpu().numpy(), gro) < TOL
+        r0 += n
