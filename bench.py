@@ -69,9 +69,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=24)
-    ap.add_argument("--workload", default="fruit_bowl", choices=["fruit_bowl", "multi_light"],
+    ap.add_argument("--workload", default="fruit_bowl", choices=["fruit_bowl", "multi_light", "uneven_batch"],
                     help="fruit_bowl: the 100k sparse path (default); multi_light: the 32k box room with 100 "
-                         "lights on the dense BF16 path")
+                         "lights on the dense BF16 path; uneven_batch: 64 cluster rooms of 2k-65k surfels in one "
+                         "batch")
     ap.add_argument("--fp32-lights", type=int, default=10,
                     help="multi_light: lights timed on the plain FP32 per-light path (scaled to all lights)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -94,6 +95,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "multi_light":
         return multi_light(args, g, scenes, torch, np)
+    if args.workload == "uneven_batch":
+        return uneven_batch(args, g, scenes, torch, np)
     sc = scenes.make_config("fruit_bowl", n=args.n)
     N, R, K, nb, topk, Lt = sc.n, sc.R, sc.K, sc.n_bounces, sc.topk, sc.n_lights
     dev = torch.device("cuda")
@@ -455,6 +458,107 @@ def multi_light(args, g, scenes, torch, np):
         result["err_vs_fp64"] = dense_slice_errors(g, torch, np, N, 256, Lt, K, nb)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = dense_cpu_baseline(np, N, int(nnz // N), Lt, K, nb)
+    print(json.dumps(result))
+
+
+def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
+    """64 cluster rooms with log-uniform surfel counts in [2048, 65536]
+    (1.19 M surfels, 152 M rays at R = 128), K = 9, 8 bounces, each room
+    lit by U{1..4} lights, F truncated to 512 entries per row.  A step is the
+    whole path: per-scene BVH, form factors and direct light, then one batch
+    solve and backward (persistent launches, tuned lanes per row, captured
+    bounce loop).  The same transport run scene by scene is timed beside it."""
+    rooms = scenes.uneven_batch(lights=lights)
+    K, R, nb = rooms[0].K, rooms[0].R, rooms[0].n_bounces
+    dev = torch.device("cuda")
+    surs = [{k: torch.from_numpy(v).to(dev) for k, v in sc.surfels.items()} for sc in rooms]
+    albs = [torch.from_numpy(sc.albedo).to(dev) for sc in rooms]
+    lps = [torch.from_numpy(sc.light_pos).to(dev) for sc in rooms]
+    lIs = [torch.from_numpy(sc.light_I).to(dev) for sc in rooms]
+    Lts = [sc.n_lights for sc in rooms]
+    st = {"bvh": [None] * len(rooms), "ff": [None] * len(rooms)}
+
+    def step():
+        Es, rhos = [], []
+        for s, sc in enumerate(rooms):
+            bvh = g.build_bvh(surs[s], st["bvh"][s])
+            st["bvh"][s] = bvh
+            st["ff"][s] = g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, topk=topk, ff=st["ff"][s], records=False)
+            Es.append(g.direct_light(bvh, albs[s], lps[s], lIs[s], K))
+            rhos.append(g.reflectance(bvh, albs[s]))
+        batch = g.batch_create(st["ff"], Lts, K, batch=st.get("batch"))
+        rho = torch.cat(rhos)
+        E = batch.pack(Es)
+        if "gB" not in st:
+            st["gB"] = torch.from_numpy(scenes.seeded_array((E.shape[0],), seed=98, lo=-1e-3, hi=1e-3)).to(dev)
+        B = g.batch_transport_solve(batch, rho, E, nb)
+        out = g.batch_transport_backward(batch, rho, st["gB"])
+        st.update(batch=batch, rho=rho, E=E, rhos=rhos, Es=Es)
+        return B, out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.gsrad.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.gsrad.profile_report()
+    g.gsrad.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    batch = st["batch"]
+    info = batch.info()
+
+    def avg(name):
+        return prof[name]["total_ms"] / args.steps if name in prof else 0.0
+
+    t_batch = avg("batch_bounces") + avg("batch_adjoint") + avg("batch_sddmm") + avg("transpose")
+    # the same transport, one scene at a time (unbatched launches)
+    gBs = batch.unpack(st["gB"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for s in range(len(rooms)):
+        _, tp = g.transport_solve(st["ff"][s], st["rhos"][s], st["Es"][s], nb)
+        g.transport_backward(st["ff"][s], tp, st["rhos"][s], gBs[s].contiguous())
+    torch.cuda.synchronize()
+    t_scene = (time.perf_counter() - t2) * 1e3
+    rays = sum(sc.n for sc in rooms) * R
+    phases = {k: v["total_ms"] / args.steps for k, v in prof.items()}
+    bb = prof.get("batch_bounces", {}).get("avg_ms", 0.0)
+    _, nnz = batch.ff().info()
+    vals = info["vals"]
+    per_bounce = nnz * 8 + 3 * vals * 4.0      # F entries + read B, E, write B (algorithmic)
+    achieved = per_bounce * nb / (bb * 1e-3) / 1e9 if bb > 0 else None
+    result = {
+        "metric": "fwd+bwd transport solves/s over a batch of 64 uneven scenes",
+        "value": 1e3 / ms,
+        "unit": "batch solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"64 cluster rooms, {sum(sc.n for sc in rooms)} surfels (2048-65536 each), "
+                               f"U{{{lights[0]}..{lights[1]}}} lights per room, R={R}, top-{topk} F, K={K}, "
+                               f"{nb} bounces, fwd+bwd",
+                   "scenes": len(rooms), "surfels": sum(sc.n for sc in rooms), "lights": sum(Lts),
+                   "rays": rays, "nnz": nnz, "values": vals},
+        "batch_transport_ms": t_batch,
+        "per_scene_transport_ms": t_scene,
+        "speedup_vs_per_scene": t_scene / t_batch if t_batch > 0 else None,
+        "lanes_per_row": {"bounce": info["lanes_bounce"], "adjoint": info["lanes_adjoint"]},
+        "grays_per_s": rays / (avg("ff_trace") * 1e-3) / 1e9 if avg("ff_trace") > 0 else None,
+        "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())},
+        "roofline": {"kernel": "batch_bounces", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                     "bytes_per_launch": per_bounce, "launches_per_graph": nb},
+    }
     print(json.dumps(result))
 
 

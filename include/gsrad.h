@@ -264,7 +264,9 @@ gsrad_status gsrad_tape_grad_F_dense(const gsrad_tape *tape, float *grad_F_out, 
  * are one [n_s][lights[s]][K][3] block, blocks concatenated in scene order
  * (val_off_s = sum_{t<s} n_t C_t values before it).  lights is a host
  * array of n_scenes entries; the scenes' handles may be destroyed after
- * the call.
+ * the call.  *batch == NULL creates a batch; an existing batch with the
+ * same scene sizes, lights and K is refilled with the new operators and
+ * keeps its tuned shapes and captured loop.
  *
  * gsrad_batch_transport_solve runs the bounces of Eq. final-radiosity on
  * every scene at once: each bounce is one persistent launch in which

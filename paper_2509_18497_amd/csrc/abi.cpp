@@ -223,6 +223,8 @@ struct gsrad_batch {
     int64_t rows = 0, vals = 0;
     gsrad_ff *F = nullptr;   // block-diagonal, owned
     DevBuf row_off, val_off, scene_C, row_scene, order, counter, temp;
+    std::vector<int64_t> scene_rows;   // row offsets (host copy)
+    std::vector<int32_t> scene_cols;   // C_s (host copy)
     // forward iterates B^(0..nb-1) and adjoint iterates lambda^(1..nb)
     int nb = -1;
     DevBuf Bt, Lt, lam0;
@@ -1020,9 +1022,16 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
     if (roff[n_scenes] >= ((int64_t)1 << 31) || eoff[n_scenes] >= ((int64_t)1 << 32))
         return einval("gsrad_batch_create: batch too large (rows < 2^31, entries < 2^32)");
     hipStream_t st = S(stream);
-    gsrad_batch *b = new gsrad_batch();
+    // an existing batch of the same scene layout is refilled in place: its
+    // tuned lanes per row stay, and so does its captured bounce loop while
+    // no buffer has to grow
+    gsrad_batch *b = *batch;
+    const bool reuse = b && b->S == n_scenes && b->K == K && b->rows == roff[n_scenes] && b->vals == voff[n_scenes] &&
+                       b->scene_rows == std::vector<int64_t>(roff.begin(), roff.end()) && b->scene_cols == Cs;
+    const bool created = !reuse;
+    if (created) b = new gsrad_batch();
     auto fail = [&](gsrad_status e) {
-        delete b;
+        if (created) delete b;
         return e;
     };
     gsrad_status e;
@@ -1030,8 +1039,11 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
     b->K = K;
     b->rows = roff[n_scenes];
     b->vals = voff[n_scenes];
-    b->F = new gsrad_ff();
+    b->scene_rows.assign(roff.begin(), roff.end());
+    b->scene_cols = Cs;
+    if (!b->F) b->F = new gsrad_ff();
     gsrad_ff *F = b->F;
+    const void *old_ptrs[3] = {F->row_ptr.p, F->col.p, F->val.p};
     const int64_t rows = b->rows, nnz = eoff[n_scenes];
     if ((e = F->row_ptr.ensure((size_t)(rows + 1) * 8, "batch row_ptr")) != GSRAD_OK) return fail(e);
     if ((e = F->col.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "batch col")) != GSRAD_OK) return fail(e);
@@ -1055,6 +1067,8 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
     F->n = rows;
     F->nnz = nnz;
     F->max_row = max_row;
+    F->has_t = false;
+    if (old_ptrs[0] != F->row_ptr.p || old_ptrs[1] != F->col.p || old_ptrs[2] != F->val.p) b->drop_graph();
     if ((e = b->row_off.ensure((size_t)(n_scenes + 1) * 8, "scene rows")) != GSRAD_OK) return fail(e);
     if ((e = b->val_off.ensure((size_t)(n_scenes + 1) * 8, "scene values")) != GSRAD_OK) return fail(e);
     if ((e = b->scene_C.ensure((size_t)n_scenes * 4, "scene columns")) != GSRAD_OK) return fail(e);
@@ -1075,6 +1089,7 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
         return fail(e);
     // the host vectors above are sources of asynchronous copies
     if ((e = check_hip(hipStreamSynchronize(st), "batch create sync")) != GSRAD_OK) return fail(e);
+    b->nb = -1;
     *batch = b;
     return GSRAD_OK;
 }

@@ -278,12 +278,13 @@ class _BorrowedFF(FF):
     _destroy = None
 
 
-def batch_create(ffs, lights, K: int, stream=None) -> Batch:
-    """Join the scenes' operators into one batch (scene s lit by lights[s] lights)."""
+def batch_create(ffs, lights, K: int, batch: Optional[Batch] = None, stream=None) -> Batch:
+    """Join the scenes' operators into one batch (scene s lit by lights[s]
+    lights); an existing batch of the same layout is refilled in place."""
     S = len(ffs)
     arr = (ctypes.c_void_p * S)(*[f.h.value for f in ffs])
     lt = (ctypes.c_int32 * S)(*[int(x) for x in lights])
-    b = Batch()
+    b = batch if batch is not None else Batch()
     _check(lib().gsrad_batch_create(arr, S, lt, int(K), ctypes.byref(b.h), _stream(stream)), "gsrad_batch_create")
     b.scene_rows = [f.info()[0] for f in ffs]
     b.lights = [int(x) for x in lights]

@@ -170,3 +170,24 @@ def test_batch_of_ray_cast_cluster_rooms(g, orc):
         assert rel_err(gEb.cpu().numpy(), gEo) < TOL
         assert rel_err(gr[r0:r0 + n].cpu().numpy(), gro) < TOL
         r0 += n
+
+
+def test_batch_refill_keeps_shape_and_follows_new_values(g):
+    K, nb = 4, 3
+    sc = _scenes(g, K)
+    batch = g.batch_create([x["ff"] for x in sc], [x["lt"] for x in sc], K)
+    rho = dev(np.concatenate([x["rho"] for x in sc]))
+    E = _flat([x["E"] for x in sc])
+    g.batch_transport_solve(batch, rho, E, nb)
+    lanes = batch.info()["lanes_bounce"]
+    # new values in every scene's F (same sizes): the batch is refilled in place
+    ffs2 = []
+    for s, x in enumerate(sc):
+        rp, c, v = scenes.seeded_csr(x["n"], ROWLEN[s] // 2 + 1, seed=900 + s)
+        ffs2.append(g.ff_from_csr(dev(rp), dev(c), dev(v)))
+    same = g.batch_create(ffs2, [x["lt"] for x in sc], K, batch=batch)
+    assert same is batch and batch.info()["lanes_bounce"] == lanes
+    B = batch.unpack(g.batch_transport_solve(batch, rho, E, nb))
+    for x, f2, Bb in zip(sc, ffs2, B):
+        Bs, _ = g.transport_solve(f2, dev(x["rho"]), dev(x["E"]), nb, keep_tape=False)
+        assert torch.equal(Bb, Bs)
