@@ -51,20 +51,33 @@ __global__ void __launch_bounds__(256) k_ragged_spmm(BatchDev bd, const int64_t 
         for (int c0 = 0; c0 < C; c0 += LPR) {
             const int c = c0 + lig;
             const bool on = c < C;
-            const int colour = c % 3;
+            const int cc = on ? c : 0;   // lanes past C gather column 0 and discard it
+            const int colour = cc % 3;
             float acc = 0.0f;
             for (int64_t k0 = b; k0 < e; k0 += LPR) {
                 const int64_t kk = k0 + lig;
-                const int jv = kk < e ? col[kk] : 0;
+                const int jv = kk < e ? col[kk] : (int)r0;
                 const float vv = kk < e ? val[kk] : 0.0f;
                 const int m = (int)min<int64_t>(LPR, e - k0);
-                for (int t = 0; t < m; ++t) {
-                    const int64_t j = __shfl(jv, gbase + t, 64);
-                    const float v = __shfl(vv, gbase + t, 64);
-                    if (on) {
-                        const float x = in[base + (j - r0) * C + c];
-                        acc = ADJ ? __builtin_fmaf(v * rho[j * 3 + colour], x, acc) : __builtin_fmaf(v, x, acc);
+                int t = 0;
+                // eight gathers in flight, added in CSR order
+                for (; t + 8 <= m; t += 8) {
+                    float w[8], x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int64_t j = __shfl(jv, gbase + t + u, 64);
+                        w[u] = __shfl(vv, gbase + t + u, 64);
+                        if (ADJ) w[u] *= rho[j * 3 + colour];
+                        x[u] = in[base + (j - r0) * C + cc];
                     }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc = __builtin_fmaf(w[u], x[u], acc);
+                }
+                for (; t < m; ++t) {
+                    const int64_t j = __shfl(jv, gbase + t, 64);
+                    float w = __shfl(vv, gbase + t, 64);
+                    if (ADJ) w *= rho[j * 3 + colour];
+                    acc = __builtin_fmaf(w, in[base + (j - r0) * C + cc], acc);
                 }
             }
             if (on) {

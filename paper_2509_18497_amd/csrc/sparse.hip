@@ -51,6 +51,47 @@ __global__ void __launch_bounds__(256) k_transpose_gather(const uint32_t *__rest
     if (perm) perm[k] = e;
 }
 
+// sum over the entries e in [b, e_end) of w_e * in[col_e][c] in CSR order,
+// w_e = val_e (bounce) or val_e * rho[col_e][c % 3] (adjoint).  The wave
+// reads 64 entries at a time and issues eight row gathers before it adds
+// them, so eight loads are in flight per wave; the additions keep the CSR
+// order, so the result is the plain sequential sum.  Lanes past C gather
+// column 0 and discard it.
+template <bool ADJ>
+__device__ __forceinline__ float gather_row(const int32_t *__restrict__ col, const float *__restrict__ val,
+                                            int64_t b, int64_t e_end, const float *__restrict__ in,
+                                            const float *__restrict__ rho, int C, int c, int lane) {
+    const int cc = c < C ? c : 0;
+    const int colour = cc % 3;
+    float acc = 0.0f;
+    for (int64_t k0 = b; k0 < e_end; k0 += 64) {
+        const int64_t kk = k0 + lane;
+        const int jv = kk < e_end ? col[kk] : 0;
+        const float vv = kk < e_end ? val[kk] : 0.0f;
+        const int m = (int)min<int64_t>(64, e_end - k0);
+        int q = 0;
+        for (; q + 8 <= m; q += 8) {
+            float w[8], x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = __builtin_amdgcn_readlane(jv, q + u);
+                w[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), q + u));
+                if (ADJ) w[u] *= rho[(int64_t)j * 3 + colour];
+                x[u] = in[(int64_t)j * C + cc];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = __builtin_fmaf(w[u], x[u], acc);
+        }
+        for (; q < m; ++q) {
+            const int j = __builtin_amdgcn_readlane(jv, q);
+            float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), q));
+            if (ADJ) w *= rho[(int64_t)j * 3 + colour];
+            acc = __builtin_fmaf(w, in[(int64_t)j * C + cc], acc);
+        }
+    }
+    return acc;
+}
+
 // B_out[row] = E[row] + rho[row] * sum_e val[e] * B_in[col[e]]
 __global__ void __launch_bounds__(256) k_bounce(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                 const float *__restrict__ val, int64_t n, int C,
@@ -63,20 +104,8 @@ __global__ void __launch_bounds__(256) k_bounce(const int64_t *__restrict__ row_
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
     for (int c0 = 0; c0 < C; c0 += 64) {
         const int c = c0 + lane;
-        const bool on = c < C;
-        float acc = 0.0f;
-        for (int64_t k0 = b; k0 < e; k0 += 64) {
-            const int64_t kk = k0 + lane;
-            const int jv = kk < e ? col[kk] : 0;
-            const float vv = kk < e ? val[kk] : 0.0f;
-            const int m = (int)min<int64_t>(64, e - k0);
-            for (int q = 0; q < m; ++q) {
-                const int j = __builtin_amdgcn_readlane(jv, q);
-                const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), q));
-                if (on) acc = __builtin_fmaf(v, Bin[(int64_t)j * C + c], acc);
-            }
-        }
-        if (on) Bout[row * C + c] = __builtin_fmaf(rho[row * 3 + c % 3], acc, E[row * C + c]);
+        const float acc = gather_row<false>(col, val, b, e, Bin, nullptr, C, c, lane);
+        if (c < C) Bout[row * C + c] = __builtin_fmaf(rho[row * 3 + c % 3], acc, E[row * C + c]);
     }
 }
 
@@ -92,21 +121,8 @@ __global__ void __launch_bounds__(256) k_adjoint(const int64_t *__restrict__ row
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
     for (int c0 = 0; c0 < C; c0 += 64) {
         const int c = c0 + lane;
-        const bool on = c < C;
-        const int colour = c % 3;
-        float acc = 0.0f;
-        for (int64_t k0 = b; k0 < e; k0 += 64) {
-            const int64_t kk = k0 + lane;
-            const int jv = kk < e ? col[kk] : 0;
-            const float vv = kk < e ? val[kk] : 0.0f;
-            const int m = (int)min<int64_t>(64, e - k0);
-            for (int q = 0; q < m; ++q) {
-                const int j = __builtin_amdgcn_readlane(jv, q);
-                const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv), q));
-                if (on) acc = __builtin_fmaf(v * rho[(int64_t)j * 3 + colour], lam_in[(int64_t)j * C + c], acc);
-            }
-        }
-        if (on) {
+        const float acc = gather_row<true>(col, val, b, e, lam_in, rho, C, c, lane);
+        if (c < C) {
             lam_out[row * C + c] = acc;
             gE[row * C + c] += acc;
         }
@@ -153,6 +169,73 @@ __global__ void __launch_bounds__(256) k_sddmm(const int64_t *__restrict__ row_p
         gr0 = __builtin_fmaf(f, s0, gr0);
         gr1 = __builtin_fmaf(f, s1, gr1);
         gr2 = __builtin_fmaf(f, s2, gr2);
+    }
+    if (lane == 0 && grad_rho) {
+        grad_rho[row * 3 + 0] = gr0;
+        grad_rho[row * 3 + 1] = gr1;
+        grad_rho[row * 3 + 2] = gr2;
+    }
+}
+
+// The same sums for up to 8 bounces and C <= 64 (one column per lane): each
+// lane keeps its column of rho_row-free lambda^(k+1)[row] for every k in
+// registers, and four entries are gathered at a time (32 loads in flight)
+// before their per-colour sums are reduced over the wave.  Per entry and
+// lane the bounce sum runs in the same order, and the reductions and the
+// grad_rho accumulation are those of k_sddmm, so both give the same bits.
+constexpr int kSddmmMaxNb = 8;
+
+__global__ void __launch_bounds__(256) k_sddmm_fast(const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                    int64_t n, int C, int nb, const float *__restrict__ Bt,
+                                                    const float *__restrict__ Lt, const float *__restrict__ rho,
+                                                    float *__restrict__ grad_F, float *__restrict__ grad_rho,
+                                                    int64_t nblocks) {
+    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (row >= n) return;
+    const int lane = __lane_id();
+    const bool on = lane < C;
+    const int c = on ? lane : 0;
+    const int colour = c % 3;
+    const int64_t NC = n * (int64_t)C;
+    float lr[kSddmmMaxNb];
+#pragma unroll
+    for (int q = 0; q < kSddmmMaxNb; ++q) lr[q] = (q < nb && on) ? Lt[q * NC + row * C + c] : 0.0f;
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    const float r0 = rho[row * 3 + 0], r1 = rho[row * 3 + 1], r2 = rho[row * 3 + 2];
+    float gr0 = 0.0f, gr1 = 0.0f, gr2 = 0.0f;
+    constexpr int kE = 4;
+    for (int64_t k0 = b; k0 < e; k0 += kE) {
+        const int m = (int)min<int64_t>(kE, e - k0);
+        float sv[kE];
+#pragma unroll
+        for (int u = 0; u < kE; ++u) {
+            const int64_t j = u < m ? col[k0 + u] : col[k0];
+            float x[kSddmmMaxNb];
+#pragma unroll
+            for (int q = 0; q < kSddmmMaxNb; ++q) x[q] = q < nb ? Bt[q * NC + j * C + c] : 0.0f;
+            float sum = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kSddmmMaxNb; ++q)
+                if (q < nb) sum = __builtin_fmaf(lr[q], x[q], sum);
+            sv[u] = on ? sum : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kE; ++u) {
+            if (u >= m) break;
+            float s0 = colour == 0 ? sv[u] : 0.0f;
+            float s1 = colour == 1 ? sv[u] : 0.0f;
+            float s2 = colour == 2 ? sv[u] : 0.0f;
+            s0 = wave_sum(s0);
+            s1 = wave_sum(s1);
+            s2 = wave_sum(s2);
+            const int64_t k = k0 + u;
+            if (lane == 0 && grad_F) grad_F[k] = r0 * s0 + r1 * s1 + r2 * s2;
+            const float f = val[k];
+            gr0 = __builtin_fmaf(f, s0, gr0);
+            gr1 = __builtin_fmaf(f, s1, gr1);
+            gr2 = __builtin_fmaf(f, s2, gr2);
+        }
     }
     if (lane == 0 && grad_rho) {
         grad_rho[row * 3 + 0] = gr0;
@@ -272,8 +355,12 @@ gsrad_status launch_adjoint(const Csr &FT, int C, const float *lam_in, const flo
 gsrad_status launch_sddmm(const Csr &F, int C, int nb, const float *Btape, const float *Ltape, const float *rho,
                           float *grad_F, float *grad_rho, hipStream_t st) {
     const unsigned g = row_blocks(F.n);
-    hipLaunchKernelGGL(k_sddmm, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, nb, Btape, Ltape, rho,
-                       grad_F, grad_rho, (int64_t)g);
+    if (C <= 64 && nb <= kSddmmMaxNb)
+        hipLaunchKernelGGL(k_sddmm_fast, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, nb, Btape, Ltape,
+                           rho, grad_F, grad_rho, (int64_t)g);
+    else
+        hipLaunchKernelGGL(k_sddmm, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, nb, Btape, Ltape, rho,
+                           grad_F, grad_rho, (int64_t)g);
     return check_hip(hipGetLastError(), "sddmm launch");
 }
 
