@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 97724.15e6, "write": 10924.16e6,
+    "ff_trace": {"fetch": 99940.56e6, "write": 10913.04e6,
                  "files": ["trace.hip", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "5f385d6be018b298ed1c6345c092a0361fc29f60a37b57a96bd69a366aa6406d",
+                 "sha256": "1f79866158039277361b67291e303b4cb8297e74ad628abbc99dbbd8edb7f2ea",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
 }
 
@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--n", type=int, default=100_000, help="surfel count (100k is the measured workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-receivers", type=int, default=24)
+    ap.add_argument("--cpu-receivers", type=int, default=200,
+                    help="receivers of the bounded oracle sample (about 15 s of host work)")
     ap.add_argument("--workload", default="fruit_bowl", choices=["fruit_bowl", "multi_light", "uneven_batch"],
                     help="fruit_bowl: the 100k sparse path (default); multi_light: the 32k box room with 100 "
                          "lights on the dense BF16 path; uneven_batch: 64 cluster rooms of 2k-65k surfels in one "

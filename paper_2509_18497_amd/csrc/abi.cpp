@@ -1249,7 +1249,8 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
     }
     if (grad_F || grad_rho) {
         ProfScope ps("batch_sddmm", st);
-        GS_TRY(launch_ragged_sddmm(b->dev(), b->F->csr(), nb, vals, b->Bt.as<float>(), L, rho, grad_F, grad_rho,
+        const int max_C = *std::max_element(b->scene_cols.begin(), b->scene_cols.end());
+        GS_TRY(launch_ragged_sddmm(b->dev(), b->F->csr(), nb, vals, max_C, b->Bt.as<float>(), L, rho, grad_F, grad_rho,
                                    b->counter.as<uint32_t>(), st));
     }
     return GSRAD_OK;

@@ -146,6 +146,97 @@ __global__ void __launch_bounds__(256) k_ragged_sddmm(BatchDev bd, const int64_t
     }
 }
 
+// The same sums for scenes with up to 8 bounces and C <= 128: each lane
+// keeps its (at most two) columns of lambda^(k+1)[row] in registers for
+// every k, and four entries are gathered at a time.  Per lane the column
+// chunks and bounces are added in the order of k_ragged_sddmm, and the
+// reductions are the same, so both give the same bits.
+constexpr int kFastNb = 8;
+
+__global__ void __launch_bounds__(256) k_ragged_sddmm_fast(BatchDev bd, const int64_t *__restrict__ row_ptr,
+                                                           const int32_t *__restrict__ col,
+                                                           const float *__restrict__ val, int nb, int64_t vals,
+                                                           const float *__restrict__ Bt, const float *__restrict__ Lt,
+                                                           const float *__restrict__ rho, float *__restrict__ grad_F,
+                                                           float *__restrict__ grad_rho, uint32_t *counter) {
+    const int lane = __lane_id();
+    for (;;) {
+        const int64_t q = next_row<64>(counter, lane, 0);
+        if (q >= bd.rows) break;
+        const int64_t row = bd.order[q];
+        const int s = bd.row_scene[row];
+        const int C = bd.scene_C[s];
+        const int64_t r0 = bd.row_off[s], base = bd.val_off[s];
+        const int64_t lr = row - r0;
+        const bool on0 = lane < C, on1 = lane + 64 < C;
+        const int c0 = on0 ? lane : 0, c1 = on1 ? lane + 64 : 0;
+        const int col0 = c0 % 3, col1 = c1 % 3;
+        float l0[kFastNb], l1[kFastNb];
+#pragma unroll
+        for (int t = 0; t < kFastNb; ++t) {
+            l0[t] = (t < nb && on0) ? Lt[t * vals + base + lr * C + c0] : 0.0f;
+            l1[t] = (t < nb && on1) ? Lt[t * vals + base + lr * C + c1] : 0.0f;
+        }
+        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+        const float rr0 = rho[row * 3 + 0], rr1 = rho[row * 3 + 1], rr2 = rho[row * 3 + 2];
+        float gr0 = 0.0f, gr1 = 0.0f, gr2 = 0.0f;
+        constexpr int kE = 4;
+        for (int64_t k0 = b; k0 < e; k0 += kE) {
+            const int m = (int)min<int64_t>(kE, e - k0);
+            float a0[kE], a1[kE];
+#pragma unroll
+            for (int u = 0; u < kE; ++u) {
+                const int64_t j = (u < m ? col[k0 + u] : col[k0]) - r0;
+                float x0[kFastNb], x1[kFastNb];
+#pragma unroll
+                for (int t = 0; t < kFastNb; ++t) {
+                    x0[t] = t < nb ? Bt[t * vals + base + j * C + c0] : 0.0f;
+                    x1[t] = (t < nb && on1) ? Bt[t * vals + base + j * C + c1] : 0.0f;
+                }
+                float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+                for (int t = 0; t < kFastNb; ++t)
+                    if (t < nb) {
+                        s0 = __builtin_fmaf(l0[t], x0[t], s0);
+                        s1 = __builtin_fmaf(l1[t], x1[t], s1);
+                    }
+                a0[u] = on0 ? s0 : 0.0f;
+                a1[u] = on1 ? s1 : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kE; ++u) {
+                if (u >= m) break;
+                // chunk 0 then chunk 1, as the column loop of k_ragged_sddmm adds them
+                float s0 = col0 == 0 ? a0[u] : 0.0f;
+                float s1 = col0 == 1 ? a0[u] : 0.0f;
+                float s2 = col0 == 2 ? a0[u] : 0.0f;
+                if (on1) {
+                    s0 += col1 == 0 ? a1[u] : 0.0f;
+                    s1 += col1 == 1 ? a1[u] : 0.0f;
+                    s2 += col1 == 2 ? a1[u] : 0.0f;
+                }
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    s0 += __shfl_xor(s0, o, 64);
+                    s1 += __shfl_xor(s1, o, 64);
+                    s2 += __shfl_xor(s2, o, 64);
+                }
+                const int64_t k = k0 + u;
+                if (lane == 0 && grad_F) grad_F[k] = rr0 * s0 + rr1 * s1 + rr2 * s2;
+                const float f = val[k];
+                gr0 = __builtin_fmaf(f, s0, gr0);
+                gr1 = __builtin_fmaf(f, s1, gr1);
+                gr2 = __builtin_fmaf(f, s2, gr2);
+            }
+        }
+        if (lane == 0 && grad_rho) {
+            grad_rho[row * 3 + 0] = gr0;
+            grad_rho[row * 3 + 1] = gr1;
+            grad_rho[row * 3 + 2] = gr2;
+        }
+    }
+}
+
 __global__ void k_reset_counter(uint32_t *counter) {
     if (threadIdx.x == 0) counter[0] = 0u;
 }
@@ -232,12 +323,16 @@ gsrad_status launch_ragged_spmm(const BatchDev &bd, const Csr &F, int lpr, bool 
     return check_hip(hipGetLastError(), "ragged product launch");
 }
 
-gsrad_status launch_ragged_sddmm(const BatchDev &bd, const Csr &F, int nb, int64_t vals, const float *Bt,
+gsrad_status launch_ragged_sddmm(const BatchDev &bd, const Csr &F, int nb, int64_t vals, int max_C, const float *Bt,
                                  const float *Lt, const float *rho, float *grad_F, float *grad_rho, uint32_t *counter,
                                  hipStream_t st) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-    hipLaunchKernelGGL(k_ragged_sddmm, dim3(persistent_blocks()), dim3(256), 0, st, bd, F.row_ptr, F.col, F.val, nb,
-                       vals, Bt, Lt, rho, grad_F, grad_rho, counter);
+    if (nb <= kFastNb && max_C <= 128)
+        hipLaunchKernelGGL(k_ragged_sddmm_fast, dim3(persistent_blocks()), dim3(256), 0, st, bd, F.row_ptr, F.col,
+                           F.val, nb, vals, Bt, Lt, rho, grad_F, grad_rho, counter);
+    else
+        hipLaunchKernelGGL(k_ragged_sddmm, dim3(persistent_blocks()), dim3(256), 0, st, bd, F.row_ptr, F.col, F.val,
+                           nb, vals, Bt, Lt, rho, grad_F, grad_rho, counter);
     return check_hip(hipGetLastError(), "ragged sddmm launch");
 }
 

@@ -26,7 +26,8 @@ gsrad_status launch_ragged_spmm(const BatchDev &bd, const Csr &F, int lpr, bool 
                                 const float *E, const float *rho, float *out, float *gE, uint32_t *counter,
                                 hipStream_t st);
 // grad_F at the stored entries and grad_rho from the tapes [nb][vals]
-gsrad_status launch_ragged_sddmm(const BatchDev &bd, const Csr &F, int nb, int64_t vals, const float *Bt,
+// (max_C: the largest C_s of the batch)
+gsrad_status launch_ragged_sddmm(const BatchDev &bd, const Csr &F, int nb, int64_t vals, int max_C, const float *Bt,
                                  const float *Lt, const float *rho, float *grad_F, float *grad_rho, uint32_t *counter,
                                  hipStream_t st);
 
