@@ -198,9 +198,13 @@ __device__ __forceinline__ float transmit(float c, float g) { return exp_fx(-__f
 __device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix, float hiy, float hiz, float ox,
                                      float oy, float oz, float ix, float iy, float iz, float t0, float t1,
                                      float &tn) {
-    const float ax = (lox - ox) * ix, bx = (hix - ox) * ix;
-    const float ay = (loy - oy) * iy, by = (hiy - oy) * iy;
-    const float az = (loz - oz) * iz, bz = (hiz - oz) * iz;
+    // (lo - o) / d as fma(lo, 1/d, -o/d): one operation per plane (o/d is
+    // loop-invariant); its rounding, a few 1e-8 of |o| in distance, is far
+    // inside the boxes' inflation (4e-7 |p| + t_eps)
+    const float ox_ = ox * ix, oy_ = oy * iy, oz_ = oz * iz;
+    const float ax = __builtin_fmaf(lox, ix, -ox_), bx = __builtin_fmaf(hix, ix, -ox_);
+    const float ay = __builtin_fmaf(loy, iy, -oy_), by = __builtin_fmaf(hiy, iy, -oy_);
+    const float az = __builtin_fmaf(loz, iz, -oz_), bz = __builtin_fmaf(hiz, iz, -oz_);
     const float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t0));
     const float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t1));
     tn = tmin;
