@@ -341,6 +341,19 @@ gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, c
                          int32_t K, double *out_host, void *stream);
 
 /*
+ * Reciprocity of the estimated operator (Sec. 5.3: A_i F_ij = A_j F_ji
+ * holds for the exact form factors, with A the App. E effective areas of
+ * gsrad_effective_area).  FP64 over the stored entries, the mirror entry
+ * F_ji found in row j (0 when it is not stored, e.g. cut by top-k):
+ *   out_host[0] = sum |A_i F_ij - A_j F_ji| / sum A_i F_ij
+ *   out_host[1] = max |A_i F_ij - A_j F_ji| / max(A_i F_ij, A_j F_ji)
+ * The ray-cast estimate is reciprocal only in expectation and up to the
+ * receiver-centre approximation, so these measure noise plus that bias.
+ * bvh and ff must describe the same n surfels.
+ */
+gsrad_status gsrad_check_reciprocity(const gsrad_bvh *bvh, const gsrad_ff *ff, double *out_host, void *stream);
+
+/*
  * Timing of the library's phases with HIP events recorded on the caller's
  * stream around each kernel group (bvh_build, ff_trace, ff_aggregate,
  * ff_csr, direct_light, bounce, transpose, adjoint, sddmm, opacity_records,

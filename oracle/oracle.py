@@ -268,6 +268,26 @@ def _rho_cols(rho_arr, C):
     return np.tile(rho_arr, (1, C // 3))
 
 
+def reciprocity(F, area):
+    """Reciprocity of an operator against the areas (Sec. 5.3: A_i F_ij =
+    A_j F_ji for exact form factors), over the stored entries of F, the
+    mirror entry taken as 0 where F_ji is not stored:
+    (sum |A_i F_ij - A_j F_ji| / sum A_i F_ij,
+     max |A_i F_ij - A_j F_ji| / max(A_i F_ij, A_j F_ji))."""
+    F = sp.csr_matrix(F, dtype=np.float64)
+    A = np.asarray(area, np.float64)
+    rows = np.repeat(np.arange(F.shape[0]), np.diff(F.indptr))
+    cols = F.indices
+    a = A[rows] * F.data
+    Ft = F.T.tocsr()
+    mirror = np.asarray(Ft[rows, cols]).ravel()     # F[j, i]
+    b = A[cols] * mirror
+    d = np.abs(a - b)
+    m = np.maximum(a, b)
+    rel = np.where(m > 0, d / np.where(m > 0, m, 1.0), 0.0)
+    return (float(d.sum() / a.sum()) if a.sum() > 0 else 0.0), (float(rel.max()) if rel.size else 0.0)
+
+
 def bounce(F, rho_arr, E, n_bounces: int, keep_tape: bool = False):
     """B^(0) = E, B^(k+1) = E + rho * (F B^(k)), k < n (Eq. final-radiosity,
     scalar Lambertian transfer applied to every SH coefficient and light).

@@ -957,6 +957,23 @@ gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, c
     return GSRAD_OK;
 }
 
+gsrad_status gsrad_check_reciprocity(const gsrad_bvh *bvh, const gsrad_ff *ff, double *out_host, void *stream) {
+    if (!bvh || !ff || !out_host) return einval("gsrad_check_reciprocity: null argument");
+    if (bvh->n != ff->n) return einval("gsrad_check_reciprocity: the BVH and F have different sizes");
+    hipStream_t st = S(stream);
+    gsrad_ff *f = const_cast<gsrad_ff *>(ff);
+    GS_TRY(f->err.ensure(128, "check accumulators"));
+    double *acc = reinterpret_cast<double *>(f->err.as<char>() + 64);
+    GS_TRY(check_hip(hipMemsetAsync(acc, 0, 24, st), "reciprocity zero"));
+    GS_TRY(launch_reciprocity(ff->csr(), bvh->B.area, acc, st));
+    double a[3];
+    GS_TRY(check_hip(hipMemcpyAsync(a, acc, sizeof(a), hipMemcpyDeviceToHost, st), "reciprocity copy"));
+    GS_TRY(check_hip(hipStreamSynchronize(st), "reciprocity sync"));
+    out_host[0] = a[1] > 0 ? a[0] / a[1] : 0.0;
+    out_host[1] = a[2];
+    return GSRAD_OK;
+}
+
 gsrad_status gsrad_profile_enable(int32_t on) {
     prof_clear();
     g_prof = on != 0;

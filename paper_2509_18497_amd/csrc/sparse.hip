@@ -280,6 +280,48 @@ __global__ void __launch_bounds__(256) k_check(const int64_t *__restrict__ row_p
     }
 }
 
+// Reciprocity of the estimated operator (A_i F_ij = A_j F_ji for the exact
+// form factors, App. E areas): per stored entry the FP64 difference with
+// its mirror entry F_ji (binary search in row j; 0 if not stored).
+// acc[0] += |A_i F_ij - A_j F_ji|, acc[1] += A_i F_ij,
+// acc[2] = max |A_i F_ij - A_j F_ji| / max(A_i F_ij, A_j F_ji) (bit order).
+__global__ void __launch_bounds__(256) k_reciprocity(const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                     int64_t n, const double *__restrict__ area, double *acc) {
+    const int64_t row = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / 64;
+    if (row >= n) return;
+    const int lane = __lane_id();
+    double sd = 0.0, sf = 0.0, mx = 0.0;
+    const double ai = area[row];
+    for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += 64) {
+        const int64_t j = col[k];
+        int64_t lo = row_ptr[j], hi = row_ptr[j + 1];
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (col[mid] < row) lo = mid + 1;
+            else hi = mid;
+        }
+        const double fji = (lo < row_ptr[j + 1] && col[lo] == row) ? (double)val[lo] : 0.0;
+        const double a = ai * (double)val[k], b = area[j] * fji;
+        const double d = fabs(a - b);
+        sd += d;
+        sf += a;
+        const double m = fmax(a, b);
+        if (m > 0.0) mx = fmax(mx, d / m);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        sd += __shfl_xor(sd, o, 64);
+        sf += __shfl_xor(sf, o, 64);
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if (lane == 0) {
+        unsafeAtomicAdd(&acc[0], sd);
+        unsafeAtomicAdd(&acc[1], sf);
+        atomicMax(reinterpret_cast<unsigned long long *>(&acc[2]), (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
 inline unsigned row_blocks(int64_t n) { return (unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock); }
 
 }  // namespace
@@ -362,6 +404,12 @@ gsrad_status launch_sddmm(const Csr &F, int C, int nb, const float *Btape, const
         hipLaunchKernelGGL(k_sddmm, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, nb, Btape, Ltape, rho,
                            grad_F, grad_rho, (int64_t)g);
     return check_hip(hipGetLastError(), "sddmm launch");
+}
+
+gsrad_status launch_reciprocity(const Csr &F, const double *area, double *acc, hipStream_t st) {
+    if (F.n == 0) return GSRAD_OK;
+    hipLaunchKernelGGL(k_reciprocity, dim3(row_blocks(F.n)), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, area, acc);
+    return check_hip(hipGetLastError(), "reciprocity launch");
 }
 
 gsrad_status launch_check(const Csr &F, int C, const float *rho, const float *E, const float *B, double *acc,

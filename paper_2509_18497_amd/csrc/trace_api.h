@@ -59,6 +59,9 @@ gsrad_status launch_adjoint(const Csr &FT, int C, const float *lam_in, const flo
 // lambda^(k+1), both [nb][N][C]
 gsrad_status launch_sddmm(const Csr &F, int C, int nb, const float *Btape, const float *Ltape, const float *rho,
                           float *grad_F, float *grad_rho, hipStream_t st);
+// reciprocity sums over the stored entries (areas [n] FP64): acc[0] +=
+// |A_i F_ij - A_j F_ji|, acc[1] += A_i F_ij, acc[2] = max relative difference
+gsrad_status launch_reciprocity(const Csr &F, const double *area, double *acc, hipStream_t st);
 // FP64 checks: acc[0] = sum r^2, acc[1] = sum B^2, acc[2] = max row sum,
 // acc[3] = number of non-finite inputs
 gsrad_status launch_check(const Csr &F, int C, const float *rho, const float *E, const float *B, double *acc,

@@ -26,7 +26,7 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_effective_area", "gsrad_reflectance", "gsrad_form_factors", "gsrad_ff_info", "gsrad_ff_view",
            "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
-           "gsrad_check", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
+           "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
            "gsrad_batch_transport_solve", "gsrad_batch_transport_backward", "gsrad_batch_destroy")
 
@@ -73,6 +73,7 @@ def lib():
             "gsrad_ff_copy": ([vp, vp, vp, vp, vp], i32),
             "gsrad_ff_from_csr": ([i64, i64, vp, vp, vp, pvp, vp], i32),
             "gsrad_ff_dense": ([vp, vp], i32),
+            "gsrad_check_reciprocity": ([vp, vp, vp, vp], i32),
             "gsrad_batch_create": ([vp, i32, vp, i32, pvp, vp], i32),
             "gsrad_batch_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)], i32),
@@ -389,6 +390,14 @@ def ray_hits(bvh: BVH, receivers: torch.Tensor, rays_per_surfel: int, seed: int,
                                 _ptr(dirs), _ptr(cnt, torch.int32), _ptr(hj, torch.int32), _ptr(ht),
                                 _ptr(hf, torch.int8), _ptr(hT), _stream(stream)), "gsrad_ray_hits")
     return {"dirs": dirs, "count": cnt, "j": hj, "t": ht, "front": hf, "T": hT}
+
+
+def check_reciprocity(bvh: BVH, ff: FF, stream=None) -> dict:
+    """FP64 reciprocity of F with the App. E areas: relative L1 asymmetry
+    sum|A_i F_ij - A_j F_ji| / sum A_i F_ij and the largest relative entry."""
+    out = (ctypes.c_double * 2)()
+    _check(lib().gsrad_check_reciprocity(bvh.h, ff.h, out, _stream(stream)), "gsrad_check_reciprocity")
+    return {"asymmetry": out[0], "max_entry": out[1]}
 
 
 def check(ff: FF, rho: torch.Tensor, E: torch.Tensor, B: torch.Tensor, stream=None) -> dict:

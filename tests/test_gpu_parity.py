@@ -343,3 +343,20 @@ def test_deep_tree_retraces_with_deep_stack(g, orc):
                        dev(np.array([3.0], np.float32)), 1)
     Eo = orc.direct_light(sur, alb, np.array([[2.0, 2.0, 2.0]]), np.array([3.0]), 1, te)
     assert rel_err(E.cpu().numpy(), Eo) < TOL
+
+
+# ---------------------------------------------------------------------------
+# FP64 reciprocity check of the estimated operator
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,kw,R", [("furnace", {}, 64), ("box_room", dict(n=1500), 32)])
+def test_reciprocity_check_matches_oracle(g, orc, name, kw, R):
+    sc = _scene(name, **kw)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    ff = g.form_factors(bvh, R, sc.seed, t_min=1e-4)
+    rec = g.check_reciprocity(bvh, ff)
+    te = orc.default_t_eps(sc.surfels)
+    Fo, _ = orc.ff_matrix(sc.surfels, R, sc.seed, te, 1e-4, 0)
+    A = orc.effective_area(sc.surfels["su"], sc.surfels["sv"], sc.surfels["opacity"])
+    asym, mx = orc.reciprocity(Fo, A)
+    assert abs(rec["asymmetry"] - asym) <= 1e-4 * asym
+    assert abs(rec["max_entry"] - mx) <= 1e-4 * max(mx, 1e-12)

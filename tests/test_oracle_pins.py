@@ -574,3 +574,25 @@ def test_cut_transmittance_tracks_fp64(orc):
                 if keep.any():
                     worst = max(worst, float(np.max(np.abs(h["T32"][keep] - T64[keep]) / T64[keep])))
     assert worst < 1e-5
+
+
+def test_reciprocity_measure(orc):
+    """Zero on an exactly reciprocal operator (closed sphere, F_ij = A_j / sum A);
+    a single perturbed entry shows up with its exact relative size, and an
+    entry whose mirror is missing counts fully."""
+    rng = np.random.default_rng(5)
+    A = rng.uniform(0.5, 2.0, 40)
+    Fd = np.tile(A / A.sum(), (40, 1))
+    np.fill_diagonal(Fd, 0.0)
+    asym, mx = orc.reciprocity(sp.csr_matrix(Fd), A)
+    assert asym < 1e-15 and mx < 1e-15
+    Fp = Fd.copy()
+    Fp[3, 7] *= 1.5
+    a, b = A[3] * Fp[3, 7], A[7] * Fp[7, 3]
+    asym, mx = orc.reciprocity(sp.csr_matrix(Fp), A)
+    assert abs(mx - abs(a - b) / max(a, b)) < 1e-14
+    assert abs(asym - 2 * abs(a - b) / (A[:, None] * Fp).sum()) < 1e-14
+    Fm = Fd.copy()
+    Fm[9, 2] = 0.0
+    _, mx = orc.reciprocity(sp.csr_matrix(Fm), A)
+    assert mx == 1.0
