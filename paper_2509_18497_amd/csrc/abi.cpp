@@ -168,8 +168,10 @@ struct gsrad_ff {
     bool has_records = false;
     int rec_cap = 0;
     DevBuf recs, rcnt;
+    // capacities the last ray cast needed (starting points of the next)
+    int deep_stack = 0, agg_log2h = 0;
     // scratch of the ray-cast path
-    DevBuf slab, ell_col, ell_val, row_len, err, scan_temp;
+    DevBuf slab, ell_col, ell_val, row_len, err, scan_temp, redo;
     // dense BF16 copies (gsrad_ff_dense): F and F^T, hi and lo parts
     bool has_dense = false;
     int64_t Np = 0;
@@ -194,7 +196,7 @@ struct gsrad_ff {
         return c;
     }
     ~gsrad_ff() {
-        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col,
+        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col, &redo,
                           &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl})
             b->release();
     }
@@ -418,9 +420,11 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     hipStream_t st = S(stream);
     const int64_t n = bvh->n;
     const int R = p->rays_per_surfel;
-    int rcap = kRecCap;
-    int log2h = kLog2Table;
-    int deep = 0;
+    // a handle traced before starts from the record slots, stack and
+    // aggregation table its last call needed (the rows do not depend on them)
+    int rcap = created ? kRecCap : std::max(kRecCap, h->rec_cap);
+    const int log2h = created ? kLog2Table : std::max(kLog2Table, h->agg_log2h);
+    int deep = created ? 0 : h->deep_stack;
     const int64_t cap_row = p->topk > 0 ? p->topk : (1 << kLog2TableMax);
     gsrad_status e;
     float t_eps = p->t_eps;
@@ -449,6 +453,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
         ENS(ell_col, n * cap_row * 4, "row staging");
         ENS(ell_val, n * cap_row * 4, "row staging");
         ENS(row_len, n * 4, "row lengths");
+        ENS(redo, ((size_t)chunk + 2) * 4, "aggregation redo list");
         ENS(err, 128, "error flags");
         ENS(row_ptr, (n + 1) * 8, "row_ptr");
         ENS(scan_temp, scan_temp_bytes(n), "scan temp");
@@ -466,8 +471,9 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
             }
             ProfScope ps("ff_aggregate", st);
             if ((e = launch_ff_aggregate(bv, h->recs.as<uint2>(), h->rcnt.as<uint32_t>(), rcap, s0, cnt, keep ? 1 : 0,
-                                         R, p->topk, log2h, cap_row, h->ell_col.as<int32_t>(), h->ell_val.as<float>(),
-                                         h->row_len.as<uint32_t>(), err, st)) != GSRAD_OK)
+                                         R, p->topk, log2h, kLog2TableMax, h->redo.as<int32_t>() + 2,
+                                         h->redo.as<uint32_t>(), cap_row, h->ell_col.as<int32_t>(),
+                                         h->ell_val.as<float>(), h->row_len.as<uint32_t>(), err, st)) != GSRAD_OK)
                 return fail(e);
         }
         hipLaunchKernelGGL(k_max_u32, dim3(64), dim3(256), 0, st, h->row_len.as<uint32_t>(), n, err + 1);
@@ -493,17 +499,11 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
             while (rcap < flags[3]) rcap *= 2;
             continue;
         }
-        // more distinct senders than the aggregation table holds: run again
-        // with the largest table
-        if ((flags[0] & kErrTable) && log2h < kLog2TableMax && attempt < 4) {
-            log2h = kLog2TableMax;
-            continue;
-        }
         break;
     }
     if (flags[0] != 0) {
         set_error("gsrad_form_factors: overflow flags 0x%x (1 traversal stack, 4 aggregation table of %d, 8 row, "
-                  "16 hit records of %d per ray)", flags[0], 1 << log2h, rcap);
+                  "16 hit records of %d per ray)", flags[0], 1 << kLog2TableMax, rcap);
         if (created) delete h;
         return GSRAD_EOVERFLOW;
     }
@@ -526,6 +526,9 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     h->t_min = p->t_min;
     h->has_records = keep;
     h->rec_cap = rcap;
+    h->deep_stack = deep;
+    // most rows needed the largest table: start there next time
+    h->agg_log2h = flags[2] > n / 4 ? kLog2TableMax : log2h;
     *ff = h;
     return GSRAD_OK;
 }

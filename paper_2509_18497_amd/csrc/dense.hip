@@ -242,19 +242,45 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Segs sg, int nseg, int64_t lda,
         if (kt + 1 < KT) GEMM_GLOAD(kt + 1);
         const __bf16 *Ab = As + buf * kBM * kPitch + (wm * 128 + frow) * kPitch + fk;
         const __bf16 *Bb = Bs + buf * kBN * kPitch + (wn * 128 + frow) * kPitch + fk;
+        // fragments of the next 16-wide K step are read while the sixteen
+        // MFMAs of the current one run (two register sets)
+        bf16x8 af[2][4], bf[2][4];
 #pragma unroll
-        for (int kk = 0; kk < kBK; kk += 16) {
-            bf16x8 af[4], bf[4];
+        for (int mi = 0; mi < 4; ++mi) af[0][mi] = *reinterpret_cast<const bf16x8 *>(Ab + mi * 32 * kPitch);
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi) af[mi] = *reinterpret_cast<const bf16x8 *>(Ab + mi * 32 * kPitch + kk);
+        for (int ni = 0; ni < 4; ++ni) bf[0][ni] = *reinterpret_cast<const bf16x8 *>(Bb + ni * 32 * kPitch);
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni) bf[ni] = *reinterpret_cast<const bf16x8 *>(Bb + ni * 32 * kPitch + kk);
+        for (int ks = 0; ks < kBK / 16; ++ks) {
+            const int cur = ks & 1, nxt = cur ^ 1;
+            if (ks + 1 < kBK / 16) {
+#pragma unroll
+                for (int mi = 0; mi < 4; ++mi)
+                    af[nxt][mi] = *reinterpret_cast<const bf16x8 *>(Ab + mi * 32 * kPitch + (ks + 1) * 16);
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    bf[nxt][ni] = *reinterpret_cast<const bf16x8 *>(Bb + ni * 32 * kPitch + (ks + 1) * 16);
+            }
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+                    acc[mi][ni] =
+                        __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
         }
+        // issue order: the first step's eight LDS reads, then each step's
+        // sixteen MFMAs with the next step's reads slotted between the first
+        // eight of them
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+        for (int ks = 0; ks + 1 < kBK / 16; ++ks) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
         if (kt + 1 < KT) GEMM_LSTORE(buf ^ 1);
         __syncthreads();
     }

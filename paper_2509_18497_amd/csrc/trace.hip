@@ -380,9 +380,18 @@ constexpr int kAggMaxPer = 32;   // table slots (or entries) per thread: H <= 81
 // the sums do not depend on the order of the atomics).  The distinct senders
 // are compacted, the topk largest (value desc, column asc) kept by a radix
 // select on the FP32 values, and the row sorted by column (bitonic).
+//
+// A row whose insertion probes max_probe slots (a table nearly full) is
+// given up: with redo_list set its slot b is appended there (and counted in
+// err[2]) for the REDO pass, which takes the listed rows one after the
+// other (a ticket per row) with the largest table; without a list, or in
+// the REDO pass, the row is an overflow.  Either table size gives the same
+// row.
+template <bool REDO>
 __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__restrict__ recs,
                                                       const uint32_t *__restrict__ rcnt, int rcap, int64_t s_begin,
-                                                      int by_orig, int R, int topk, int log2h, int64_t cap_row,
+                                                      int by_orig, int R, int topk, int log2h, int max_probe,
+                                                      int32_t *redo_list, uint32_t *redo_cnt, int64_t cap_row,
                                                       int32_t *__restrict__ ell_col, float *__restrict__ ell_val,
                                                       uint32_t *__restrict__ row_len, int *err) {
     extern __shared__ __align__(16) unsigned char sm[];
@@ -393,21 +402,34 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
     // key region, FP32 values in the first half of the value region
     uint32_t *cj = hkey;
     float *cv = reinterpret_cast<float *>(hval);
-    __shared__ uint32_t hist[256], wsum[4], dsel, before_sh;
+    __shared__ uint32_t hist[256], wsum[4], dsel, before_sh, habort, ticket;
+    volatile uint32_t *abort_v = &habort;
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
+    for (;;) {
+    int64_t b;
+    if (REDO) {
+        if (tid == 0) ticket = atomicAdd(redo_cnt + 1, 1u);
+        __syncthreads();
+        const uint32_t k = ticket;
+        if (k >= redo_cnt[0]) break;
+        b = redo_list[k];
+    } else {
+        b = blockIdx.x;
+    }
     const uint32_t i = __float_as_uint(bv.rec[s_begin + b].d.w);
     const int64_t slot = by_orig ? (int64_t)i : b;
     for (int k = tid; k < H; k += 256) {
         hkey[k] = kEmpty;
         hval[k] = 0ull;
     }
+    if (tid == 0) habort = 0;
     __syncthreads();
     for (int r = tid; r < R; r += 256) {
         const uint32_t m = min(rcnt[slot * R + r], (uint32_t)rcap);
         const uint2 *in = recs + slot * rcap * R + r;
         float T = 1.0f;
         for (uint32_t q = 0; q < m; ++q) {
+            if ((q & 7) == 0 && *abort_v) break;
             const uint2 h = in[(int64_t)q * R];
             const float gs = __uint_as_float(h.y);
             const float x = bv.c[h.x] * fabsf(gs);
@@ -416,7 +438,7 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
                 const unsigned long long fx = (unsigned long long)__float2ull_rn(w * kFixScaleF);
                 uint32_t hs = hash_slot(h.x, log2h);
                 int probe = 0;
-                for (; probe < H; ++probe) {
+                for (; probe < max_probe; ++probe) {
                     const uint32_t prev = atomicCAS(&hkey[hs], kEmpty, h.x);
                     if (prev == kEmpty || prev == h.x) {
                         atomicAdd(&hval[hs], fx);
@@ -424,12 +446,26 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
                     }
                     hs = (hs + 1) & (uint32_t)(H - 1);
                 }
-                if (probe == H) atomicOr(err, kErrTable);
+                if (probe == max_probe) *abort_v = 1;
             }
             T = __fmul_rn(T, exp_fx(-x));
         }
     }
     __syncthreads();
+    if (habort) {
+        if (tid == 0) {
+            row_len[i] = 0;
+            if (!REDO && redo_list) {
+                redo_list[atomicAdd(redo_cnt, 1u)] = (int32_t)b;
+                atomicAdd(err + 2, 1);
+            } else {
+                atomicOr(err, kErrTable);
+            }
+        }
+        if (!REDO) return;
+        __syncthreads();
+        continue;
+    }
     // compact the table in place: each thread stages its own slots
     const double scale = 1.0 / (kFixScale * (double)R);
     const int per = H >> 8;
@@ -562,6 +598,9 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
         ell_val[(int64_t)i * cap_row + e] = cv[e];
     }
     if (tid == 0) row_len[i] = m;
+    if (!REDO) return;
+    __syncthreads();   // the LDS is reused by the next listed row
+    }
 }
 
 __global__ void __launch_bounds__(256) k_ell_to_csr(const int32_t *__restrict__ ell_col,
@@ -840,18 +879,36 @@ gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps
 size_t ff_aggregate_smem(int log2h) { return (size_t)(1 << log2h) * 12; }
 
 gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *recs, const uint32_t *rcnt, int rcap, int64_t s_begin,
-                                 int64_t count, int by_orig, int R, int topk, int log2h, int64_t cap_row,
-                                 int32_t *ell_col, float *ell_val, uint32_t *row_len, int *err, hipStream_t st) {
-    if (log2h < 8 || log2h > 13) {
+                                 int64_t count, int by_orig, int R, int topk, int log2h, int log2h_max,
+                                 int32_t *redo_list, uint32_t *redo_cnt, int64_t cap_row, int32_t *ell_col,
+                                 float *ell_val, uint32_t *row_len, int *err, hipStream_t st) {
+    if (log2h < 8 || log2h > log2h_max || log2h_max > 13) {
         set_error("aggregation table size out of range");
         return GSRAD_EINVAL;
     }
+    const bool redo = log2h < log2h_max;
+    // a probe chain of 256 slots means a table nearly full (at 7/8 load the
+    // mean chain is about 32): such rows are redone with the largest table
+    const int max_probe = redo ? 256 : 1 << log2h;
     const size_t smem = ff_aggregate_smem(log2h);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_aggregate),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_aggregate<false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    hipLaunchKernelGGL(k_ff_aggregate, dim3((unsigned)count), dim3(256), smem, st, bv, recs, rcnt, rcap, s_begin,
-                       by_orig, R, topk, log2h, cap_row, ell_col, ell_val, row_len, err);
-    return check_hip(hipGetLastError(), "ff aggregate launch");
+    gsrad_status e;
+    if (redo && (e = check_hip(hipMemsetAsync(redo_cnt, 0, 8, st), "aggregate redo counter")) != GSRAD_OK) return e;
+    hipLaunchKernelGGL(k_ff_aggregate<false>, dim3((unsigned)count), dim3(256), smem, st, bv, recs, rcnt, rcap,
+                       s_begin, by_orig, R, topk, log2h, max_probe, redo ? redo_list : nullptr, redo_cnt, cap_row,
+                       ell_col, ell_val, row_len, err);
+    if ((e = check_hip(hipGetLastError(), "ff aggregate launch")) != GSRAD_OK || !redo) return e;
+    const size_t smem_max = ff_aggregate_smem(log2h_max);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_aggregate<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_max);
+    // one workgroup per CU holds the largest table; each takes listed rows
+    // until the list is drained (none listed: every workgroup exits at once)
+    const unsigned grid = (unsigned)std::min<int64_t>(count, 256);
+    hipLaunchKernelGGL(k_ff_aggregate<true>, dim3(grid), dim3(256), smem_max, st, bv, recs, rcnt, rcap, s_begin,
+                       by_orig, R, topk, log2h_max, 1 << log2h_max, redo_list, redo_cnt, cap_row, ell_col, ell_val,
+                       row_len, err);
+    return check_hip(hipGetLastError(), "ff aggregate redo launch");
 }
 
 gsrad_status launch_ell_to_csr(const int32_t *ell_col, const float *ell_val, int64_t cap_row, const int64_t *row_ptr,

@@ -18,9 +18,13 @@ size_t ff_aggregate_smem(int log2h);
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
                              int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, int *err,
                              hipStream_t st);
+// Rows overflowing a table of 2^log2h entries (a probe chain of 256) are listed in
+// redo_list (count in redo_cnt[0], tickets in redo_cnt[1]; room for count
+// rows) and aggregated again with 2^log2h_max entries; err[2] counts them.
 gsrad_status launch_ff_aggregate(const BvhDev &bv, const uint2 *recs, const uint32_t *rcnt, int rcap, int64_t s_begin,
-                                 int64_t count, int by_orig, int R, int topk, int log2h, int64_t cap_row,
-                                 int32_t *ell_col, float *ell_val, uint32_t *row_len, int *err, hipStream_t st);
+                                 int64_t count, int by_orig, int R, int topk, int log2h, int log2h_max,
+                                 int32_t *redo_list, uint32_t *redo_cnt, int64_t cap_row, int32_t *ell_col,
+                                 float *ell_val, uint32_t *row_len, int *err, hipStream_t st);
 gsrad_status launch_ell_to_csr(const int32_t *ell_col, const float *ell_val, int64_t cap_row, const int64_t *row_ptr,
                                int64_t n, int32_t *col, float *val, hipStream_t st);
 gsrad_status launch_direct(const BvhDev &bv, const float *albedo, const float *lpos, const float *lI, int Lt, int K,

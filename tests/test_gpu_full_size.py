@@ -109,3 +109,31 @@ def test_full_size_transport_on_two_coefficients(g, orc):
     assert rel_err(gE[:, :, slots, :], gEo) < TOL
     assert rel_err(gr, gro) < TOL
     assert rel_err(gF, gFo) < TOL
+
+
+def test_all_entry_rows_past_the_first_table(g, orc):
+    """The 32,768-surfel box room with 256 rays and every entry kept: many
+    receivers see more distinct senders than the first 4096-entry
+    aggregation table holds, so their rows are aggregated again with the
+    8192 table.  The longest rows and a random sample against the oracle, and a
+    second cast on the same handle (which may start from the larger table)
+    bit for bit equal to the first."""
+    sc = scenes.make_config("multi_light")
+    n = sc.n
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    ff = g.form_factors(bvh, sc.R, sc.seed, t_min=sc.t_min, topk=0, records=False)
+    rp, col, val = (x.cpu().numpy() for x in ff.csr())
+    lens = np.diff(rp)
+    assert lens.max() > 4096          # rows that only the second table can hold
+    longest = np.argsort(lens)[-4:]
+    rnd = np.random.default_rng(23).choice(n, size=4, replace=False)
+    recv = np.unique(np.concatenate([longest, rnd])).astype(np.int64)
+    te = orc.default_t_eps(sc.surfels)
+    rpo, co, vo, _ = orc.ff_rows(sc.surfels, recv, sc.R, sc.seed, te, sc.t_min, 0, cap_row=8192)
+    for k, i in enumerate(recv):
+        assert np.array_equal(col[rp[i]:rp[i + 1]], co[rpo[k]:rpo[k + 1]]), i
+        b = vo[rpo[k]:rpo[k + 1]]
+        assert np.max(np.abs(val[rp[i]:rp[i + 1]] - b)) / np.max(b) < 1e-5, i
+    ff2 = g.form_factors(bvh, sc.R, sc.seed, t_min=sc.t_min, topk=0, records=False, ff=ff)
+    rp2, col2, val2 = (x.cpu().numpy() for x in ff2.csr())
+    assert np.array_equal(rp2, rp) and np.array_equal(col2, col) and np.array_equal(val2, val)
