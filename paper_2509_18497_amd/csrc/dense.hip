@@ -6,11 +6,15 @@
 //
 // Tiles: a 256-thread workgroup computes a 256 x 256 block of C, its four
 // waves 128 x 128 each (4 x 4 MFMA tiles of 32 x 32, 256 accumulators per
-// lane), K advanced 64 at a time through a double-buffered LDS stage
-// (rows padded to 72 BF16 = 144 B, which keeps the 16-byte fragment reads
-// of 16 consecutive rows on distinct banks).  Tiles are numbered row-block
+// lane), K advanced 64 at a time through two LDS stages filled by direct
+// global -> LDS buffer loads (no staging registers): the next K tile is in
+// flight while the current one is multiplied.  LDS rows are unpadded with
+// their 16-byte chunks XOR-permuted per row, which keeps the fragment reads
+// of consecutive rows on distinct banks.  Tiles are numbered row-block
 // major and handed to the XCDs in contiguous ranges, so the workgroups that
-// share an A row-block (the large operand) run on one XCD and share its L2.
+// share an A row-block (the large operand) run on one XCD and share its L2;
+// the dL/dF product, whose operands are equally large, uses bands of eight
+// tile rows instead.
 //
 // A K range may be split into up to three segments with their own A and B
 // (the correction sweep sums F_hi X_hi + F_hi X_lo + F_lo X_hi in one pass).
@@ -24,10 +28,14 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16-byte register chunk
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr int kWaitVm0 = 0x0F70;   // s_waitcnt vmcnt(0), other counters unconstrained
 
 constexpr int kBM = 256, kBN = 256, kBK = 64;
-constexpr int kPitch = kBK + 8;   // LDS row pitch (BF16 elements)
-constexpr size_t kGemmSmem = (size_t)2 * (kBM + kBN) * kPitch * sizeof(__bf16);
+constexpr int kRowBytes = kBK * 2;                         // one LDS row: 8 chunks of 16 bytes
+constexpr int kStageBytes = (kBM + kBN) * kRowBytes;      // A then B of one K tile (64 KiB)
+constexpr size_t kGemmSmem = (size_t)2 * kStageBytes;     // two stages
+constexpr int kBufFlags = 0x00020000;                     // raw buffer resource (stride 0) on CDNA
 
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t g) {
     const int64_t x = b & 7, q = b >> 3, per = g >> 3, rem = g & 7;
@@ -159,6 +167,47 @@ __device__ __forceinline__ void epi_tile(const Epi &epi, const f32x16 &a, int64_
     }
 }
 
+// LDS rows hold their eight 16-byte K chunks permuted: logical chunk q of
+// tile row r sits at chunk q ^ swz(r), swz(r) = (r ^ (r >> 3)) & 7, so the
+// fragment reads of 8 (or 16) consecutive rows at one logical chunk touch
+// every bank once, without padding (the direct global -> LDS loads write
+// 64 lanes x 16 bytes contiguously).
+__device__ __forceinline__ int swz(int r) { return (r ^ (r >> 3)) & 7; }
+
+// The 64-wide K tile of one wave's 128 x 128 block out of one stage: four
+// 16-wide steps of sixteen 32 x 32 x 16 MFMAs, each step's fragments read
+// while the previous step multiplies (two register sets).  Ab/Bb address
+// the wave's row frow of A and B; fsw = swz(frow) (rows 32 mi + frow add
+// 4 (mi & 1) to it), h = the lane's K half.
+__device__ __forceinline__ void gemm_k_tile(const unsigned char *Ab, const unsigned char *Bb, int fsw, int h,
+                                            f32x16 (&acc)[4][4]) {
+    bf16x8 af[2][4], bf[2][4];
+#define GEMM_FRAG(ks, i) (16 * ((2 * (ks) + h) ^ fsw ^ (((i) & 1) << 2)) + (i) * 32 * kRowBytes)
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) af[0][mi] = *reinterpret_cast<const bf16x8 *>(Ab + GEMM_FRAG(0, mi));
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) bf[0][ni] = *reinterpret_cast<const bf16x8 *>(Bb + GEMM_FRAG(0, ni));
+#pragma unroll
+    for (int ks = 0; ks < kBK / 16; ++ks) {
+        const int cur = ks & 1, nxt = cur ^ 1;
+        if (ks + 1 < kBK / 16) {
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+                af[nxt][mi] = *reinterpret_cast<const bf16x8 *>(Ab + GEMM_FRAG(ks + 1, mi));
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                bf[nxt][ni] = *reinterpret_cast<const bf16x8 *>(Bb + GEMM_FRAG(ks + 1, ni));
+        }
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+                acc[mi][ni] =
+                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
+    }
+#undef GEMM_FRAG
+}
+
 struct Segs {
     const __bf16 *a[3];
     const __bf16 *b[3];
@@ -166,17 +215,26 @@ struct Segs {
 
 template <class Epi>
 __global__ void __launch_bounds__(256) k_gemm_nt(Segs sg, int nseg, int64_t lda, int64_t ldb, int64_t kpad,
-                                                 int tiles_n, int64_t ntiles, Epi epi) {
-    extern __shared__ __align__(16) unsigned char gemm_smem[];
-    __bf16 *As = reinterpret_cast<__bf16 *>(gemm_smem);   // [2][kBM][kPitch]
-    __bf16 *Bs = As + 2 * kBM * kPitch;                     // [2][kBN][kPitch]
+                                                 int tiles_n, int64_t ntiles, int group_m, Epi epi) {
+    extern __shared__ __align__(16) unsigned char gemm_smem[];   // [2 stages][A 256 rows | B 256 rows]
     const int64_t t = xcd_block(blockIdx.x, ntiles);
-    const int64_t bm = t / tiles_n, bn = t % tiles_n;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int64_t bm, bn;
+    if (group_m > 0) {
+        // column-major within bands of group_m tile rows: the 32 tiles an
+        // XCD runs at once share group_m A blocks and 32/group_m B blocks
+        const int64_t band = (int64_t)group_m * tiles_n, g = t / band, first = g * group_m;
+        const int64_t rows = min(ntiles / tiles_n - first, (int64_t)group_m), r = t - g * band;
+        bm = first + r % rows;
+        bn = r / rows;
+    } else {
+        bm = t / tiles_n;
+        bn = t % tiles_n;
+    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = w >> 1, wn = w & 1;
     const int kt_per = (int)(kpad / kBK);
     const int KT = nseg * kt_per;
-    u32x4 ra[8], rb[8];
     f32x16 acc[4][4];
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
@@ -184,108 +242,54 @@ __global__ void __launch_bounds__(256) k_gemm_nt(Segs sg, int nseg, int64_t lda,
         for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
-    const int frow = lane & 31, fk = 8 * (lane >> 5);
-    // global -> registers of K tile kt (select, not index, the segment's
-    // operands: a dynamic index into the argument struct would put it in
-    // scratch memory)
-#define GEMM_GLOAD(kt)                                                                                   \
+    // Direct global -> LDS loads: wave w brings rows 64 w .. 64 w + 63 of
+    // the A and the B tile, eight rows (1 KiB) per instruction; lane l
+    // fills row 64 w + 8 i + l / 8, physical chunk l % 8, so it fetches the
+    // logical chunk (l % 8) ^ swz(row) = (l % 8) ^ (l / 8) ^ i.  One buffer
+    // resource per segment operand based at the workgroup's first row
+    // (selected, not indexed: a dynamic index into the argument struct
+    // would put it in scratch memory), the row step and K offset in SGPRs.
+    const int lr = lane >> 3, lc = lane & 7;
+    const int nra = kBM * (int)lda * 2, nrb = kBN * (int)ldb * 2;
+#define GEMM_LOAD(kt, stage)                                                                             \
     do {                                                                                                 \
         const int s_ = (kt) / kt_per;                                                                    \
-        const int64_t k0_ = (int64_t)((kt) - s_ * kt_per) * kBK;                                         \
-        const __bf16 *A_ = (s_ == 0 ? sg.a[0] : s_ == 1 ? sg.a[1] : sg.a[2]) + bm * kBM * lda + k0_;     \
-        const __bf16 *B_ = (s_ == 0 ? sg.b[0] : s_ == 1 ? sg.b[1] : sg.b[2]) + bn * kBN * ldb + k0_;     \
-        const __bf16 *a_ = A_ + (tid >> 3) * lda + (tid & 7) * 8;                                        \
-        const __bf16 *b_ = B_ + (tid >> 3) * ldb + (tid & 7) * 8;                                        \
-        ra[0] = *reinterpret_cast<const u32x4 *>(a_);                                                    \
-        ra[1] = *reinterpret_cast<const u32x4 *>(a_ + 32 * lda);                                         \
-        ra[2] = *reinterpret_cast<const u32x4 *>(a_ + 64 * lda);                                         \
-        ra[3] = *reinterpret_cast<const u32x4 *>(a_ + 96 * lda);                                         \
-        ra[4] = *reinterpret_cast<const u32x4 *>(a_ + 128 * lda);                                        \
-        ra[5] = *reinterpret_cast<const u32x4 *>(a_ + 160 * lda);                                        \
-        ra[6] = *reinterpret_cast<const u32x4 *>(a_ + 192 * lda);                                        \
-        ra[7] = *reinterpret_cast<const u32x4 *>(a_ + 224 * lda);                                        \
-        rb[0] = *reinterpret_cast<const u32x4 *>(b_);                                                    \
-        rb[1] = *reinterpret_cast<const u32x4 *>(b_ + 32 * ldb);                                         \
-        rb[2] = *reinterpret_cast<const u32x4 *>(b_ + 64 * ldb);                                         \
-        rb[3] = *reinterpret_cast<const u32x4 *>(b_ + 96 * ldb);                                         \
-        rb[4] = *reinterpret_cast<const u32x4 *>(b_ + 128 * ldb);                                        \
-        rb[5] = *reinterpret_cast<const u32x4 *>(b_ + 160 * ldb);                                        \
-        rb[6] = *reinterpret_cast<const u32x4 *>(b_ + 192 * ldb);                                        \
-        rb[7] = *reinterpret_cast<const u32x4 *>(b_ + 224 * ldb);                                        \
+        const int k0_ = ((kt) - s_ * kt_per) * kBK * 2;                                                  \
+        const __bf16 *A_ = (s_ == 0 ? sg.a[0] : s_ == 1 ? sg.a[1] : sg.a[2]) + bm * kBM * lda;           \
+        const __bf16 *B_ = (s_ == 0 ? sg.b[0] : s_ == 1 ? sg.b[1] : sg.b[2]) + bn * kBN * ldb;           \
+        const __amdgpu_buffer_rsrc_t ar_ = __builtin_amdgcn_make_buffer_rsrc((void *)A_, 0, nra, kBufFlags); \
+        const __amdgpu_buffer_rsrc_t br_ = __builtin_amdgcn_make_buffer_rsrc((void *)B_, 0, nrb, kBufFlags); \
+        unsigned char *ls_ = gemm_smem + (stage) * kStageBytes + w * 64 * kRowBytes;                     \
+        GEMM_LOAD_ROWS(0); GEMM_LOAD_ROWS(1); GEMM_LOAD_ROWS(2); GEMM_LOAD_ROWS(3);                      \
+        GEMM_LOAD_ROWS(4); GEMM_LOAD_ROWS(5); GEMM_LOAD_ROWS(6); GEMM_LOAD_ROWS(7);                      \
     } while (0)
-#define GEMM_LSTORE(buf)                                                                                 \
+#define GEMM_LOAD_ROWS(i)                                                                                \
     do {                                                                                                 \
-        __bf16 *la_ = As + ((buf) * kBM + (tid >> 3)) * kPitch + (tid & 7) * 8;                          \
-        __bf16 *lb_ = Bs + ((buf) * kBN + (tid >> 3)) * kPitch + (tid & 7) * 8;                          \
-        *reinterpret_cast<u32x4 *>(la_) = ra[0];                                                         \
-        *reinterpret_cast<u32x4 *>(la_ + 32 * kPitch) = ra[1];                                           \
-        *reinterpret_cast<u32x4 *>(la_ + 64 * kPitch) = ra[2];                                           \
-        *reinterpret_cast<u32x4 *>(la_ + 96 * kPitch) = ra[3];                                           \
-        *reinterpret_cast<u32x4 *>(la_ + 128 * kPitch) = ra[4];                                          \
-        *reinterpret_cast<u32x4 *>(la_ + 160 * kPitch) = ra[5];                                          \
-        *reinterpret_cast<u32x4 *>(la_ + 192 * kPitch) = ra[6];                                          \
-        *reinterpret_cast<u32x4 *>(la_ + 224 * kPitch) = ra[7];                                          \
-        *reinterpret_cast<u32x4 *>(lb_) = rb[0];                                                         \
-        *reinterpret_cast<u32x4 *>(lb_ + 32 * kPitch) = rb[1];                                           \
-        *reinterpret_cast<u32x4 *>(lb_ + 64 * kPitch) = rb[2];                                           \
-        *reinterpret_cast<u32x4 *>(lb_ + 96 * kPitch) = rb[3];                                           \
-        *reinterpret_cast<u32x4 *>(lb_ + 128 * kPitch) = rb[4];                                          \
-        *reinterpret_cast<u32x4 *>(lb_ + 160 * kPitch) = rb[5];                                          \
-        *reinterpret_cast<u32x4 *>(lb_ + 192 * kPitch) = rb[6];                                          \
-        *reinterpret_cast<u32x4 *>(lb_ + 224 * kPitch) = rb[7];                                          \
+        const int r_ = w * 64 + 8 * (i);                                                                 \
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ar_, (lds_void *)(ls_ + 8 * (i) * kRowBytes), 16,       \
+                                                 lr * (int)lda * 2 + 16 * (lc ^ lr ^ (i)),               \
+                                                 r_ * (int)lda * 2 + k0_, 0, 0);                         \
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(br_, (lds_void *)(ls_ + kBM * kRowBytes + 8 * (i) * kRowBytes), \
+                                                 16, lr * (int)ldb * 2 + 16 * (lc ^ lr ^ (i)),           \
+                                                 r_ * (int)ldb * 2 + k0_, 0, 0);                         \
     } while (0)
-    GEMM_GLOAD(0);
-    GEMM_LSTORE(0);
+    const int frow = lane & 31, h = lane >> 5, fsw = swz(frow);
+    const unsigned char *Aw = gemm_smem + (wm * 128 + frow) * kRowBytes;
+    const unsigned char *Bw = gemm_smem + kBM * kRowBytes + (wn * 128 + frow) * kRowBytes;
+    GEMM_LOAD(0, 0);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
     for (int kt = 0; kt < KT; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < KT) GEMM_GLOAD(kt + 1);
-        const __bf16 *Ab = As + buf * kBM * kPitch + (wm * 128 + frow) * kPitch + fk;
-        const __bf16 *Bb = Bs + buf * kBN * kPitch + (wn * 128 + frow) * kPitch + fk;
-        // fragments of the next 16-wide K step are read while the sixteen
-        // MFMAs of the current one run (two register sets)
-        bf16x8 af[2][4], bf[2][4];
-#pragma unroll
-        for (int mi = 0; mi < 4; ++mi) af[0][mi] = *reinterpret_cast<const bf16x8 *>(Ab + mi * 32 * kPitch);
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) bf[0][ni] = *reinterpret_cast<const bf16x8 *>(Bb + ni * 32 * kPitch);
-#pragma unroll
-        for (int ks = 0; ks < kBK / 16; ++ks) {
-            const int cur = ks & 1, nxt = cur ^ 1;
-            if (ks + 1 < kBK / 16) {
-#pragma unroll
-                for (int mi = 0; mi < 4; ++mi)
-                    af[nxt][mi] = *reinterpret_cast<const bf16x8 *>(Ab + mi * 32 * kPitch + (ks + 1) * 16);
-#pragma unroll
-                for (int ni = 0; ni < 4; ++ni)
-                    bf[nxt][ni] = *reinterpret_cast<const bf16x8 *>(Bb + ni * 32 * kPitch + (ks + 1) * 16);
-            }
-#pragma unroll
-            for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < 4; ++ni)
-                    acc[mi][ni] =
-                        __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
-        }
-        // issue order: the first step's eight LDS reads, then each step's
-        // sixteen MFMAs with the next step's reads slotted between the first
-        // eight of them
-        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
-#pragma unroll
-        for (int ks = 0; ks + 1 < kBK / 16; ++ks) {
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            }
-            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
-        if (kt + 1 < KT) GEMM_LSTORE(buf ^ 1);
+        const int st = kt & 1;
+        // the next tile (the last one again at the end: in bounds, unused)
+        // goes into the other stage, free since the previous barrier
+        GEMM_LOAD(min(kt + 1, KT - 1), st ^ 1);
+        gemm_k_tile(Aw + st * kStageBytes, Bw + st * kStageBytes, fsw, h, acc);
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
         __syncthreads();
     }
-#undef GEMM_GLOAD
-#undef GEMM_LSTORE
+#undef GEMM_LOAD_ROWS
+#undef GEMM_LOAD
     // accumulator register r of lane l holds row (r/4)*8 + (l/32)*4 + r%4,
     // column l%32 of its 32 x 32 tile
     const int64_t i0 = bm * kBM + wm * 128 + (lane >> 5) * 4, j0 = bn * kBN + wn * 128 + (lane & 31);
@@ -401,9 +405,14 @@ __global__ void __launch_bounds__(256) k_gather_csr(const int64_t *__restrict__ 
 
 template <class Epi>
 gsrad_status launch_gemm(const Segs &sg, int nseg, int64_t lda, int64_t ldb, int64_t kpad, int64_t m_pad,
-                         int64_t n_pad, const Epi &epi, hipStream_t st) {
+                         int64_t n_pad, const Epi &epi, hipStream_t st, int group_m = 0) {
     if (m_pad % kBM || n_pad % kBN || kpad % kBK || lda % 8 || ldb % 8 || nseg < 1 || nseg > 3) {
         set_error("dense product: operand shapes are not padded to the tile sizes");
+        return GSRAD_EINVAL;
+    }
+    // buffer offsets within a 256-row block are 32-bit
+    if (kpad > lda || kpad > ldb || lda > (1 << 22) || ldb > (1 << 22)) {
+        set_error("dense product: rows longer than 2^22 elements or shorter than the reduction");
         return GSRAD_EINVAL;
     }
     const int tiles_n = (int)(n_pad / kBN);
@@ -413,7 +422,7 @@ gsrad_status launch_gemm(const Segs &sg, int nseg, int64_t lda, int64_t ldb, int
                                "dense product LDS attribute");
     if (e != GSRAD_OK) return e;
     hipLaunchKernelGGL(k_gemm_nt<Epi>, dim3((unsigned)ntiles), dim3(256), kGemmSmem, st, sg, nseg, lda, ldb, kpad,
-                       tiles_n, ntiles, epi);
+                       tiles_n, ntiles, group_m, epi);
     return check_hip(hipGetLastError(), "dense product launch");
 }
 
@@ -503,7 +512,9 @@ gsrad_status launch_dense_grad_F(const __bf16 *P, const __bf16 *P_lo, const __bf
     sg.a[2] = P_lo;
     sg.b[2] = Bb;
     EpiStore epi{G, ldg, n, n};
-    return launch_gemm(sg, 3, ldk, ldk, kpad, ld_pad, ld_pad, epi, st);
+    // both operands are n_pad x kpad: bands of 8 tile rows keep the blocks
+    // that run together few enough to be read from L2
+    return launch_gemm(sg, 3, ldk, ldk, kpad, ld_pad, ld_pad, epi, st, 8);
 }
 
 }  // namespace gsrad

@@ -64,7 +64,7 @@ def test_dense_products_are_exact_on_dyadic_inputs(g, orc, n, k, Lt, K, nb):
 
 
 @pytest.mark.parametrize("n,kk,Lt,K,nb", [(1000, 40, 1, 9, 8), (300, 30, 10, 9, 3), (777, 25, 2, 16, 5),
-                                          (256, 16, 1, 1, 1)])
+                                          (256, 16, 1, 1, 1), (2600, 20, 1, 4, 2)])
 def test_dense_bf16_matches_oracle(g, orc, n, kk, Lt, K, nb):
     rp, c, v = scenes.seeded_csr(n, kk, seed=n + kk)
     F = sp.csr_matrix((v.astype(np.float64), c, rp), shape=(n, n))
