@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 99940.56e6, "write": 10913.04e6,
+    "ff_trace": {"fetch": 100055.87e6, "write": 10911.60e6,
                  "files": ["trace.hip", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "1f79866158039277361b67291e303b4cb8297e74ad628abbc99dbbd8edb7f2ea",
+                 "sha256": "87d936161e7cfda468b4548e7aed015af84965da20068a8f25022691129b90b5",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
 }
 
@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--n", type=int, default=100_000, help="surfel count (100k is the measured workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-receivers", type=int, default=200,
+    ap.add_argument("--cpu-receivers", type=int, default=500,
                     help="receivers of the bounded oracle sample (about 15 s of host work)")
     ap.add_argument("--workload", default="fruit_bowl", choices=["fruit_bowl", "multi_light", "uneven_batch"],
                     help="fruit_bowl: the 100k sparse path (default); multi_light: the 32k box room with 100 "
