@@ -34,12 +34,12 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t g) {
 }
 
 // Leaf visit of the sorted traversal: FP32 hit decision, then insertion
-// into the ascending k-buffer (keys (t bits, j), payload +-gamma with the
-// sign = front face; gamma from the FP64 kernel argument).
+// into the ascending k-buffer of keys (t bits, j).  The kernel value and
+// the face of a hit are found only for the hits that end up buffered.
 template <int KB>
 __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int s, uint32_t self, float ox, float oy,
                                            float oz, float dx, float dy, float dz, float t_eps, uint64_t last,
-                                           uint64_t (&key)[KB], float (&gam)[KB], int &found, float &t1) {
+                                           uint64_t (&key)[KB], int &found, float &t1) {
     const SurfRec r = rec[s];
     const uint32_t j = __float_as_uint(r.d.w);
     if (j == self) return;
@@ -50,18 +50,13 @@ __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int 
     if (kk <= last) return;
     ++found;
     if (kk >= key[KB - 1]) return;
-    const float g = kernel_gamma(hit_r2_exact(r, ox, oy, oz, dx, dy, dz));
     uint64_t x = kk;
-    float y = front ? g : -g;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         const bool lt = x < key[k];
         const uint64_t tk = key[k];
-        const float tg = gam[k];
         key[k] = lt ? x : tk;
-        gam[k] = lt ? y : tg;
         x = lt ? tk : x;
-        y = lt ? tg : y;
     }
     if (found >= KB) t1 = __uint_as_float((uint32_t)(key[KB - 1] >> 32)) * 1.00001f + 1e-30f;
 }
@@ -79,18 +74,14 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
     float T = 1.0f;
     for (;;) {
         uint64_t key[KB];
-        float gam[KB];
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            key[k] = ~0ull;
-            gam[k] = 0.0f;
-        }
+        for (int k = 0; k < KB; ++k) key[k] = ~0ull;
         int found = 0;
         const float tlo = last ? __uint_as_float((uint32_t)(last >> 32)) : t_eps;
         const float t0 = tlo * 0.99999f;
         float t1 = INFINITY;
         if (bv.n == 1) {
-            visit_leaf<KB>(bv.rec, 0, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, gam, found, t1);
+            visit_leaf<KB>(bv.rec, 0, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
         } else {
             int sp = 0, node = 0;
             for (;;) {
@@ -100,11 +91,11 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
                 bool h1 = slab(nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, ox, oy, oz, ix, iy, iz, t0, t1, tn1);
                 const int c0 = nd.ch.x, c1 = nd.ch.y;
                 if (h0 && c0 < 0) {
-                    visit_leaf<KB>(bv.rec, ~c0, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, gam, found, t1);
+                    visit_leaf<KB>(bv.rec, ~c0, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
                     h0 = false;
                 }
                 if (h1 && c1 < 0) {
-                    visit_leaf<KB>(bv.rec, ~c1, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, gam, found, t1);
+                    visit_leaf<KB>(bv.rec, ~c1, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
                     h1 = false;
                 }
                 if (h0 && h1) {
@@ -128,6 +119,18 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
             }
         }
         const int m = found < KB ? found : KB;
+        // kernel values (FP64 hit point) and faces of the buffered hits only
+        float gam[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            gam[k] = 0.0f;
+            if (k < m) {
+                const SurfRec r = bv.rec[bv.inv[(uint32_t)key[k]]];
+                const float den = __builtin_fmaf(dz, r.b.z, __builtin_fmaf(dy, r.b.y, __fmul_rn(dx, r.b.x)));
+                const float g = kernel_gamma(hit_r2_exact(r, ox, oy, oz, dx, dy, dz));
+                gam[k] = den < 0.0f ? g : -g;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             if (k < m) {
@@ -243,9 +246,8 @@ constexpr int kPoolRays = 1024;   // rays sorted and pooled per batch
 // pool through an LDS counter: neighbouring lanes trace rays that leave
 // close origins in close directions, and a lane whose ray ends early takes
 // the next one instead of idling until its wave's longest ray is done.
-// Three waves per SIMD (at most 168 VGPRs): without the bound the FP64
-// kernel argument in the leaf visit pushes the kernel to 181 VGPRs and two
-// waves, a third slower.
+// Three waves per SIMD (at most 168 VGPRs), held by a launch bound; four
+// (at most 128) were measured no faster.
 template <int STK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
                                                   int64_t s_begin, int64_t count, int group, int64_t nblocks,
