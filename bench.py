@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 100055.87e6, "write": 10911.60e6,
+    "ff_trace": {"fetch": 113835.06e6, "write": 10909.48e6,
                  "files": ["trace.hip", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "87d936161e7cfda468b4548e7aed015af84965da20068a8f25022691129b90b5",
+                 "sha256": "1449f6810f07ca5ff1df3fea975144e71a1d9f8864b2037ea6d6f80ccf181edd",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
 }
 

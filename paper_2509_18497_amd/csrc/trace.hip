@@ -23,7 +23,7 @@ namespace {
 // covers any LBVH of 30-bit Morton codes plus 32 index bits.
 constexpr int kStackShallow = 32;
 constexpr int kStackDeep = 64;
-constexpr int kKB = 16;
+constexpr int kKB = 20;   // k-buffer entries per traversal round (measured best of 8-32)
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
