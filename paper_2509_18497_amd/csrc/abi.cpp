@@ -158,6 +158,9 @@ struct gsrad_ff {
     DevBuf row_ptr, col, val;
     // transpose, built on first use by the backward
     bool has_t = false;
+    // receivers in Morton order (ray-cast F): the order the row kernels take
+    bool has_order = false;
+    DevBuf row_order;
     DevBuf t_row_ptr, t_col, t_val, perm, t_temp;
     // provenance for the opacity backward
     const gsrad_bvh *bvh = nullptr;
@@ -184,6 +187,7 @@ struct gsrad_ff {
         c.row_ptr = row_ptr.as<int64_t>();
         c.col = col.as<int32_t>();
         c.val = val.as<float>();
+        c.order = has_order ? row_order.as<int32_t>() : nullptr;
         return c;
     }
     Csr csr_t() const {
@@ -193,10 +197,11 @@ struct gsrad_ff {
         c.row_ptr = t_row_ptr.as<int64_t>();
         c.col = t_col.as<int32_t>();
         c.val = t_val.as<float>();
+        c.order = has_order ? row_order.as<int32_t>() : nullptr;
         return c;
     }
     ~gsrad_ff() {
-        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col, &redo,
+        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col, &redo, &row_order,
                           &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl})
             b->release();
     }
@@ -513,10 +518,13 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     if ((e = launch_ell_to_csr(h->ell_col.as<int32_t>(), h->ell_val.as<float>(), cap_row, h->row_ptr.as<int64_t>(), n,
                                h->col.as<int32_t>(), h->val.as<float>(), st)) != GSRAD_OK)
         return fail(e);
+    if ((e = h->row_order.ensure((size_t)n * 4, "row order")) != GSRAD_OK) return fail(e);
+    if ((e = launch_sorted_order(bvh->dev(), h->row_order.as<int32_t>(), st)) != GSRAD_OK) return fail(e);
     h->n = n;
     h->nnz = nnz;
     h->max_row = flags[1];
     h->has_t = false;
+    h->has_order = true;
     h->has_dense = false;
     h->bvh = bvh;
     h->R = R;
@@ -597,6 +605,7 @@ gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, c
     h->nnz = nnz;
     h->max_row = mx;
     h->has_t = false;
+    h->has_order = false;
     h->has_dense = false;
     h->bvh = nullptr;
     *ff = h;
@@ -1088,6 +1097,7 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
     F->nnz = nnz;
     F->max_row = max_row;
     F->has_t = false;
+    F->has_order = false;
     if (old_ptrs[0] != F->row_ptr.p || old_ptrs[1] != F->col.p || old_ptrs[2] != F->val.p) b->drop_graph();
     if ((e = b->row_off.ensure((size_t)(n_scenes + 1) * 8, "scene rows")) != GSRAD_OK) return fail(e);
     if ((e = b->val_off.ensure((size_t)(n_scenes + 1) * 8, "scene values")) != GSRAD_OK) return fail(e);

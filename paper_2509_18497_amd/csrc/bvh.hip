@@ -277,6 +277,12 @@ __global__ void __launch_bounds__(kThreads) k_pack(Node *__restrict__ nodes, con
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+__global__ void __launch_bounds__(kThreads) k_sorted_order(const SurfRec *__restrict__ rec, int64_t n,
+                                                          int32_t *__restrict__ order) {
+    const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (s < n) order[s] = (int32_t)__float_as_uint(rec[s].d.w);
+}
+
 }  // namespace
 
 size_t bvh_temp_bytes(int64_t n) {
@@ -331,6 +337,12 @@ gsrad_status bvh_build(const gsrad_surfels &sf, BvhBuffers &B, hipStream_t st) {
         hipLaunchKernelGGL(k_pack, dim3(nblk(n - 1)), dim3(kThreads), 0, st, B.nodes, B.leafbox, nodebox, n);
     }
     return check_hip(hipGetLastError(), "bvh build");
+}
+
+gsrad_status launch_sorted_order(const BvhDev &bv, int32_t *order, hipStream_t st) {
+    if (bv.n == 0) return GSRAD_OK;
+    hipLaunchKernelGGL(k_sorted_order, dim3(nblk(bv.n)), dim3(kThreads), 0, st, bv.rec, bv.n, order);
+    return check_hip(hipGetLastError(), "sorted order launch");
 }
 
 }  // namespace gsrad

@@ -97,9 +97,10 @@ __global__ void __launch_bounds__(256) k_bounce(const int64_t *__restrict__ row_
                                                 const float *__restrict__ val, int64_t n, int C,
                                                 const float *__restrict__ Bin, const float *__restrict__ E,
                                                 const float *__restrict__ rho, float *__restrict__ Bout,
-                                                int64_t nblocks) {
-    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
-    if (row >= n) return;
+                                                int64_t nblocks, const int32_t *__restrict__ order) {
+    const int64_t idx = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (idx >= n) return;
+    const int64_t row = order ? (int64_t)order[idx] : idx;
     const int lane = __lane_id();
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
     for (int c0 = 0; c0 < C; c0 += 64) {
@@ -114,9 +115,10 @@ __global__ void __launch_bounds__(256) k_adjoint(const int64_t *__restrict__ row
                                                  const float *__restrict__ val, int64_t n, int C,
                                                  const float *__restrict__ lam_in, const float *__restrict__ rho,
                                                  float *__restrict__ lam_out, float *__restrict__ gE,
-                                                 int64_t nblocks) {
-    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
-    if (row >= n) return;
+                                                 int64_t nblocks, const int32_t *__restrict__ order) {
+    const int64_t idx = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (idx >= n) return;
+    const int64_t row = order ? (int64_t)order[idx] : idx;
     const int lane = __lane_id();
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
     for (int c0 = 0; c0 < C; c0 += 64) {
@@ -142,9 +144,10 @@ __global__ void __launch_bounds__(256) k_sddmm(const int64_t *__restrict__ row_p
                                                const float *__restrict__ val, int64_t n, int C, int nb,
                                                const float *__restrict__ Bt, const float *__restrict__ Lt,
                                                const float *__restrict__ rho, float *__restrict__ grad_F,
-                                               float *__restrict__ grad_rho, int64_t nblocks) {
-    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
-    if (row >= n) return;
+                                               float *__restrict__ grad_rho, int64_t nblocks, const int32_t *__restrict__ order) {
+    const int64_t idx = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (idx >= n) return;
+    const int64_t row = order ? (int64_t)order[idx] : idx;
     const int lane = __lane_id();
     const int64_t b = row_ptr[row], e = row_ptr[row + 1];
     const int64_t NC = n * (int64_t)C;
@@ -190,9 +193,10 @@ __global__ void __launch_bounds__(256) k_sddmm_fast(const int64_t *__restrict__ 
                                                     int64_t n, int C, int nb, const float *__restrict__ Bt,
                                                     const float *__restrict__ Lt, const float *__restrict__ rho,
                                                     float *__restrict__ grad_F, float *__restrict__ grad_rho,
-                                                    int64_t nblocks) {
-    const int64_t row = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
-    if (row >= n) return;
+                                                    int64_t nblocks, const int32_t *__restrict__ order) {
+    const int64_t idx = xcd_block(blockIdx.x, nblocks) * kWavesPerBlock + threadIdx.x / 64;
+    if (idx >= n) return;
+    const int64_t row = order ? (int64_t)order[idx] : idx;
     const int lane = __lane_id();
     const bool on = lane < C;
     const int c = on ? lane : 0;
@@ -382,7 +386,7 @@ gsrad_status launch_bounce(const Csr &F, int C, const float *Bin, const float *E
                            hipStream_t st) {
     const unsigned g = row_blocks(F.n);
     hipLaunchKernelGGL(k_bounce, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, Bin, E, rho, Bout,
-                       (int64_t)g);
+                       (int64_t)g, F.order);
     return check_hip(hipGetLastError(), "bounce launch");
 }
 
@@ -390,7 +394,7 @@ gsrad_status launch_adjoint(const Csr &FT, int C, const float *lam_in, const flo
                             hipStream_t st) {
     const unsigned g = row_blocks(FT.n);
     hipLaunchKernelGGL(k_adjoint, dim3(g), dim3(256), 0, st, FT.row_ptr, FT.col, FT.val, FT.n, C, lam_in, rho,
-                       lam_out, gE, (int64_t)g);
+                       lam_out, gE, (int64_t)g, FT.order);
     return check_hip(hipGetLastError(), "adjoint launch");
 }
 
@@ -399,10 +403,10 @@ gsrad_status launch_sddmm(const Csr &F, int C, int nb, const float *Btape, const
     const unsigned g = row_blocks(F.n);
     if (C <= 64 && nb <= kSddmmMaxNb)
         hipLaunchKernelGGL(k_sddmm_fast, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, nb, Btape, Ltape,
-                           rho, grad_F, grad_rho, (int64_t)g);
+                           rho, grad_F, grad_rho, (int64_t)g, F.order);
     else
         hipLaunchKernelGGL(k_sddmm, dim3(g), dim3(256), 0, st, F.row_ptr, F.col, F.val, F.n, C, nb, Btape, Ltape, rho,
-                           grad_F, grad_rho, (int64_t)g);
+                           grad_F, grad_rho, (int64_t)g, F.order);
     return check_hip(hipGetLastError(), "sddmm launch");
 }
 

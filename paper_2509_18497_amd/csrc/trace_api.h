@@ -48,12 +48,18 @@ struct Csr {
     const int64_t *row_ptr = nullptr;
     const int32_t *col = nullptr;
     const float *val = nullptr;
+    // optional order in which the row kernels take the rows (a permutation
+    // of 0..n-1, e.g. the receivers' Morton order, so that the rows one XCD
+    // runs together gather from nearby columns); results do not depend on it
+    const int32_t *order = nullptr;
 };
 
 size_t transpose_temp_bytes(int64_t n, int64_t nnz);
 gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, float *t_val, uint32_t *perm,
                            void *temp, size_t temp_bytes, hipStream_t st);
 // Bout = E + rho * (F Bin), rows of C columns
+// Morton-sorted position -> original surfel index (the sorted records' ids)
+gsrad_status launch_sorted_order(const BvhDev &bv, int32_t *order, hipStream_t st);
 gsrad_status launch_bounce(const Csr &F, int C, const float *Bin, const float *E, const float *rho, float *Bout,
                            hipStream_t st);
 // lam_out = F^T (rho * lam_in) given FT = transpose(F); gE += lam_out
