@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 113835.06e6, "write": 10909.48e6,
+    "ff_trace": {"fetch": 113828.04e6, "write": 10907.93e6,
                  "files": ["trace.hip", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "1449f6810f07ca5ff1df3fea975144e71a1d9f8864b2037ea6d6f80ccf181edd",
+                 "sha256": "0f573283ebf8e59f4066946b6f22f28cacd904ceadbbcdc7abcbe8981703ba7c",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
 }
 
