@@ -147,10 +147,13 @@ gsrad_status gsrad_reflectance(const gsrad_bvh *bvh, const float *albedo, float 
  * with columns ascending in each row, values FP32, deterministic (bit
  * identical between runs).
  * EINVAL: null arguments, R < 1, topk < 0, t_min < 0.
- * Per-ray hit records (8 bytes per composited hit) and per-receiver
- * aggregation tables grow automatically (the call is then repeated) up to
- * 2048 composited hits per ray and 8192 distinct senders per row.
- * EOVERFLOW: beyond those limits, or a traversal stack overflow.
+ * Per-ray hit records (8 bytes per composited hit) grow automatically (the
+ * call is then repeated) up to 2048 composited hits per ray; a row whose
+ * distinct senders overflow the 4096-entry aggregation table is aggregated
+ * again with 8192 entries within the same call, and a handle passed back in
+ * starts from the capacities its previous call needed.
+ * EOVERFLOW: more than 2048 composited hits on a ray, more than 8192
+ * distinct senders in a row, or a traversal stack overflow.
  */
 gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, gsrad_ff **ff, void *stream);
 
