@@ -1,6 +1,7 @@
-"""The 100k-surfel fruit bowl in the launch configuration the benchmark
-times (128 rays per surfel, top-512 rows, SH degree 3, 8 bounces), checked
-against the FP64 oracle on outputs it can compute at that size:
+"""The benchmark workloads at full size, checked against the FP64 oracle on
+outputs it can compute at that size.  The 100k-surfel fruit bowl in the
+launch configuration the benchmark times (128 rays per surfel, top-512
+rows, SH degree 3, 8 bounces):
 
 * form-factor rows and direct-light rows of sampled receivers (the oracle
   casts only those receivers' rays, by brute force over all surfels);
@@ -10,6 +11,11 @@ against the FP64 oracle on outputs it can compute at that size:
   B and lambda vanish on every other column and the oracle's FP64 run on
   the two non-zero coefficients gives the exact B, grad_E, grad_rho and
   grad_F of the full 48-column launch.
+
+The 32,768-surfel multi-light room (all-entry F rows past the first
+aggregation table; the dense BF16 launch over 2700 columns on two lights),
+and the 64-scene uneven batch (bit-identical to the scene-by-scene path,
+the smallest scenes against the oracle).
 """
 import numpy as np
 import pytest
@@ -137,3 +143,88 @@ def test_all_entry_rows_past_the_first_table(g, orc):
     ff2 = g.form_factors(bvh, sc.R, sc.seed, t_min=sc.t_min, topk=0, records=False, ff=ff)
     rp2, col2, val2 = (x.cpu().numpy() for x in ff2.csr())
     assert np.array_equal(rp2, rp) and np.array_equal(col2, col) and np.array_equal(val2, val)
+
+
+def _slice_rel(x, ref):
+    return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def test_full_size_dense_multi_light_on_two_lights(g, orc):
+    """The dense BF16 launch of the multi-light workload (32,768 rows,
+    100 lights x 9 SH x 3 = 2700 columns, 8 bounces) on a seeded operator
+    with ~190 entries per row, E and grad_B non-zero for lights 0 and 57
+    only.  The transport is separable over columns, so the oracle's FP64 run
+    on those two lights gives B, dL/dE, dL/drho and dL/dF of the whole
+    launch; the other lights' outputs must be exactly zero."""
+    N, k, Lt, K, nb, lights = 32768, 190, 100, 9, 8, [0, 57]
+    rp, c, v = scenes.seeded_csr(N, k, seed=41)
+    F = sp.csr_matrix((v.astype(np.float64), c, rp), shape=(N, N))
+    rho = scenes.seeded_array((N, 3), seed=1, lo=0.1, hi=0.9)
+    Es = scenes.seeded_array((N, len(lights), K, 3), seed=2)
+    gBs = scenes.seeded_array((N, len(lights), K, 3), seed=3, lo=-1, hi=1)
+    E = np.zeros((N, Lt, K, 3), np.float32)
+    gB = np.zeros((N, Lt, K, 3), np.float32)
+    E[:, lights] = Es
+    gB[:, lights] = gBs
+    ff = g.ff_dense(g.ff_from_csr(dev(rp), dev(c), dev(v)))
+    B, tape = g.transport_solve(ff, dev(rho), dev(E), nb, precision=g.BF16)
+    gE, gr, gF = g.transport_backward(ff, tape, dev(rho), dev(gB))
+    B, gE, gr, gF = (x.cpu().numpy() for x in (B, gE, gr, gF))
+    Bo, tp = orc.bounce(F, rho, Es, nb, keep_tape=True)
+    gEo, gro, gFo = orc.adjoint(F, rho, tp, gBs)
+    others = np.setdiff1d(np.arange(Lt), lights)
+    assert not B[:, others].any() and not gE[:, others].any()
+    assert _slice_rel(B[:, lights], Bo) < 1e-3
+    assert _slice_rel(gE[:, lights], gEo) < 1e-3
+    assert _slice_rel(gr, gro) < 1e-3
+    assert _slice_rel(gF, gFo) < 1e-3
+
+
+def test_full_size_uneven_batch(g, orc):
+    """The uneven batch of the benchmark (64 cluster rooms, 2k-65k surfels,
+    1-4 lights each, 1.19 M surfels, top-512 F, K = 9, 8 bounces): one batch
+    solve and backward, bit for bit equal to the scene-by-scene path on
+    every scene, and the two smallest scenes against the FP64 oracle on the
+    ray-cast F."""
+    rooms = scenes.uneven_batch(lights=(1, 4))
+    K, R, nb = rooms[0].K, rooms[0].R, rooms[0].n_bounces
+    ffs, Es, rhos, Lts = [], [], [], []
+    for sc in rooms:
+        bvh = g.build_bvh(dev_surfels(sc.surfels))
+        ffs.append(g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, topk=512, records=False))
+        alb = dev(sc.albedo)
+        Es.append(g.direct_light(bvh, alb, dev(sc.light_pos), dev(sc.light_I), K))
+        rhos.append(g.reflectance(bvh, alb))
+        Lts.append(sc.n_lights)
+    assert sum(sc.n for sc in rooms) > 1_000_000
+    batch = g.batch_create(ffs, Lts, K)
+    rho = torch.cat(rhos)
+    E = batch.pack(Es)
+    gB = dev(scenes.seeded_array((E.shape[0],), seed=98, lo=-1, hi=1))
+    Bb = batch.unpack(g.batch_transport_solve(batch, rho, E, nb))
+    gEb, grb, gFb = g.batch_transport_backward(batch, rho, gB)
+    gEb = batch.unpack(gEb)
+    gBs = batch.unpack(gB)
+    smallest = set(np.argsort([sc.n for sc in rooms])[:2].tolist())
+    r0 = e0 = 0
+    for s, (sc, ff) in enumerate(zip(rooms, ffs)):
+        n = sc.n
+        nnz = ff.info()[1]
+        Bs, tape = g.transport_solve(ff, rhos[s], Es[s], nb)
+        gEs, grs, gFs = g.transport_backward(ff, tape, rhos[s], gBs[s].contiguous())
+        assert torch.equal(Bb[s], Bs), s
+        assert torch.equal(gEb[s], gEs), s
+        assert torch.equal(grb[r0:r0 + n], grs), s
+        assert torch.equal(gFb[e0:e0 + nnz], gFs), s
+        if s in smallest:
+            rp, col, val = (x.cpu().numpy() for x in ff.csr())
+            F = sp.csr_matrix((val.astype(np.float64), col, rp), shape=(n, n))
+            rh = rhos[s].cpu().numpy()
+            Bo, tp = orc.bounce(F, rh, Es[s].cpu().numpy(), nb, keep_tape=True)
+            gEo, gro, gFo = orc.adjoint(F, rh, tp, gBs[s].cpu().numpy())
+            assert rel_err(Bs.cpu().numpy(), Bo) < TOL
+            assert rel_err(gEs.cpu().numpy(), gEo) < TOL
+            assert rel_err(grs.cpu().numpy(), gro) < TOL
+            assert rel_err(gFs.cpu().numpy(), gFo) < TOL
+        r0 += n
+        e0 += nnz
