@@ -506,6 +506,7 @@ def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
         st.update(batch=batch, rho=rho, E=E, rhos=rhos, Es=Es)
         return B, out
 
+    calibration_copy(args, torch, dev)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -566,7 +567,8 @@ def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
         "grays_per_s": rays / (avg("ff_trace") * 1e-3) / 1e9 if avg("ff_trace") > 0 else None,
         "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())},
         "roofline": {"kernel": "batch_bounces", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS if achieved else None,
+                     "traffic": measured_traffic("batch_bounces"),
                      "bytes_per_launch": per_bounce, "launches_per_graph": nb},
     }
     print(json.dumps(result))

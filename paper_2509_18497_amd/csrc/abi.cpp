@@ -1117,6 +1117,16 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
         return fail(e);
     if ((e = batch_order_rows(b->dev(), F->row_ptr.as<int64_t>(), b->temp.p, b->temp.bytes, st)) != GSRAD_OK)
         return fail(e);
+    // scenes that all come from a ray cast: their rows in the receivers'
+    // Morton order, scene after scene, so the rows running together gather
+    // from one scene's nearby columns (replaces the cost order)
+    bool all_ordered = true;
+    for (int s = 0; s < n_scenes; ++s) all_ordered = all_ordered && ffs[s]->has_order;
+    if (all_ordered)
+        for (int s = 0; s < n_scenes; ++s)
+            if ((e = launch_offset_widen(ffs[s]->row_order.as<int32_t>(), ffs[s]->n, roff[s],
+                                         b->order.as<int64_t>() + roff[s], st)) != GSRAD_OK)
+                return fail(e);
     // the host vectors above are sources of asynchronous copies
     if ((e = check_hip(hipStreamSynchronize(st), "batch create sync")) != GSRAD_OK) return fail(e);
     b->nb = -1;

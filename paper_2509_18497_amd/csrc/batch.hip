@@ -5,9 +5,13 @@
 // val_off[s] of one array.
 //
 // Each bounce (and each adjoint step) is ONE persistent launch over all
-// scenes: groups of LPR lanes take rows from a global counter in an order
-// sorted by cost (entries x columns, largest first), so scenes of 2k and
-// 65k surfels and 8 or 100 lights share the chip without tail effects.
+// scenes: groups of LPR lanes take rows from a work queue (eight ranges,
+// one per XCD, drained by the others once their own is done), so scenes of
+// 2k and 65k surfels and 8 or 100 lights share the chip without tail
+// effects.  The queue holds each ray-cast scene's rows in the receivers'
+// Morton order, scene after scene (rows that one XCD takes together gather
+// from nearby columns), else all rows by cost (entries x columns, largest
+// first).
 // LPR (lanes per row: 64, 32 or 16) is the tile shape the autotuner picks;
 // every variant accumulates each output in the same order (the row's
 // entries in CSR order), so the choice never changes a result bit.
@@ -19,12 +23,27 @@ namespace gsrad {
 namespace {
 
 // Work-queue position -> row, for a group of LPR lanes: one lane takes the
-// next index and the group shares it.
+// next index and the group shares it.  The queue is cut into eight equal
+// ranges with a counter each; a group takes from the range of the XCD it
+// runs on first (consecutive rows of the order, nearby receivers of one
+// scene, share that XCD's L2) and from the others once it is drained.
+// Every position below `rows` is handed out exactly once; `rows` means done.
 template <int LPR>
-__device__ __forceinline__ int64_t next_row(uint32_t *counter, int lane_in_group, int group_base) {
-    uint32_t idx = 0;
-    if (lane_in_group == 0) idx = atomicAdd(counter, 1u);
-    return (int64_t)__shfl((int)idx, group_base, 64);
+__device__ __forceinline__ int64_t next_row(uint32_t *counter, int64_t rows, int lane_in_group, int group_base) {
+    int q = (int)rows;
+    if (lane_in_group == 0) {
+        const int xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7;   // HW_REG_XCC_ID
+        for (int t = 0; t < 8; ++t) {
+            const int x = (xcc + t) & 7;
+            const int64_t lo = rows * x / 8, len = rows * (x + 1) / 8 - lo;
+            const uint32_t idx = atomicAdd(counter + x, 1u);
+            if ((int64_t)idx < len) {
+                q = (int)(lo + idx);
+                break;
+            }
+        }
+    }
+    return (int64_t)__shfl(q, group_base, 64);
 }
 
 // out = E + rho * (F in) on the rows of all scenes (bounce), or
@@ -40,7 +59,7 @@ __global__ void __launch_bounds__(256) k_ragged_spmm(BatchDev bd, const int64_t 
     const int lig = lane % LPR;                 // lane in group
     const int gbase = lane - lig;               // first lane of the group
     for (;;) {
-        const int64_t q = next_row<LPR>(counter, lig, gbase);
+        const int64_t q = next_row<LPR>(counter, bd.rows, lig, gbase);
         if (q >= bd.rows) break;
         const int64_t row = bd.order[q];
         const int s = bd.row_scene[row];
@@ -104,7 +123,7 @@ __global__ void __launch_bounds__(256) k_ragged_sddmm(BatchDev bd, const int64_t
                                                       float *__restrict__ grad_rho, uint32_t *counter) {
     const int lane = __lane_id();
     for (;;) {
-        const int64_t q = next_row<64>(counter, lane, 0);
+        const int64_t q = next_row<64>(counter, bd.rows, lane, 0);
         if (q >= bd.rows) break;
         const int64_t row = bd.order[q];
         const int s = bd.row_scene[row];
@@ -161,7 +180,7 @@ __global__ void __launch_bounds__(256) k_ragged_sddmm_fast(BatchDev bd, const in
                                                            float *__restrict__ grad_rho, uint32_t *counter) {
     const int lane = __lane_id();
     for (;;) {
-        const int64_t q = next_row<64>(counter, lane, 0);
+        const int64_t q = next_row<64>(counter, bd.rows, lane, 0);
         if (q >= bd.rows) break;
         const int64_t row = bd.order[q];
         const int s = bd.row_scene[row];
@@ -238,7 +257,7 @@ __global__ void __launch_bounds__(256) k_ragged_sddmm_fast(BatchDev bd, const in
 }
 
 __global__ void k_reset_counter(uint32_t *counter) {
-    if (threadIdx.x == 0) counter[0] = 0u;
+    if (threadIdx.x < 8) counter[threadIdx.x] = 0u;
 }
 
 // row -> scene and the per-row cost (entries x columns) used for ordering
@@ -354,6 +373,12 @@ __global__ void __launch_bounds__(256) k_offset_copy_i64(const int64_t *__restri
         out[k] = in[k] + add;
 }
 
+__global__ void __launch_bounds__(256) k_offset_widen(const int32_t *__restrict__ in, int64_t n, int64_t add,
+                                                      int64_t *__restrict__ out) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+        out[k] = (int64_t)in[k] + add;
+}
+
 __global__ void __launch_bounds__(256) k_copy_f32(const float *__restrict__ in, int64_t n, float *__restrict__ out) {
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) out[k] = in[k];
 }
@@ -366,6 +391,12 @@ gsrad_status launch_offset_copy_i32(const int32_t *in, int64_t n, int32_t add, i
     if (n <= 0) return GSRAD_OK;
     hipLaunchKernelGGL(k_offset_copy_i32, dim3(grid_for(n)), dim3(256), 0, st, in, n, add, out);
     return check_hip(hipGetLastError(), "offset copy launch");
+}
+
+gsrad_status launch_offset_widen(const int32_t *in, int64_t n, int64_t add, int64_t *out, hipStream_t st) {
+    if (n <= 0) return GSRAD_OK;
+    hipLaunchKernelGGL(k_offset_widen, dim3(grid_for(n)), dim3(256), 0, st, in, n, add, out);
+    return check_hip(hipGetLastError(), "offset widen launch");
 }
 
 gsrad_status launch_offset_copy_i64(const int64_t *in, int64_t n, int64_t add, int64_t *out, hipStream_t st) {

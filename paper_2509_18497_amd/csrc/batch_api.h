@@ -13,7 +13,8 @@ struct BatchDev {
     const int64_t *val_off = nullptr;   // [scenes + 1] first value of each scene's [N_s][C_s] block
     const int32_t *scene_C = nullptr;   // [scenes] columns C_s = Lt_s * K * 3
     int32_t *row_scene = nullptr;       // [rows] scene of each row (filled by batch_order_rows)
-    const int64_t *order = nullptr;     // [rows] rows by cost, largest first (filled by batch_order_rows)
+    const int64_t *order = nullptr;     // [rows] the order the persistent kernels take rows in: each ray-cast
+                                        // scene's rows in Morton order, scene after scene, else by cost
 };
 
 size_t batch_order_temp_bytes(int64_t rows);
@@ -38,6 +39,8 @@ namespace gsrad {
 // out[k] = in[k] + add (index shifts of the block-diagonal CSR)
 gsrad_status launch_offset_copy_i32(const int32_t *in, int64_t n, int32_t add, int32_t *out, hipStream_t st);
 gsrad_status launch_offset_copy_i64(const int64_t *in, int64_t n, int64_t add, int64_t *out, hipStream_t st);
+// out[k] = (int64) in[k] + add
+gsrad_status launch_offset_widen(const int32_t *in, int64_t n, int64_t add, int64_t *out, hipStream_t st);
 // plain copy as a kernel (usable inside a captured graph)
 gsrad_status launch_copy_f32(const float *in, int64_t n, float *out, hipStream_t st);
 
