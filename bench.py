@@ -571,7 +571,49 @@ def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
                      "traffic": measured_traffic("batch_bounces"),
                      "bytes_per_launch": per_bounce, "launches_per_graph": nb},
     }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = batch_cpu_baseline(rooms, st, nnz, vals, np)
     print(json.dumps(result))
+
+
+def batch_cpu_baseline(rooms, st, nnz, vals, np, n_recv=1500):
+    """The FP64 oracle on the host cores on a bounded sample of the uneven
+    batch, scaled to one full step: form-factor rows and direct light of
+    n_recv receivers of the largest room (brute force, so a receiver costs
+    in proportion to its room's size; scaled by sum n_s^2 / n_big), plus the
+    bounces and adjoint of the smallest room on its ray-cast F (scaled by
+    stored entries x columns)."""
+    import oracle
+    import scipy.sparse as sp
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    big = max(range(len(rooms)), key=lambda s: rooms[s].n)
+    sm = min(range(len(rooms)), key=lambda s: rooms[s].n)
+    sc = rooms[big]
+    te = oracle.default_t_eps(sc.surfels)
+    recv = np.sort(np.random.default_rng(13).choice(sc.n, size=n_recv, replace=False)).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.ff_rows(sc.surfels, recv, sc.R, sc.seed, te, sc.t_min, 512, n_threads=threads)
+    oracle.direct_light(sc.surfels, sc.albedo, sc.light_pos, sc.light_I, sc.K, te, receivers=recv,
+                        n_threads=threads)
+    t_rows = time.perf_counter() - t0
+    scale_rows = sum(r.n * r.n for r in rooms) / sc.n / n_recv
+    s = rooms[sm]
+    rp, col, val = (x.cpu().numpy() for x in st["ff"][sm].csr())
+    F = sp.csr_matrix((val.astype(np.float64), col, rp), shape=(s.n, s.n))
+    rho = st["rhos"][sm].cpu().numpy().astype(np.float64)
+    E = st["Es"][sm].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    _, tape = oracle.bounce(F, rho, E, s.n_bounces, keep_tape=True)
+    oracle.adjoint(F, rho, tape, E)
+    t_lin = time.perf_counter() - t0
+    C = s.n_lights * s.K * 3
+    # linear algebra in proportion to stored entries x columns (vals / rows = mean columns per row)
+    t_step = t_rows * scale_rows + t_lin * (nnz * (vals / sum(r.n for r in rooms))) / max(F.nnz * C, 1)
+    return {"value": 1.0 / t_step, "unit": "batch solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_recv} receivers of the largest room ({sc.n} surfels; form-factor rows and direct light, "
+                      f"brute force) scaled by sum n_s^2 / n_big, plus bounces+adjoint of the smallest room "
+                      f"({s.n} surfels, {F.nnz} entries x {C} columns) scaled by entries x columns",
+            "seconds_measured": t_rows + t_lin}
 
 
 def _slice_inputs(scenes, np, N, Lt, K, lights):
