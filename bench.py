@@ -29,7 +29,7 @@ METRIC = "fwd+bwd transport solves/s + Grays/s at 100k surfels, rel err <=1e-3 v
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 
-# Algorithmic work per unit ("Rooflines"):
+# Algorithmic work per unit (operation counts of the traversal, hit test and compositing):
 FLOP_BOX = 24      # one ray / box slab test
 FLOP_HIT = 40      # one ray / surfel hit decision
 FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
