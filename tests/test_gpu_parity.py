@@ -150,6 +150,17 @@ def test_form_factors_rays_not_multiple_of_wave(g, orc):
     assert rel_err(Fg.toarray(), Fo.toarray()) < TOL
 
 
+@pytest.mark.parametrize("R,topk,n", [(1, 1, 800), (1, 0, 800), (1100, 0, 300), (64, 1, 800)])
+def test_form_factors_degenerate_ray_counts_and_topk(g, orc, R, topk, n):
+    """One ray per receiver, more rays than one 1024-ray pool, and top-1
+    rows (the selection keeps the largest entry, ties by column)."""
+    sc = _scene("box_room", n=n)
+    Fg, Fo, _, _ = _ff_compare(g, orc, sc, R, topk, seed=21)
+    assert rel_err(Fg.toarray(), Fo.toarray()) < TOL
+    if topk:
+        assert np.all(np.diff(Fg.indptr) <= topk)
+
+
 # ---------------------------------------------------------------------------
 # direct light
 # ---------------------------------------------------------------------------
