@@ -181,6 +181,7 @@ def test_direct_light_matches_oracle(g, orc, name, kw, K):
 # bounces and adjoint (operator level: seeded F, E, rho, grad_B)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,k,Lt,K,nb", [(700, 40, 1, 16, 8), (513, 17, 3, 9, 5), (300, 64, 1, 1, 3),
+                                         (400, 20, 1, 16, 12),   # more bounces than the fast SDDMM holds
                                          (257, 0, 2, 4, 2), (1000, 30, 2, 16, 0), (129, 5, 1, 9, 1)])
 def test_bounce_and_adjoint_match_oracle(g, orc, n, k, Lt, K, nb):
     rp, c, v = scenes.seeded_csr(n, k, seed=n + k)
