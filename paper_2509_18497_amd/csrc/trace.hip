@@ -430,11 +430,20 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
         const uint32_t m = min(rcnt[slot * R + r], (uint32_t)rcap);
         const uint2 *in = recs + slot * rcap * R + r;
         float T = 1.0f;
+        // the record one step ahead and its sender's c, the record two
+        // steps ahead: each load has a record's work to land
+        uint2 h1 = m > 0 ? in[0] : make_uint2(0u, 0u);
+        uint2 h2 = m > 1 ? in[(int64_t)R] : make_uint2(0u, 0u);
+        float c1 = m > 0 ? bv.c[h1.x] : 0.0f;
         for (uint32_t q = 0; q < m; ++q) {
             if ((q & 7) == 0 && *abort_v) break;
-            const uint2 h = in[(int64_t)q * R];
+            const uint2 h = h1;
+            const float cq = c1;
+            h1 = h2;
+            if (q + 2 < m) h2 = in[(int64_t)(q + 2) * R];
+            if (q + 1 < m) c1 = bv.c[h1.x];
             const float gs = __uint_as_float(h.y);
-            const float x = bv.c[h.x] * fabsf(gs);
+            const float x = cq * fabsf(gs);
             if (gs > 0.0f) {
                 const float w = -expm1f(-x) * T;
                 const unsigned long long fx = (unsigned long long)__float2ull_rn(w * kFixScaleF);
