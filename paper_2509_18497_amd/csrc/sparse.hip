@@ -32,10 +32,17 @@ __global__ void __launch_bounds__(256) k_expand_rows(const int64_t *__restrict__
     }
 }
 
-__global__ void __launch_bounds__(256) k_col_hist(const int32_t *__restrict__ col, int64_t nnz,
-                                                  uint32_t *__restrict__ cnt) {
-    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * 256)
-        atomicAdd(&cnt[col[k]], 1u);
+// Row pointers of the transpose from the column-sorted keys: position p of
+// the sorted list starts every column c with keys[p-1] < c <= keys[p]
+// (keys[-1] = -1, keys[nnz] = n), so each of the n + 1 pointers is written
+// exactly once.
+__global__ void __launch_bounds__(256) k_col_bounds(const uint32_t *__restrict__ keys, int64_t nnz, int64_t n,
+                                                    int64_t *__restrict__ t_row_ptr) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p > nnz) return;
+    const int64_t a = p == 0 ? -1 : (int64_t)keys[p - 1];
+    const int64_t b = p == nnz ? n : (int64_t)keys[p];
+    for (int64_t c = a + 1; c <= b; ++c) t_row_ptr[c] = p;
 }
 
 __global__ void __launch_bounds__(256) k_transpose_gather(const uint32_t *__restrict__ sorted_ids,
@@ -334,9 +341,7 @@ size_t transpose_temp_bytes(int64_t n, int64_t nnz) {
     size_t b = 0;
     b += 4 * ((size_t)nnz * 4 + 256);       // rows, keys, ids, sorted keys
     b += (size_t)nnz * 4 + 256;             // sorted ids
-    b += (size_t)n * 4 + 256;               // column counts
     b += radix_temp_bytes(nnz) + 256;
-    b += scan_temp_bytes(n) + 256;
     return b;
 }
 
@@ -355,21 +360,15 @@ gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, flo
     uint32_t *ids = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
     uint32_t *skeys = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
     uint32_t *sids = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(carve(p, (size_t)n * 4));
     const size_t rbytes = radix_temp_bytes(nnz);
     void *rtemp = carve(p, rbytes);
-    const size_t sbytes = scan_temp_bytes(n);
-    void *stemp = carve(p, sbytes);
     if ((size_t)(p - static_cast<char *>(temp)) > temp_bytes) {
         set_error("transpose: temp too small");
         return GSRAD_EINVAL;
     }
-    gsrad_status s = check_hip(hipMemsetAsync(cnt, 0, (size_t)n * 4, st), "transpose memset");
-    if (s != GSRAD_OK) return s;
+    gsrad_status s;
     if (nnz > 0) {
         hipLaunchKernelGGL(k_expand_rows, dim3(row_blocks(n)), dim3(256), 0, st, A.row_ptr, n, rows, keys, A.col, ids);
-        const unsigned hb = (unsigned)std::min<int64_t>(4096, (nnz + 255) / 256);
-        hipLaunchKernelGGL(k_col_hist, dim3(hb), dim3(256), 0, st, A.col, nnz, cnt);
         int bits = 1;
         while (bits < 32 && ((int64_t)1 << bits) < n) ++bits;
         s = radix_sort_pairs(keys, ids, skeys, sids, nnz, bits, rtemp, rbytes, st);
@@ -377,8 +376,8 @@ gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, flo
         hipLaunchKernelGGL(k_transpose_gather, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, sids, rows,
                            A.val, nnz, t_col, t_val, perm);
     }
-    s = exclusive_scan_u32_i64(cnt, t_row_ptr, n, stemp, sbytes, st);
-    if (s != GSRAD_OK) return s;
+    hipLaunchKernelGGL(k_col_bounds, dim3((unsigned)((nnz + 1 + 255) / 256)), dim3(256), 0, st, skeys, nnz, n,
+                       t_row_ptr);
     return check_hip(hipGetLastError(), "transpose");
 }
 
