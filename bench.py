@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 113828.04e6, "write": 10907.93e6,
+    "ff_trace": {"fetch": 114036.70e6, "write": 10910.45e6,
                  "files": ["trace.hip", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "0f573283ebf8e59f4066946b6f22f28cacd904ceadbbcdc7abcbe8981703ba7c",
+                 "sha256": "bfc7fe2947bbaf19a32308b883ac05bc29eb265ad07ae5b63a1f5c19cb92ad09",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
     "dense_grad_F": {"fetch": 218977.99e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],
