@@ -60,3 +60,16 @@ def test_bad_surfel_count_is_einval(L):
     s = _Surfels(*([None] * 15), 10)
     assert L.gsrad_build_bvh(ctypes.byref(s), ctypes.byref(h), None) == -1
     assert h.value is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for several exits with a
+    message instead of reporting a figure."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+    assert not r.stdout.strip().startswith("{")
