@@ -122,6 +122,29 @@ def test_form_factors_match_oracle(g, orc, name, kw, R, topk):
     assert np.asarray(Fg.sum(axis=1)).max() <= 1.0 + 1e-6
 
 
+def test_reused_handles_follow_new_surfels(g, orc):
+    """An optimisation loop reuses its BVH and F handles while opacities
+    and positions change: each re-cast on the reused handles equals a cast
+    on fresh handles bit for bit, and matches the oracle."""
+    sc = _scene("fruit_bowl", n=2500)
+    sur = {k: v.copy() for k, v in sc.surfels.items()}
+    bvh = g.build_bvh(dev_surfels(sur))
+    ff = g.form_factors(bvh, 32, sc.seed, t_min=1e-4, topk=48)
+    rng = np.random.default_rng(5)
+    for it in range(3):
+        sur["opacity"] = np.clip(sur["opacity"] * rng.uniform(0.8, 1.0, sur["opacity"].shape), 0.05, 0.99
+                                 ).astype(np.float32)
+        sur["px"] = (sur["px"] + rng.normal(0, 1e-3, sur["px"].shape)).astype(np.float32)
+        bvh = g.build_bvh(dev_surfels(sur), bvh)
+        ff = g.form_factors(bvh, 32, sc.seed, t_min=1e-4, topk=48, ff=ff)
+        fresh = g.form_factors(g.build_bvh(dev_surfels(sur)), 32, sc.seed, t_min=1e-4, topk=48)
+        for x, y in zip(ff.csr(), fresh.csr()):
+            assert torch.equal(x, y), it
+    Fg = gpu_csr(ff)
+    Fo, _ = orc.ff_matrix(sur, 32, sc.seed, orc.default_t_eps(sur), 1e-4, 48)
+    assert rel_err(Fg.toarray(), Fo.toarray()) < TOL
+
+
 def test_form_factors_are_deterministic(g):
     sc = _scene("fruit_bowl", n=6000)
     bvh = g.build_bvh(dev_surfels(sc.surfels))
