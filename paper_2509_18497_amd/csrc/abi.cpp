@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -129,7 +130,8 @@ static void prof_clear() {
 using namespace gsrad;
 
 struct gsrad_bvh {
-    int64_t n = 0;
+    int64_t n = 0;               // 0 after a failed (re)build: unusable
+    uint64_t gen = 0;            // unique per successful build
     hipStream_t stream = nullptr;
     DevBuf rec, nodes, leafbox, leaf_parent, inv, cst, opc, opraw, area, bounds, height, temp;
     BvhBuffers B;
@@ -153,7 +155,7 @@ struct gsrad_bvh {
 };
 
 struct gsrad_ff {
-    int64_t n = 0, nnz = 0;
+    int64_t n = 0, nnz = 0;      // n = 0 after a failed (re)fill: unusable
     int max_row = 0;
     DevBuf row_ptr, col, val;
     // transpose, built on first use by the backward
@@ -164,6 +166,7 @@ struct gsrad_ff {
     DevBuf t_row_ptr, t_col, t_val, perm, t_temp;
     // provenance for the opacity backward
     const gsrad_bvh *bvh = nullptr;
+    uint64_t bvh_gen = 0;
     int R = 0, topk = 0;
     uint64_t seed = 0;
     float t_eps = 0.0f, t_min = 0.0f;
@@ -175,6 +178,8 @@ struct gsrad_ff {
     int deep_stack = 0, agg_log2h = 0;
     // scratch of the ray-cast path
     DevBuf slab, ell_col, ell_val, row_len, err, scan_temp, redo;
+    // opacity backward: per-XCD fixed-point accumulators and scale
+    DevBuf opac;
     // dense BF16 copies (gsrad_ff_dense): F and F^T, hi and lo parts
     bool has_dense = false;
     int64_t Np = 0;
@@ -202,7 +207,7 @@ struct gsrad_ff {
     }
     ~gsrad_ff() {
         for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col, &redo, &row_order,
-                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl})
+                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl, &opac})
             b->release();
     }
 };
@@ -287,6 +292,34 @@ inline gsrad_status einval(const char *msg) {
 
 bool valid_K(int K) { return K == 1 || K == 4 || K == 9 || K == 16; }
 
+std::atomic<uint64_t> g_build_gen{0};
+
+// A handle whose last (re)build or (re)fill failed part-way is left with
+// n = 0 and refuses every later use until it is rebuilt.
+gsrad_status usable(const gsrad_bvh *b, const char *fn) {
+    if (b->n >= 1) return GSRAD_OK;
+    set_error("%s: the BVH handle is unusable after a failed gsrad_build_bvh", fn);
+    return GSRAD_ESTATE;
+}
+
+gsrad_status usable(const gsrad_ff *f, const char *fn) {
+    if (f->n >= 1) return GSRAD_OK;
+    set_error("%s: the F handle is unusable after a failed call that refilled it", fn);
+    return GSRAD_ESTATE;
+}
+
+void invalidate(gsrad_ff *f) {
+    f->n = 0;
+    f->nnz = 0;
+    f->max_row = 0;
+    f->has_t = false;
+    f->has_order = false;
+    f->has_records = false;
+    f->has_dense = false;
+    f->bvh = nullptr;
+    f->bvh_gen = 0;
+}
+
 __global__ void k_max_u32(const uint32_t *__restrict__ v, int64_t n, int *out) {
     int m = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -335,6 +368,8 @@ gsrad_status gsrad_build_bvh(const gsrad_surfels *s, gsrad_bvh **bvh, void *stre
     gsrad_bvh *h = created ? new gsrad_bvh() : *bvh;
     const int64_t n = s->n;
     hipStream_t st = S(stream);
+    h->n = 0;   // unusable until this build succeeds
+    h->gen = 0;
     auto fail = [&](gsrad_status e) {
         if (created) delete h;
         return e;
@@ -355,7 +390,6 @@ gsrad_status gsrad_build_bvh(const gsrad_surfels *s, gsrad_bvh **bvh, void *stre
     ENS(height, 64, "height");
     ENS(temp, bvh_temp_bytes(n), "bvh temp");
 #undef ENS
-    h->n = n;
     h->stream = st;
     BvhBuffers &B = h->B;
     B.rec = h->rec.as<SurfRec>();
@@ -376,6 +410,8 @@ gsrad_status gsrad_build_bvh(const gsrad_surfels *s, gsrad_bvh **bvh, void *stre
         ProfScope ps("bvh_build", st);
         if ((e = bvh_build(*s, B, st)) != GSRAD_OK) return fail(e);
     }
+    h->n = n;
+    h->gen = ++g_build_gen;
     *bvh = h;
     return GSRAD_OK;
 }
@@ -394,18 +430,21 @@ gsrad_status gsrad_bvh_info(const gsrad_bvh *bvh, int64_t *n, float *t_eps_defau
 
 gsrad_status gsrad_bvh_height(const gsrad_bvh *bvh, int32_t *height) {
     if (!bvh || !height) return einval("gsrad_bvh_height: null argument");
+    GS_TRY(usable(bvh, "gsrad_bvh_height"));
     GS_TRY(check_hip(hipStreamSynchronize(bvh->stream), "bvh height sync"));
     return check_hip(hipMemcpy(height, bvh->B.height, sizeof(int32_t), hipMemcpyDeviceToHost), "bvh height copy");
 }
 
 gsrad_status gsrad_effective_area(const gsrad_bvh *bvh, double *area_out, void *stream) {
     if (!bvh || !area_out) return einval("gsrad_effective_area: null argument");
+    GS_TRY(usable(bvh, "gsrad_effective_area"));
     return check_hip(hipMemcpyAsync(area_out, bvh->B.area, (size_t)bvh->n * 8, hipMemcpyDeviceToDevice, S(stream)),
                      "effective area copy");
 }
 
 gsrad_status gsrad_reflectance(const gsrad_bvh *bvh, const float *albedo, float *rho_out, void *stream) {
     if (!bvh || !albedo || !rho_out) return einval("gsrad_reflectance: null argument");
+    GS_TRY(usable(bvh, "gsrad_reflectance"));
     return launch_reflectance(bvh->dev(), albedo, rho_out, S(stream));
 }
 
@@ -416,8 +455,13 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     if (p->topk < 0 || p->topk > (1 << kLog2Table)) return einval("gsrad_form_factors: topk must be in [0, 4096]");
     if (!(p->t_min >= 0.0f) || !(p->t_min <= 1.0f)) return einval("gsrad_form_factors: t_min must be in [0, 1]");
     if (!std::isfinite(p->t_eps)) return einval("gsrad_form_factors: t_eps must be finite");
+    GS_TRY(usable(bvh, "gsrad_form_factors"));
     const bool created = *ff == nullptr;
     gsrad_ff *h = created ? new gsrad_ff() : *ff;
+    // a reused handle is unusable until this call succeeds (its buffers are
+    // overwritten or reallocated on the way)
+    const int prev_rec_cap = h->rec_cap, prev_log2h = h->agg_log2h, prev_deep = h->deep_stack;
+    invalidate(h);
     auto fail = [&](gsrad_status e) {
         if (created) delete h;
         return e;
@@ -427,9 +471,9 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     const int R = p->rays_per_surfel;
     // a handle traced before starts from the record slots, stack and
     // aggregation table its last call needed (the rows do not depend on them)
-    int rcap = created ? kRecCap : std::max(kRecCap, h->rec_cap);
-    const int log2h = created ? kLog2Table : std::max(kLog2Table, h->agg_log2h);
-    int deep = created ? 0 : h->deep_stack;
+    int rcap = created ? kRecCap : std::max(kRecCap, prev_rec_cap);
+    const int log2h = created ? kLog2Table : std::max(kLog2Table, prev_log2h);
+    int deep = created ? 0 : prev_deep;
     const int64_t cap_row = p->topk > 0 ? p->topk : (1 << kLog2TableMax);
     gsrad_status e;
     float t_eps = p->t_eps;
@@ -527,6 +571,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     h->has_order = true;
     h->has_dense = false;
     h->bvh = bvh;
+    h->bvh_gen = bvh->gen;
     h->R = R;
     h->topk = p->topk;
     h->seed = p->seed;
@@ -558,6 +603,7 @@ gsrad_status gsrad_ff_view(const gsrad_ff *ff, const int64_t **row_ptr, const in
 
 gsrad_status gsrad_ff_copy(const gsrad_ff *ff, int64_t *row_ptr, int32_t *col, float *val, void *stream) {
     if (!ff || !row_ptr || (ff->nnz > 0 && (!col || !val))) return einval("gsrad_ff_copy: null argument");
+    GS_TRY(usable(ff, "gsrad_ff_copy"));
     hipStream_t st = S(stream);
     GS_TRY(check_hip(hipMemcpyAsync(row_ptr, ff->row_ptr.p, (size_t)(ff->n + 1) * 8, hipMemcpyDeviceToDevice, st),
                      "ff copy row_ptr"));
@@ -574,6 +620,7 @@ gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (n < 1 || nnz < 0 || nnz >= ((int64_t)1 << 32)) return einval("gsrad_ff_from_csr: bad size");
     const bool created = *ff == nullptr;
     gsrad_ff *h = created ? new gsrad_ff() : *ff;
+    invalidate(h);
     auto fail = [&](gsrad_status e) {
         if (created) delete h;
         return e;
@@ -614,6 +661,7 @@ gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, c
 
 gsrad_status gsrad_ff_dense(gsrad_ff *ff, void *stream) {
     if (!ff) return einval("gsrad_ff_dense: null handle");
+    GS_TRY(usable(ff, "gsrad_ff_dense"));
     if (ff->n < 1) return einval("gsrad_ff_dense: empty operator");
     hipStream_t st = S(stream);
     const int64_t Np = dense_pad(ff->n);
@@ -634,6 +682,7 @@ gsrad_status gsrad_ff_dense(gsrad_ff *ff, void *stream) {
 gsrad_status gsrad_direct_light(const gsrad_bvh *bvh, const float *albedo, const float *light_pos,
                                 const float *light_I, int32_t n_lights, int32_t K, float *E_out, void *stream) {
     if (!bvh || !albedo || !light_pos || !light_I || !E_out) return einval("gsrad_direct_light: null argument");
+    GS_TRY(usable(bvh, "gsrad_direct_light"));
     if (n_lights < 1) return einval("gsrad_direct_light: n_lights must be >= 1");
     if (!valid_K(K)) return einval("gsrad_direct_light: K must be 1, 4, 9 or 16");
     hipStream_t st = S(stream);
@@ -787,6 +836,7 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
                                    int32_t n_bounces, int32_t precision, float *B_out, gsrad_tape **tape,
                                    void *stream) {
     if (!ff || !rho || !E || !B_out) return einval("gsrad_transport_solve: null argument");
+    GS_TRY(usable(ff, "gsrad_transport_solve"));
     if (n_lights < 1) return einval("gsrad_transport_solve: n_lights must be >= 1");
     if (!valid_K(K)) return einval("gsrad_transport_solve: K must be 1, 4, 9 or 16");
     if (n_bounces < 0 || n_bounces > 4096) return einval("gsrad_transport_solve: n_bounces must be in [0, 4096]");
@@ -857,6 +907,7 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
                                       const float *grad_B, float *grad_E, float *grad_rho, float *grad_F,
                                       void *stream) {
     if (!ff || !tape || !rho || !grad_B || !grad_E) return einval("gsrad_transport_backward: null argument");
+    GS_TRY(usable(ff, "gsrad_transport_backward"));
     if (tape->ff != ff || tape->n != ff->n) return einval("gsrad_transport_backward: tape does not belong to this F");
     hipStream_t st = S(stream);
     gsrad_ff *f = const_cast<gsrad_ff *>(ff);
@@ -900,43 +951,52 @@ gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, co
                                     const float *grad_rho, const float *albedo, float *grad_opacity,
                                     float *grad_albedo, void *stream) {
     if (!bvh || !ff) return einval("gsrad_opacity_backward: null handle");
-    if (grad_F && ff->bvh != bvh)
-        return einval("gsrad_opacity_backward: the F handle was not made from this BVH by gsrad_form_factors");
+    GS_TRY(usable(bvh, "gsrad_opacity_backward"));
+    if (grad_F) {
+        GS_TRY(usable(ff, "gsrad_opacity_backward"));
+        if (ff->bvh != bvh || ff->bvh_gen != bvh->gen || ff->n != bvh->n)
+            return einval("gsrad_opacity_backward: the F handle was not made by gsrad_form_factors from this BVH "
+                          "as it is now (it was rebuilt since)");
+    }
     if (grad_rho && !albedo) return einval("gsrad_opacity_backward: grad_rho needs albedo");
     hipStream_t st = S(stream);
     gsrad_ff *f = const_cast<gsrad_ff *>(ff);
     const int64_t n = bvh->n;
-    GS_TRY(f->t_temp.ensure(std::max(f->t_temp.bytes, (size_t)n * 8), "opacity accumulators"));
-    double *gacc = f->t_temp.as<double>();
-    GS_TRY(check_hip(hipMemsetAsync(gacc, 0, (size_t)n * 8, st), "opacity zero"));
-    if (grad_F && f->nnz > 0) {
+    const size_t acc_bytes = opacity_acc_bytes(n);
+    GS_TRY(f->opac.ensure(acc_bytes, "opacity accumulators"));
+    void *acc = f->opac.p;
+    GS_TRY(check_hip(hipMemsetAsync(acc, 0, acc_bytes, st), "opacity zero"));
+    const bool with_F = grad_F && f->nnz > 0;
+    GS_TRY(launch_opacity_scale(with_F ? grad_F : nullptr, f->nnz, n, acc, st));
+    if (with_F) {
         if ((size_t)f->max_row * 8 + ff_stack_bytes(256) > 150 * 1024)
             return einval("gsrad_opacity_backward: row too long for the LDS row cache");
         if (f->has_records) {
             ProfScope ps("opacity_records", st);
             GS_TRY(launch_opacity_rec(bvh->dev(), f->R, f->recs.as<uint2>(), f->rcnt.as<uint32_t>(), f->rec_cap,
                                       f->row_ptr.as<int64_t>(), f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1),
-                                      gacc, st));
+                                      acc, st));
         } else {
             // recompute the rays without (complete) records by traversal
-            GS_TRY(f->slab.ensure(std::max(f->slab.bytes, (size_t)n * f->R * 4), "ray sums"));
+            GS_TRY(f->slab.ensure(std::max(f->slab.bytes, (size_t)n * f->R * sizeof(float2)), "ray sums"));
             GS_TRY(f->err.ensure(128, "flags"));
             for (int pass = 0; pass < 2; ++pass) {
                 ProfScope ps(pass == 0 ? "opacity_pass1" : "opacity_pass2", st);
                 GS_TRY(launch_opacity_bwd(bvh->dev(), f->R, f->seed, f->t_eps, f->t_min, f->row_ptr.as<int64_t>(),
-                                          f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1), f->slab.as<float>(),
-                                          gacc, pass, nullptr, 0, f->err.as<int>() + 8, st));
+                                          f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1), f->slab.as<float2>(),
+                                          acc, pass, nullptr, 0, f->err.as<int>() + 8, st));
             }
         }
     }
     ProfScope ps("opacity_finish", st);
-    return launch_opacity_finish(bvh->dev(), gacc, grad_rho, albedo, grad_opacity, grad_albedo, st);
+    return launch_opacity_finish(bvh->dev(), acc, grad_rho, albedo, grad_opacity, grad_albedo, st);
 }
 
 gsrad_status gsrad_ray_hits(const gsrad_bvh *bvh, const gsrad_ff_params *p, const int64_t *receivers,
                             int64_t n_receivers, int32_t max_hits, float *dirs, int32_t *count, int32_t *hit_j,
                             float *hit_t, int8_t *hit_front, float *hit_T, void *stream) {
     if (!bvh || !p || !receivers || !dirs || !count) return einval("gsrad_ray_hits: null argument");
+    GS_TRY(usable(bvh, "gsrad_ray_hits"));
     if (max_hits < 0 || (max_hits > 0 && (!hit_j || !hit_t || !hit_front || !hit_T)))
         return einval("gsrad_ray_hits: bad hit buffers");
     if (p->rays_per_surfel < 1 || n_receivers < 1) return einval("gsrad_ray_hits: bad sizes");
@@ -949,6 +1009,7 @@ gsrad_status gsrad_ray_hits(const gsrad_bvh *bvh, const gsrad_ff_params *p, cons
 gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, const float *B, int32_t n_lights,
                          int32_t K, double *out_host, void *stream) {
     if (!ff || !rho || !E || !B || !out_host) return einval("gsrad_check: null argument");
+    GS_TRY(usable(ff, "gsrad_check"));
     if (n_lights < 1 || !valid_K(K)) return einval("gsrad_check: bad n_lights or K");
     hipStream_t st = S(stream);
     gsrad_ff *f = const_cast<gsrad_ff *>(ff);
@@ -971,6 +1032,8 @@ gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, c
 
 gsrad_status gsrad_check_reciprocity(const gsrad_bvh *bvh, const gsrad_ff *ff, double *out_host, void *stream) {
     if (!bvh || !ff || !out_host) return einval("gsrad_check_reciprocity: null argument");
+    GS_TRY(usable(bvh, "gsrad_check_reciprocity"));
+    GS_TRY(usable(ff, "gsrad_check_reciprocity"));
     if (bvh->n != ff->n) return einval("gsrad_check_reciprocity: the BVH and F have different sizes");
     hipStream_t st = S(stream);
     gsrad_ff *f = const_cast<gsrad_ff *>(ff);
@@ -1035,7 +1098,7 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
     int max_row = 0;
     for (int s = 0; s < n_scenes; ++s) {
         if (!ffs[s] || ffs[s]->n < 1) {
-            set_error("gsrad_batch_create: scene %d has no operator", s);
+            set_error("gsrad_batch_create: scene %d has no (usable) operator", s);
             return GSRAD_EINVAL;
         }
         if (lights[s] < 1) {
@@ -1058,9 +1121,17 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
     const bool reuse = b && b->S == n_scenes && b->K == K && b->rows == roff[n_scenes] && b->vals == voff[n_scenes] &&
                        b->scene_rows == std::vector<int64_t>(roff.begin(), roff.end()) && b->scene_cols == Cs;
     const bool created = !reuse;
+    gsrad_batch *const old = created ? *batch : nullptr;   // replaced on success
     if (created) b = new gsrad_batch();
     auto fail = [&](gsrad_status e) {
-        if (created) delete b;
+        if (created) {
+            delete b;
+        } else {
+            // a batch refilled part-way is unusable until refilled again
+            b->drop_graph();
+            b->nb = -1;
+            if (b->F) invalidate(b->F);
+        }
         return e;
     };
     gsrad_status e;
@@ -1131,6 +1202,7 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
     if ((e = check_hip(hipStreamSynchronize(st), "batch create sync")) != GSRAD_OK) return fail(e);
     b->nb = -1;
     *batch = b;
+    if (old) delete old;
     return GSRAD_OK;
 }
 
@@ -1190,6 +1262,10 @@ gsrad_status autotune_lanes(gsrad_batch *b, const Csr &F, bool adjoint, const fl
 gsrad_status gsrad_batch_transport_solve(gsrad_batch *b, const float *rho, const float *E, int32_t n_bounces,
                                          float *B_out, void *stream) {
     if (!b || !rho || !E || !B_out) return einval("gsrad_batch_transport_solve: null argument");
+    if (!b->F || b->F->n < 1) {
+        set_error("gsrad_batch_transport_solve: the batch is unusable after a failed refill");
+        return GSRAD_ESTATE;
+    }
     if (n_bounces < 0 || n_bounces > 4096) return einval("gsrad_batch_transport_solve: n_bounces must be in [0, 4096]");
     hipStream_t st = S(stream);
     const int64_t vals = b->vals;

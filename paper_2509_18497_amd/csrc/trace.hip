@@ -672,10 +672,100 @@ __device__ __forceinline__ float row_lookup(const uint32_t *lc, const float *lg,
     return (lo < len && lc[lo] == j) ? lg[lo] : 0.0f;
 }
 
+// For one ray with composited hits q = 1..m (alpha_q, transmittance T_q in
+// front of the hit, kernel value g_q) and G_q = dL/dF[i, j_q] / R on front
+// hits kept in F (0 otherwise), the F-part of the loss is
+// sum_q G_q alpha_q T_q, so
+//   dL/dalpha_q = G_q T_q - S_q / (1 - alpha_q),  S_q = sum_{p>q} G_p alpha_p T_p
+//   dalpha_q/do = g_q (1 - o)^(g_q - 1) = g_q e^(c (1 - g_q)).
+// S_q = W - P_q (W the ray's total, P_q the running sum through q) is formed
+// in double-float arithmetic (pairs of FP32 with error-free sums and
+// products), so the difference keeps the digits that the division by
+// 1 - alpha_q (down to 1e-4) magnifies; 1 - alpha_q is the transmit factor
+// e^(-c g) the transmittance uses, not 1 minus the rounded alpha.
+//
+// The contributions are summed per sender in 64-bit fixed point: integer
+// adds commute, so the gradient is bit-identical between runs whatever the
+// order of the atomics.  The scale 2^e is a power of two chosen from
+// max|dL/dF| so that no sum can leave the int64 range: a contribution is at
+// most 2 max|G| max_g g e^(c(1-g)) <= 800 max|G| for c <= -ln(1e-4), and a
+// sender is composited at most once per ray (k_fx_exp).  Each XCD adds into
+// its own copy of the accumulators with atomics kept in its L2 (scope of
+// the workgroup: every workgroup that touches copy x runs on XCD x), and
+// k_opacity_finish adds the copies.
+struct DF {
+    float hi, lo;
+};
+
+__device__ __forceinline__ DF df_add(DF x, DF y) {
+    const float s = x.hi + y.hi;
+    const float bb = s - x.hi;
+    const float e = ((x.hi - (s - bb)) + (y.hi - bb)) + (x.lo + y.lo);
+    const float hi = s + e;
+    return {hi, e - (hi - s)};
+}
+
+// G * alpha * T as an unevaluated pair (relative error about 2^-46)
+__device__ __forceinline__ DF df_prod3(float G, float a, float T) {
+    const float p = a * T;
+    const float pe = __builtin_fmaf(a, T, -p);
+    const float h = G * p;
+    return {h, __builtin_fmaf(G, p, -h) + G * pe};
+}
+
+__device__ __forceinline__ int xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7;   // HW_REG_XCC_ID
+}
+
+__device__ __forceinline__ void fx_add(unsigned long long *acc, float v, float scale) {
+    const long long q = __float2ll_rn(v * scale);
+    if (q != 0)
+        __hip_atomic_fetch_add(acc, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One hit of the second walk: the sender's contribution to dL/do.
+__device__ __forceinline__ void opacity_hit(const BvhDev &bv, uint32_t j, float G, float alpha, float f, float T,
+                                            float g, DF W, DF &P, unsigned long long *acc, float scale) {
+    if (G != 0.0f) P = df_add(P, df_prod3(G, alpha, T));
+    const float oraw = bv.raw_op[j];
+    if (!(oraw > 0.0f && oraw < kOpacityMax)) return;
+    const DF Sd = df_add(W, DF{-P.hi, -P.lo});
+    const float dLda = G * T - Sd.hi / f;
+    const float dado = g * expf(bv.c[j] * (1.0f - g));
+    fx_add(acc + j, dLda * dado, scale);
+}
+
+// max |dL/dF| as float bits (non-negative floats order like their bits)
+__global__ void __launch_bounds__(256) k_absmax(const float *__restrict__ v, int64_t n, uint32_t *out) {
+    uint32_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = max(m, __float_as_uint(fabsf(v[i])));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if (__lane_id() == 0) atomicMax(out, m);
+}
+
+// exponent e of the fixed-point scale: 801 max|dL/dF| n < 2^(62 - e)
+// (max|G| = max|dL/dF| / R, at most n R rays); kFxNonFinite marks a
+// non-finite dL/dF (the gradient is then NaN)
+constexpr int kFxNonFinite = 1 << 20;
+__global__ void k_fx_exp(const uint32_t *maxbits, int64_t n, int *e_out) {
+    const float m = __uint_as_float(*maxbits);
+    int e = 0;
+    if (!(m <= 3.0e38f)) {
+        e = kFxNonFinite;
+    } else if (m > 0.0f) {
+        int ex;
+        (void)frexpf(801.0f * m * (float)n, &ex);
+        e = min(120, max(-120, 62 - ex));
+    }
+    *e_out = e;
+}
+
 __global__ void __launch_bounds__(256) k_opacity_bwd(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
                                                      int64_t nblocks, const int64_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, const float *__restrict__ gF,
-                                                     int max_row, float *__restrict__ wbuf, double *gacc, int pass,
+                                                     int max_row, float2 *__restrict__ wbuf, const int *fx_exp,
+                                                     unsigned long long *acc, int pass,
                                                      const uint32_t *__restrict__ rcnt, int rcap, int *err) {
     extern __shared__ uint32_t sm2[];
     uint32_t *lc = sm2;                                   // [max_row]
@@ -688,6 +778,8 @@ __global__ void __launch_bounds__(256) k_opacity_bwd(BvhDev bv, int R, uint64_t 
     const int64_t e0 = row_ptr[i];
     const int len = (int)(row_ptr[i + 1] - e0);
     const float invR = 1.0f / (float)R;
+    const float scale = __builtin_ldexpf(1.0f, *fx_exp);
+    unsigned long long *my = acc + (int64_t)xcc_id() * bv.n;
     for (int k = tid; k < len; k += blockDim.x) {
         lc[k] = (uint32_t)col[e0 + k];
         lg[k] = gF[e0 + k] * invR;
@@ -700,27 +792,23 @@ __global__ void __launch_bounds__(256) k_opacity_bwd(BvhDev bv, int R, uint64_t 
         ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
                       (uint64_t)i, seed, 0, dx, dy, dz);
         if (pass == 0) {
-            float W = 0.0f;
+            DF W{0.0f, 0.0f};
             trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x,
                               err, [&](uint32_t j, float alpha, float T, bool front, float, float) {
-                                  if (front) W += row_lookup(lc, lg, len, j) * alpha * T;
+                                  const float G = front ? row_lookup(lc, lg, len, j) : 0.0f;
+                                  if (G != 0.0f) W = df_add(W, df_prod3(G, alpha, T));
                               });
-            wbuf[(int64_t)i * R + r] = W;
+            wbuf[(int64_t)i * R + r] = make_float2(W.hi, W.lo);
         } else {
-            const float W = wbuf[(int64_t)i * R + r];
-            float P = 0.0f;
+            const float2 w2 = wbuf[(int64_t)i * R + r];
+            const DF W{w2.x, w2.y};
+            if (W.hi == 0.0f) continue;   // every G_q alpha_q T_q is 0: no contribution
+            DF P{0.0f, 0.0f};
             trace_sorted<kKB>(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, i, t_eps, t_min, stack_mem + tid, blockDim.x,
                               err, [&](uint32_t j, float alpha, float T, bool front, float g, float) {
                                   const float G = front ? row_lookup(lc, lg, len, j) : 0.0f;
-                                  const float gw = G * alpha * T;
-                                  const float S = W - P - gw;
-                                  P += gw;
-                                  const float oraw = bv.raw_op[j];
-                                  if (oraw > 0.0f && oraw < kOpacityMax) {
-                                      const float dLda = G * T - S / (1.0f - alpha);
-                                      const float dado = g * expf(bv.c[j] * (1.0f - g));
-                                      unsafeAtomicAdd(&gacc[j], (double)(dLda * dado));
-                                  }
+                                  const float f = exp_fx(-__fmul_rn(bv.c[j], g));
+                                  opacity_hit(bv, j, G, alpha, f, T, g, W, P, my, scale);
                               });
         }
     }
@@ -744,7 +832,7 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
                                                      const uint32_t *__restrict__ rcnt, int rcap, int64_t nblocks,
                                                      const int64_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, const float *__restrict__ gF,
-                                                     int log2h, double *gacc) {
+                                                     int log2h, const int *fx_exp, unsigned long long *acc) {
     extern __shared__ uint32_t sm3[];
     const int H = 1 << log2h;
     uint32_t *hk = sm3;
@@ -757,6 +845,8 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
     const int64_t e0 = row_ptr[i];
     const int len = (int)(row_ptr[i + 1] - e0);
     const float invR = 1.0f / (float)R;
+    const float scale = __builtin_ldexpf(1.0f, *fx_exp);
+    unsigned long long *my = acc + (int64_t)xcc_id() * bv.n;
     for (int k = tid; k < len; k += blockDim.x) {
         const uint32_t j = (uint32_t)col[e0 + k];
         uint32_t h = hash_slot(j, log2h);
@@ -768,50 +858,50 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
         const uint32_t m = rcnt[(int64_t)i * R + r];
         if (m > (uint32_t)rcap) continue;
         const uint2 *in = recs + (int64_t)i * rcap * R + r;
-        float W = 0.0f, T = 1.0f;
+        DF W{0.0f, 0.0f};
+        float T = 1.0f;
         for (uint32_t q = 0; q < m; ++q) {
             const uint2 h = in[(int64_t)q * R];
             const float gs = __uint_as_float(h.y);
             const float x = bv.c[h.x] * fabsf(gs);
-            if (gs > 0.0f) W += row_hash_lookup(hk, hv, log2h, h.x) * (-expm1f(-x)) * T;
+            if (gs > 0.0f) {
+                const float G = row_hash_lookup(hk, hv, log2h, h.x);
+                if (G != 0.0f) W = df_add(W, df_prod3(G, -expm1f(-x), T));
+            }
             T = __fmul_rn(T, exp_fx(-x));
         }
-        float P = 0.0f;
+        if (W.hi == 0.0f) continue;   // every G_q alpha_q T_q is 0: no contribution
+        DF P{0.0f, 0.0f};
         T = 1.0f;
         for (uint32_t q = 0; q < m; ++q) {
             const uint2 h = in[(int64_t)q * R];
             const float gs = __uint_as_float(h.y);
             const float g = fabsf(gs);
-            const float c = bv.c[h.x];
-            const float x = c * g;
-            const float alpha = -expm1f(-x);
+            const float x = bv.c[h.x] * g;
+            const float f = exp_fx(-x);
             const float G = gs > 0.0f ? row_hash_lookup(hk, hv, log2h, h.x) : 0.0f;
-            const float gw = G * alpha * T;
-            const float S = W - P - gw;
-            P += gw;
-            const float oraw = bv.raw_op[h.x];
-            if (oraw > 0.0f && oraw < kOpacityMax) {
-                const float dLda = G * T - S / (1.0f - alpha);
-                const float dado = g * expf(c * (1.0f - g));
-                unsafeAtomicAdd(&gacc[h.x], (double)(dLda * dado));
-            }
-            T = __fmul_rn(T, exp_fx(-x));
+            opacity_hit(bv, h.x, G, -expm1f(-x), f, T, g, W, P, my, scale);
+            T = __fmul_rn(T, f);
         }
     }
 }
 
-__global__ void __launch_bounds__(256) k_opacity_finish(BvhDev bv, const double *__restrict__ gacc,
-                                                        const float *__restrict__ grad_rho,
+__global__ void __launch_bounds__(256) k_opacity_finish(BvhDev bv, const unsigned long long *__restrict__ acc,
+                                                        const int *fx_exp, const float *__restrict__ grad_rho,
                                                         const float *__restrict__ albedo, float *grad_o, float *grad_a) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= bv.n) return;
     const float oraw = bv.raw_op[i];
     const bool inside = oraw > 0.0f && oraw < kOpacityMax;
-    double g = gacc ? gacc[i] : 0.0;
+    unsigned long long s = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) s += acc[(int64_t)x * bv.n + i];
+    const int e = *fx_exp;
+    float g = e == kFxNonFinite ? __builtin_nanf("") : __builtin_ldexpf(__ll2float_rn((long long)s), -e);
     if (grad_rho && albedo && inside)
-        g += (double)grad_rho[3 * i] * albedo[3 * i] + (double)grad_rho[3 * i + 1] * albedo[3 * i + 1] +
-             (double)grad_rho[3 * i + 2] * albedo[3 * i + 2];
-    if (grad_o) grad_o[i] = (float)g;
+        g += grad_rho[3 * i] * albedo[3 * i] + grad_rho[3 * i + 1] * albedo[3 * i + 1] +
+             grad_rho[3 * i + 2] * albedo[3 * i + 2];
+    if (grad_o) grad_o[i] = g;
     if (grad_a) {
         const float o = bv.op[i];
         for (int c = 0; c < 3; ++c) grad_a[3 * i + c] = grad_rho ? grad_rho[3 * i + c] * o : 0.0f;
@@ -937,9 +1027,26 @@ gsrad_status launch_direct(const BvhDev &bv, const float *albedo, const float *l
     return check_hip(hipGetLastError(), "direct light launch");
 }
 
+size_t opacity_acc_bytes(int64_t n) { return (size_t)8 * n * sizeof(unsigned long long) + 256; }
+
+gsrad_status launch_opacity_scale(const float *gF, int64_t nnz, int64_t n, void *acc, hipStream_t st) {
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(static_cast<char *>(acc) + (size_t)8 * n * 8);
+    int *e = reinterpret_cast<int *>(maxbits + 1);
+    if (gF && nnz > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>((nnz + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_absmax, dim3(grid), dim3(256), 0, st, gF, nnz, maxbits);
+    }
+    hipLaunchKernelGGL(k_fx_exp, dim3(1), dim3(1), 0, st, maxbits, n, e);
+    return check_hip(hipGetLastError(), "opacity scale launch");
+}
+
+static const int *fx_exp_ptr(const BvhDev &bv, const void *acc) {
+    return reinterpret_cast<const int *>(static_cast<const char *>(acc) + (size_t)8 * bv.n * 8 + 4);
+}
+
 gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min,
-                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float *wbuf,
-                                double *gacc, int pass, const uint32_t *rcnt, int rcap, int *err, hipStream_t st) {
+                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float2 *wbuf,
+                                void *acc, int pass, const uint32_t *rcnt, int rcap, int *err, hipStream_t st) {
     const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
     const size_t smem = (size_t)max_row * 8 + ff_stack_bytes(threads);
     static bool attr_set = false;
@@ -949,13 +1056,14 @@ gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_
         attr_set = true;
     }
     hipLaunchKernelGGL(k_opacity_bwd, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, seed, t_eps, t_min, bv.n,
-                       row_ptr, col, gF, max_row, wbuf, gacc, pass, rcnt, rcap, err);
+                       row_ptr, col, gF, max_row, wbuf, fx_exp_ptr(bv, acc),
+                       static_cast<unsigned long long *>(acc), pass, rcnt, rcap, err);
     return check_hip(hipGetLastError(), "opacity backward launch");
 }
 
 gsrad_status launch_opacity_rec(const BvhDev &bv, int R, const uint2 *recs, const uint32_t *rcnt, int rcap,
                                 const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row,
-                                double *gacc, hipStream_t st) {
+                                void *acc, hipStream_t st) {
     const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
     int log2h = 4;
     while ((1 << log2h) < 2 * max_row) ++log2h;
@@ -971,14 +1079,15 @@ gsrad_status launch_opacity_rec(const BvhDev &bv, int R, const uint2 *recs, cons
         return GSRAD_EINVAL;
     }
     hipLaunchKernelGGL(k_opacity_rec, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, recs, rcnt, rcap, bv.n,
-                       row_ptr, col, gF, log2h, gacc);
+                       row_ptr, col, gF, log2h, fx_exp_ptr(bv, acc), static_cast<unsigned long long *>(acc));
     return check_hip(hipGetLastError(), "opacity records launch");
 }
 
-gsrad_status launch_opacity_finish(const BvhDev &bv, const double *gacc, const float *grad_rho, const float *albedo,
+gsrad_status launch_opacity_finish(const BvhDev &bv, const void *acc, const float *grad_rho, const float *albedo,
                                    float *grad_o, float *grad_a, hipStream_t st) {
-    hipLaunchKernelGGL(k_opacity_finish, dim3((unsigned)((bv.n + 255) / 256)), dim3(256), 0, st, bv, gacc, grad_rho,
-                       albedo, grad_o, grad_a);
+    hipLaunchKernelGGL(k_opacity_finish, dim3((unsigned)((bv.n + 255) / 256)), dim3(256), 0, st, bv,
+                       static_cast<const unsigned long long *>(acc), fx_exp_ptr(bv, acc), grad_rho, albedo, grad_o,
+                       grad_a);
     return check_hip(hipGetLastError(), "opacity finish launch");
 }
 

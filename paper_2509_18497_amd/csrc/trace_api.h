@@ -29,13 +29,17 @@ gsrad_status launch_ell_to_csr(const int32_t *ell_col, const float *ell_val, int
                                int64_t n, int32_t *col, float *val, hipStream_t st);
 gsrad_status launch_direct(const BvhDev &bv, const float *albedo, const float *lpos, const float *lI, int Lt, int K,
                            float *E, int *err, hipStream_t st);
+// Opacity backward accumulators: 8 per-XCD copies of n int64 fixed-point
+// sums, then the max |dL/dF| bits and the scale exponent (zero them first).
+size_t opacity_acc_bytes(int64_t n);
+gsrad_status launch_opacity_scale(const float *gF, int64_t nnz, int64_t n, void *acc, hipStream_t st);
 gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min,
-                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float *wbuf,
-                                double *gacc, int pass, const uint32_t *rcnt, int rcap, int *err, hipStream_t st);
+                                const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row, float2 *wbuf,
+                                void *acc, int pass, const uint32_t *rcnt, int rcap, int *err, hipStream_t st);
 gsrad_status launch_opacity_rec(const BvhDev &bv, int R, const uint2 *recs, const uint32_t *rcnt, int rcap,
                                 const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row,
-                                double *gacc, hipStream_t st);
-gsrad_status launch_opacity_finish(const BvhDev &bv, const double *gacc, const float *grad_rho, const float *albedo,
+                                void *acc, hipStream_t st);
+gsrad_status launch_opacity_finish(const BvhDev &bv, const void *acc, const float *grad_rho, const float *albedo,
                                    float *grad_o, float *grad_a, hipStream_t st);
 gsrad_status launch_ray_hits(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, const int64_t *recv,
                              int64_t n_recv, int max_hits, float *dirs, int32_t *cnt, int32_t *hj, float *ht,

@@ -91,6 +91,37 @@ def test_full_size_direct_light_rows(g, orc, bowl):
     assert np.all(E[:, :, 1:, :] == 0)
 
 
+def test_full_size_opacity_gradient_on_sampled_rows(g, orc, bowl):
+    """dL/dopacity through the compositing (decay term of Eq. dl-dgeo-0) in
+    the benchmark's launch, with dL/dF non-zero on 64 sampled receiver rows
+    only: every sender that those receivers' rays composite gets a
+    contribution, and the oracle's brute-force compositing backward over the
+    same 64 receivers gives the exact gradient of every surfel."""
+    sc, bvh, ff = bowl
+    rp, col, _ = (x.cpu().numpy() for x in ff.csr())
+    nnz = rp[-1]
+    recv = np.sort(np.random.default_rng(19).choice(N, size=64, replace=False)).astype(np.int64)
+    rng = np.random.default_rng(20)
+    gF = np.zeros(nnz, np.float32)
+    gp = [0]
+    gc, gv = [], []
+    for i in recv:
+        v = rng.standard_normal(rp[i + 1] - rp[i]).astype(np.float32)
+        gF[rp[i]:rp[i + 1]] = v
+        gc.append(col[rp[i]:rp[i + 1]])
+        gv.append(v.astype(np.float64))
+        gp.append(gp[-1] + v.shape[0])
+    go = g.opacity_backward(bvh, ff, dev(gF), None, None)[0].cpu().numpy()
+    te = orc.default_t_eps(sc.surfels)
+    goo, _ = orc.opacity_backward(sc.surfels, sc.albedo, sc.R, sc.seed, te, sc.t_min,
+                                  (np.asarray(gp, np.int64), np.concatenate(gc), np.concatenate(gv)),
+                                  receivers=recv)
+    assert np.count_nonzero(goo) > 1000
+    assert rel_err(go, goo) < TOL
+    go2 = g.opacity_backward(bvh, ff, dev(gF), None, None)[0].cpu().numpy()
+    assert np.array_equal(go, go2)
+
+
 def test_full_size_transport_on_two_coefficients(g, orc):
     K, Lt, nb, topk = 16, 1, 8, 512
     slots = [0, 15]

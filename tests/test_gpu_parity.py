@@ -304,7 +304,7 @@ def test_opacity_backward_matches_oracle(g, orc, name, kw, R, topk):
     Wo.sort_indices()
     goo, gao = orc.opacity_backward(sc.surfels, sc.albedo, R, sc.seed, te, 1e-4,
                                     (Wo.indptr, Wo.indices, Wo.data), grad_rho=grho)
-    assert rel_err(go.cpu().numpy(), goo) < 5 * TOL
+    assert rel_err(go.cpu().numpy(), goo) < TOL
     assert rel_err(ga.cpu().numpy(), gao) < TOL
 
 
@@ -334,7 +334,94 @@ def test_autograd_function_chain(g, orc):
     assert rel_err(B.detach().cpu().numpy(), Bo) < TOL
     assert rel_err(E.grad.cpu().numpy(), gEo) < TOL
     assert rel_err(alb.grad.cpu().numpy(), gao) < TOL
-    assert rel_err(op.grad.cpu().numpy(), goo) < 5 * TOL
+    assert rel_err(op.grad.cpu().numpy(), goo) < TOL
+
+
+def test_opacity_backward_is_bit_identical_between_runs(g):
+    """The per-sender sums are 64-bit fixed point (integer adds commute), so
+    the gradient does not depend on the order of the atomics."""
+    sc = _scene("fruit_bowl", n=3000)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    for records in (True, False):
+        ff = g.form_factors(bvh, 32, sc.seed, t_min=1e-4, records=records)
+        nnz = ff.info()[1]
+        gF = dev(np.random.default_rng(4).standard_normal(nnz).astype(np.float32))
+        runs = [g.opacity_backward(bvh, ff, gF, None, None)[0] for _ in range(3)]
+        assert torch.isfinite(runs[0]).all()
+        assert runs[0].abs().max() > 0
+        for r in runs[1:]:
+            assert torch.equal(r, runs[0])
+
+
+def test_opacity_backward_scale_follows_the_gradient_size(g, orc):
+    """The fixed-point scale is derived from max |dL/dF|: a dL/dF scaled by
+    2^-60 or 2^40 gives the gradient scaled exactly the same way."""
+    sc = _scene("fruit_bowl", n=2000)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    ff = g.form_factors(bvh, 16, sc.seed, t_min=1e-4)
+    nnz = ff.info()[1]
+    gF = np.random.default_rng(5).standard_normal(nnz).astype(np.float32)
+    base = g.opacity_backward(bvh, ff, dev(gF), None, None)[0].cpu().numpy()
+    for e in (-60, 40):
+        s = np.float32(2.0 ** e)
+        go = g.opacity_backward(bvh, ff, dev(gF * s), None, None)[0].cpu().numpy()
+        assert rel_err(go / s, base) < 1e-6
+    zero = g.opacity_backward(bvh, ff, dev(np.zeros(nnz, np.float32)), None, None)[0]
+    assert not zero.any()
+    bad = gF.copy()
+    bad[7] = np.inf
+    assert torch.isnan(g.opacity_backward(bvh, ff, dev(bad), None, None)[0]).all()
+
+
+# ---------------------------------------------------------------------------
+# handle state after failures and rebuilds
+# ---------------------------------------------------------------------------
+def test_failed_refill_leaves_the_handle_unusable(g):
+    """A reused F handle whose ray cast fails (more than 8192 distinct
+    senders in one row) refuses later use with ESTATE instead of exposing
+    half-written buffers; a successful cast makes it usable again."""
+    ok_sc = _scene("fruit_bowl", n=1500)
+    ok_bvh = g.build_bvh(dev_surfels(ok_sc.surfels))
+    ff = g.form_factors(ok_bvh, 16, ok_sc.seed)
+    rho = dev(np.full((ok_sc.n, 3), 0.5, np.float32))
+    E = dev(scenes.seeded_array((ok_sc.n, 1, 1, 3), seed=2))
+    g.transport_solve(ff, rho, E, 2)
+    # 20k nearly transparent surfels in a cube, no compositing cut: each
+    # receiver's 1024 rays composite ~250 surfels each, and central
+    # receivers see over 8192 distinct front-facing senders
+    sur = scenes.random_frame_surfels(20000, seed=9, extent=1.0, scale=(0.05, 0.06), opacity=(0.04, 0.05))
+    bvh = g.build_bvh(dev_surfels(sur))
+    with pytest.raises(g.GsradError) as ei:
+        g.form_factors(bvh, 1024, 3, t_min=0.0, records=False, ff=ff)
+    assert ei.value.status == g.gsrad.EOVERFLOW
+    with pytest.raises(g.GsradError) as ei:
+        g.transport_solve(ff, rho, E, 2)
+    assert ei.value.status == g.gsrad.ESTATE
+    with pytest.raises(g.GsradError) as ei:
+        g.opacity_backward(ok_bvh, ff, dev(np.zeros(4, np.float32)), None, None)
+    assert ei.value.status == g.gsrad.ESTATE
+    g.form_factors(ok_bvh, 16, ok_sc.seed, ff=ff)
+    B = g.transport_solve(ff, rho, E, 2)[0]
+    assert torch.isfinite(B).all()
+
+
+def test_opacity_backward_refuses_an_f_from_before_a_rebuild(g):
+    """Rebuilding a BVH handle in place (same size, new opacity) makes the F
+    cast from it before the rebuild unusable for the opacity backward."""
+    sc = _scene("fruit_bowl", n=1500)
+    d = dev_surfels(sc.surfels)
+    bvh = g.build_bvh(d)
+    ff = g.form_factors(bvh, 16, sc.seed)
+    gF = dev(np.ones(ff.info()[1], np.float32))
+    g.opacity_backward(bvh, ff, gF, None, None)
+    d["opacity"] = d["opacity"] * 0.5
+    g.build_bvh(d, bvh=bvh)
+    with pytest.raises(g.GsradError) as ei:
+        g.opacity_backward(bvh, ff, gF, None, None)
+    assert ei.value.status == g.gsrad.EINVAL
+    ff = g.form_factors(bvh, 16, sc.seed, ff=ff)
+    go = g.opacity_backward(bvh, ff, dev(np.ones(ff.info()[1], np.float32)), None, None)[0]
+    assert torch.isfinite(go).all()
 
 
 # ---------------------------------------------------------------------------
@@ -375,7 +462,7 @@ def test_layer_stack_forward_and_opacity_backward(g, orc, records):
     W = sp.csr_matrix((gF.astype(np.float64), Fg.indices, Fg.indptr), shape=Fg.shape).multiply(Fo != 0).tocsr()
     W.sort_indices()
     goo, _ = orc.opacity_backward(sur, alb, R, seed, te, 1e-4, (W.indptr, W.indices, W.data), grad_rho=grho)
-    assert rel_err(go.cpu().numpy(), goo) < 5 * TOL
+    assert rel_err(go.cpu().numpy(), goo) < TOL
 
 
 # ---------------------------------------------------------------------------
