@@ -22,7 +22,10 @@
  *   the number of non-zeros and the overflow flags back to the host).
  * - Errors: every call returns GSRAD_OK (0) or a negative code; the message
  *   of the last error of the calling thread is gsrad_last_error().  No
- *   exception crosses the ABI and handles stay valid after an error.
+ *   exception crosses the ABI.  A failed call leaves the handles it only
+ *   reads as they were; a handle that a failed call was rebuilding or
+ *   refilling in place is left unusable, and every later use of it returns
+ *   GSRAD_ESTATE until a call rebuilds or refills it successfully.
  * - Layouts: E, B and their gradients are [N][Lt][K][3] (surfel, light,
  *   spherical-harmonic coefficient in the order Y00, Y1-1, Y10, Y11, ...,
  *   RGB), i.e. N rows of C = Lt*K*3 columns; colour = column % 3.  rho and
