@@ -228,6 +228,22 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
                                    gsrad_tape **tape, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP32
+ * bounces of gsrad_transport_solve without a tape, B_out = B^(n_bounces),
+ * bit-identical to it.  The two ping-pong iterates live in a fixed 64 MiB
+ * device array of the library, one per GPU, held until the process ends, so
+ * the call allocates nothing: it needs 2 * n * n_lights * K * 3 * 4 <= 2^26
+ * bytes when n_bounces >= 2 and returns GSRAD_EINVAL for larger operators.
+ * The array belongs to the device current on the calling thread (which must
+ * be the device of stream and of every buffer).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialised by the caller.  FP32 only.
+ */
+gsrad_status gsrad_transport_solve_noalloc(const gsrad_ff *ff, const float *rho, const float *E, int32_t n_lights,
+                                           int32_t K, int32_t n_bounces, float *B_out, void *stream);
+
+/*
  * Exact adjoint of gsrad_transport_solve for dL/dB^(n) = grad_B (Eq.
  * final_dL_dE in division-free form, truncated like the forward):
  *   lambda^(n) = grad_B,  lambda^(k) = F^T (rho * lambda^(k+1))

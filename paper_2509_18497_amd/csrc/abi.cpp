@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -899,6 +900,82 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
         tp->has_G = false;
         tp->ff = ff;
         *tape = tp;
+    }
+    return GSRAD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free bounce iterations: the ping-pong iterates live in a
+// fixed device array of this translation unit (one per GPU, held until the
+// process ends).  Its device address is looked up once per device; host
+// code only ever passes that address, never the array's name.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchMaxDevices] = {};
+
+gsrad_status scratch_of_current_device(void **out) {
+    int dev = -1;
+    GS_TRY(check_hip(hipGetDevice(&dev), "scratch: current device"));
+    if (dev < 0 || dev >= kScratchMaxDevices) {
+        set_error("scratch: device %d out of range", dev);
+        return GSRAD_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        GS_TRY(check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch: symbol address"));
+        if (!p) {
+            set_error("scratch: null symbol address on device %d", dev);
+            return GSRAD_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GSRAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsrad_status gsrad_transport_solve_noalloc(const gsrad_ff *ff, const float *rho, const float *E, int32_t n_lights,
+                                           int32_t K, int32_t n_bounces, float *B_out, void *stream) {
+    if (!ff || !rho || !E || !B_out) return einval("gsrad_transport_solve_noalloc: null argument");
+    GS_TRY(usable(ff, "gsrad_transport_solve_noalloc"));
+    if (n_lights < 1) return einval("gsrad_transport_solve_noalloc: n_lights must be >= 1");
+    if (!valid_K(K)) return einval("gsrad_transport_solve_noalloc: K must be 1, 4, 9 or 16");
+    if (n_bounces < 0 || n_bounces > 4096)
+        return einval("gsrad_transport_solve_noalloc: n_bounces must be in [0, 4096]");
+    hipStream_t st = S(stream);
+    const int C = n_lights * K * 3;
+    const int64_t n = ff->n;
+    const size_t row_bytes = (size_t)n * C * sizeof(float);
+    if (n_bounces == 0)
+        return check_hip(hipMemcpyAsync(B_out, E, row_bytes, hipMemcpyDeviceToDevice, st), "noalloc solve copy");
+    float *slots = nullptr;
+    if (n_bounces > 1) {
+        if (2 * row_bytes > kScratchBytes) {
+            set_error("gsrad_transport_solve_noalloc: two iterates of %lld x %d values need %zu bytes, more than the "
+                      "%zu-byte scratch array", (long long)n, C, 2 * row_bytes, kScratchBytes);
+            return GSRAD_EINVAL;
+        }
+        void *p = nullptr;
+        GS_TRY(scratch_of_current_device(&p));
+        slots = static_cast<float *>(p);
+    }
+    const Csr F = ff->csr();
+    const float *src = E;
+    for (int k = 0; k < n_bounces; ++k) {
+        float *dst = k == n_bounces - 1 ? B_out : slots + (size_t)(k & 1) * n * C;
+        GS_TRY(launch_bounce(F, C, src, E, rho, dst, st));
+        src = dst;
     }
     return GSRAD_OK;
 }

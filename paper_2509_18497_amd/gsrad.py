@@ -25,6 +25,7 @@ SOA = ("px", "py", "pz", "tux", "tuy", "tuz", "tvx", "tvy", "tvz", "nx", "ny", "
 EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_info", "gsrad_bvh_height",
            "gsrad_effective_area", "gsrad_reflectance", "gsrad_form_factors", "gsrad_ff_info", "gsrad_ff_view",
            "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
+           "gsrad_transport_solve_noalloc",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
@@ -83,6 +84,7 @@ def lib():
             "gsrad_tape_grad_F_dense": ([vp, vp, vp], i32),
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
+            "gsrad_transport_solve_noalloc": ([vp, vp, vp, i32, i32, i32, vp, vp], i32),
             "gsrad_transport_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_opacity_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_ray_hits": ([vp, ctypes.POINTER(_FFParams), vp, i64, i32, vp, vp, vp, vp, vp, vp, vp], i32),
@@ -345,6 +347,20 @@ def transport_solve(ff: FF, rho: torch.Tensor, E: torch.Tensor, n_bounces: int, 
                                        _ptr(B, name="B"), ctypes.byref(tp.h) if tp is not None else None,
                                        _stream(stream)), "gsrad_transport_solve")
     return B, tp
+
+
+def transport_solve_noalloc(ff: FF, rho: torch.Tensor, E: torch.Tensor, n_bounces: int, out: torch.Tensor,
+                            stream=None) -> torch.Tensor:
+    """The FP32 bounces of transport_solve (no tape) through the entry point
+    that allocates nothing: its two ping-pong iterates live in the library's
+    fixed per-GPU scratch array (at most 64 MiB, i.e. n * C <= 2^23 values);
+    the caller provides B in out."""
+    if E.dim() != 4 or E.shape[3] != 3:
+        raise ValueError("E must be [n, Lt, K, 3]")
+    Lt, K = int(E.shape[1]), int(E.shape[2])
+    _check(lib().gsrad_transport_solve_noalloc(ff.h, _ptr(rho, name="rho"), _ptr(E, name="E"), Lt, K, int(n_bounces),
+                                               _ptr(out, name="out"), _stream(stream)), "gsrad_transport_solve_noalloc")
+    return out
 
 
 def transport_backward(ff: FF, tape: Tape, rho: torch.Tensor, grad_B: torch.Tensor, want_grad_F: bool = True,
