@@ -276,7 +276,8 @@ gsrad_status gsrad_tape_grad_F_dense(const gsrad_tape *tape, float *grad_F_out, 
 
 /*
  * Batches of scenes of uneven size (many scenes, each lit by its own set of
- * point lights, propagated together; Sec. 6 renders many images from one
+ * point lights, propagated together; the batch-size paragraph of the
+ * ablation study in Sec. 9 propagates once and renders many images from one
  * propagation).  gsrad_batch_create joins the scenes' transport operators
  * (each from gsrad_form_factors or gsrad_ff_from_csr, n_s rows) into one
  * block-diagonal F with global indices: scene s owns rows
@@ -363,9 +364,10 @@ gsrad_status gsrad_check(const gsrad_ff *ff, const float *rho, const float *E, c
                          int32_t K, double *out_host, void *stream);
 
 /*
- * Reciprocity of the estimated operator (Sec. 5.3: A_i F_ij = A_j F_ji
- * holds for the exact form factors, with A the App. E effective areas of
- * gsrad_effective_area).  FP64 over the stored entries, the mirror entry
+ * Reciprocity of the estimated operator: A_i F_ij = A_j F_ji holds for
+ * exact form factors (the reciprocity of classical radiosity, which the
+ * paper does not state; an invariant of the estimator), with A the App. E
+ * effective areas of gsrad_effective_area.  FP64 over the stored entries, the mirror entry
  * F_ji found in row j (0 when it is not stored, e.g. cut by top-k):
  *   out_host[0] = sum |A_i F_ij - A_j F_ji| / sum A_i F_ij
  *   out_host[1] = max |A_i F_ij - A_j F_ji| / max(A_i F_ij, A_j F_ji)

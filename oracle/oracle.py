@@ -269,8 +269,9 @@ def _rho_cols(rho_arr, C):
 
 
 def reciprocity(F, area):
-    """Reciprocity of an operator against the areas (Sec. 5.3: A_i F_ij =
-    A_j F_ji for exact form factors), over the stored entries of F, the
+    """Reciprocity of an operator against the areas (A_i F_ij = A_j F_ji
+    for exact form factors: classical radiosity reciprocity, not stated in
+    the paper; an invariant of the estimator), over the stored entries of F, the
     mirror entry taken as 0 where F_ji is not stored:
     (sum |A_i F_ij - A_j F_ji| / sum A_i F_ij,
      max |A_i F_ij - A_j F_ji| / max(A_i F_ij, A_j F_ji))."""
