@@ -318,6 +318,75 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *batch, const float *rho
 void gsrad_batch_destroy(gsrad_batch *batch);
 
 /*
+ * Directional transfer with the diffuse + Phong BRDF (Eq. final-radiosity
+ * with f_i(w) = f^c_i x Ybar(w), Sec. 3.2; Eq. brdf, Sec. 5.1; App. A).
+ * Coefficient vectors of surfel i (E_i, B_i, f^c_i, the rows of R) are taken
+ * in its tangent frame (t_u, t_v, n) as (x, y, z): there App. A's
+ * c_lm = (-1)^m c_l0 is the Phong lobe about the mirror direction.  Per
+ * stored entry (i, j) of F the directional factors use the unit direction
+ * d_ij from p_i to p_j (the BRDF and radiance factors taken as constant over
+ * the pair, as Sec. 8 does); F_ij carries the decay:
+ *   (T X)_i[l][a][c] = sum_j F_ij Y_a(d_ij in i's frame) sum_b Y_b(-d_ij in j's frame) X_j[l][b][c]
+ *   B^(0) = E,  B^(k+1) = E + R (.) (T B^(k))
+ * with R_i[a][c] = pi o_i f^c_i[a][c] (receiver opacity absorbed into the
+ * BRDF; pi from the cosine-weighted hemisphere estimator of F).  For
+ * k = 1 (Lambertian) and DC-only radiance this is exactly
+ * gsrad_transport_solve.  Real SH in the order Y00, Y1-1, Y10, Y11, ...
+ *
+ * gsrad_brdf_reflectance: R [n][K][3] from the BRDF parameters per surfel:
+ *   blend k [n] (diffuse weight), diffuse albedo a^d [n][3], specular
+ *   albedo a^s [n][3], shininess s [n] (>= 0):
+ *   f^c_00 = 4 k a^d + (1 - k) a^s,
+ *   f^c_lm = (-1)^m (1 - k) g_l(s) a^s, g_1 = (s+1)/(s+2), g_2 = s/(s+3),
+ *   g_3 = (s+1)(s-1)/((s+2)(s+4)).
+ * gsrad_brdf_backward: the gradients of sum(grad_R * R) with respect to the
+ *   opacity (0 where the clamp is active), k, a^d, a^s and s (each output
+ *   may be NULL; written, not accumulated).
+ */
+gsrad_status gsrad_brdf_reflectance(const gsrad_bvh *bvh, const float *k, const float *albedo_d,
+                                    const float *albedo_s, const float *shininess, int32_t K, float *R_out,
+                                    void *stream);
+gsrad_status gsrad_brdf_backward(const gsrad_bvh *bvh, const float *k, const float *albedo_d, const float *albedo_s,
+                                 const float *shininess, int32_t K, const float *grad_R, float *grad_opacity,
+                                 float *grad_k, float *grad_albedo_d, float *grad_albedo_s, float *grad_shininess,
+                                 void *stream);
+
+/*
+ * Direct light with the BRDF (Eq. forward rendering equation, direct
+ * illumination): E_i,l = (R_i / pi) (.) Y(w_il in i's frame)
+ * I_l max(0, n_i . w_il) / r_il^2 T_il, w_il the unit direction to light l,
+ * T_il the shadow transmittance as in gsrad_direct_light.  R [n][K][3],
+ * E_out [n][n_lights][K][3].
+ */
+gsrad_status gsrad_direct_light_sh(const gsrad_bvh *bvh, const float *R, int32_t K, const float *light_pos,
+                                   const float *light_I, int32_t n_lights, float *E_out, void *stream);
+
+/*
+ * Bounces of the directional transfer above on F (any gsrad_ff of n rows:
+ * ray-cast or imported) with the geometry of bvh (same n surfels).  R
+ * [n][K][3], E and B_out [n][n_lights][K][3].  The tape keeps B^(k) and
+ * T B^(k) for gsrad_transport_backward_sh.  Deterministic.
+ */
+gsrad_status gsrad_transport_solve_sh(const gsrad_ff *ff, const gsrad_bvh *bvh, const float *R, const float *E,
+                                      int32_t n_lights, int32_t K, int32_t n_bounces, float *B_out,
+                                      gsrad_tape **tape, void *stream);
+
+/*
+ * Exact adjoint of gsrad_transport_solve_sh for dL/dB^(n) = grad_B (Eq.
+ * final_dL_dE in division-free form; the backward runs the same transfer
+ * on F^T with the pair directions reversed, App. C):
+ *   lambda^(n) = grad_B,  lambda^(k) = T^T (R (.) lambda^(k+1)),  grad_E = sum_k lambda^(k)
+ *   grad_R[i][a][c] = sum_{k<n} sum_l lambda^(k+1)_i[l][a][c] (T B^(k))_i[l][a][c]
+ *   grad_F[e = (i, j)] = sum_{k<n} sum_{l, c} (Y(d_ij)^T (R (.) lambda^(k+1))_i[l][:, c])
+ *                                             (Y(-d_ij)^T B^(k)_j[l][:, c])
+ * (Eq. final-dl-dbrdf and the decay term of Eq. dl-dgeo-0 before their
+ * fixed-point limits).  grad_R [n][K][3] and grad_F [nnz] may be NULL.
+ */
+gsrad_status gsrad_transport_backward_sh(const gsrad_ff *ff, const gsrad_bvh *bvh, const gsrad_tape *tape,
+                                         const float *R, const float *grad_B, float *grad_E, float *grad_R,
+                                         float *grad_F, void *stream);
+
+/*
  * Opacity and albedo gradients (Eq. dl-dgeo-0, decay term, restricted to
  * opacity; and rho = o a).  For every ray of every receiver i the hits of
  * the forward pass are recomputed and, with G_q = grad_F[i, j_q] / R on

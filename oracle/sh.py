@@ -31,6 +31,7 @@ Readings (where the paper leaves a choice):
   pair.  The decay of the pair is the ray-cast form factor F_ij (or any
   other operator F given).  With w_I = -d_ij (the direction light travels),
   Ybar(w_I) = Y(d_ij) in i's frame and Y(w_I) = Y(-d_ij) in j's frame.
+  Coincident centres (no direction) take the receiver's normal as d_ij.
 * Normalisation.  With cosine-weighted rays the hemisphere integral of
   g(w)|n.w| is pi times the mean over rays, so the transfer is
   (T X)_i = sum_j F_ij Y(d_ij^(i)) (Y(-d_ij^(j))^T X_j) and the receiver
@@ -219,7 +220,8 @@ def pair_bases(F, surfels, K: int):
     rows = np.repeat(np.arange(F.shape[0]), np.diff(F.indptr))
     cols = F.indices
     d = P[cols] - P[rows]
-    d = d / np.linalg.norm(d, axis=1, keepdims=True)
+    ln = np.linalg.norm(d, axis=1)
+    d = np.where(ln[:, None] > 0, d / np.where(ln > 0, ln, 1.0)[:, None], Fr[rows, 2])   # coincident: normal of i
     di = np.einsum("eab,eb->ea", Fr[rows], d)
     ej = np.einsum("eab,eb->ea", Fr[cols], -d)
     return rows, cols, sh_basis(di, K), sh_basis(ej, K)
@@ -230,6 +232,13 @@ def _as_rows(X, K):
     return X.reshape(X.shape[0], -1, K, 3)
 
 
+def _sum_by(index, n, contrib):
+    """out[r] = sum of contrib[e] over the entries e with index[e] = r."""
+    S = sp.csr_matrix((np.ones(index.size), (index, np.arange(index.size))), shape=(n, index.size))
+    width = int(np.prod(contrib.shape[1:]))
+    return (S @ contrib.reshape(index.size, width)).reshape((n,) + contrib.shape[1:])
+
+
 def transfer(F, bases, X, K: int) -> np.ndarray:
     """(T X)_i[l, a, c] = sum_j F_ij Yd_ij[a] sum_b Ye_ij[b] X_j[l, b, c]."""
     F = sp.csr_matrix(F)
@@ -237,9 +246,7 @@ def transfer(F, bases, X, K: int) -> np.ndarray:
     X4 = _as_rows(X, K)
     s = np.einsum("eb,elbc->elc", Ye, X4[cols])                  # radiance of j towards i
     contrib = F.data[:, None, None, None] * Yd[:, None, :, None] * s[:, :, None, :]
-    out = np.zeros_like(X4)
-    np.add.at(out, rows, contrib)
-    return out.reshape(np.shape(X))
+    return _sum_by(rows, F.shape[0], contrib).reshape(np.shape(X))
 
 
 def transfer_T(F, bases, U, K: int) -> np.ndarray:
@@ -250,9 +257,7 @@ def transfer_T(F, bases, U, K: int) -> np.ndarray:
     U4 = _as_rows(U, K)
     s = np.einsum("ea,elac->elc", Yd, U4[rows])
     contrib = F.data[:, None, None, None] * Ye[:, None, :, None] * s[:, :, None, :]
-    out = np.zeros_like(U4)
-    np.add.at(out, cols, contrib)
-    return out.reshape(np.shape(U))
+    return _sum_by(cols, F.shape[1], contrib).reshape(np.shape(U))
 
 
 def _times_R(R, X, K):

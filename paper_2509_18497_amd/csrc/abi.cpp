@@ -18,6 +18,7 @@
 #include "trace_api.h"
 #include "dense_api.h"
 #include "batch_api.h"
+#include "sh_api.h"
 
 namespace gsrad {
 
@@ -69,6 +70,7 @@ struct DevBuf {
     }
 };
 
+constexpr int kTapeSH = 2;          // tape precision tag of gsrad_transport_solve_sh
 constexpr int kLog2Table = 12;      // 4096-entry aggregation table per receiver
 constexpr int kLog2TableMax = 13;   // 8192 entries: rows with more distinct senders
 constexpr int kRecCap = 256;        // recorded hits per ray to start with (composited: ~27 mean here)
@@ -986,6 +988,8 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
     if (!ff || !tape || !rho || !grad_B || !grad_E) return einval("gsrad_transport_backward: null argument");
     GS_TRY(usable(ff, "gsrad_transport_backward"));
     if (tape->ff != ff || tape->n != ff->n) return einval("gsrad_transport_backward: tape does not belong to this F");
+    if (tape->precision == kTapeSH)
+        return einval("gsrad_transport_backward: the tape is from gsrad_transport_solve_sh (use gsrad_transport_backward_sh)");
     hipStream_t st = S(stream);
     gsrad_ff *f = const_cast<gsrad_ff *>(ff);
     gsrad_tape *tp = const_cast<gsrad_tape *>(tape);
@@ -1021,6 +1025,163 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
     }
     ProfScope ps("sddmm", st);
     if (grad_F || grad_rho) GS_TRY(launch_sddmm(ff->csr(), C, nb, tp->B.as<float>(), L, rho, grad_F, grad_rho, st));
+    return GSRAD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// directional (spherical-harmonic) transfer with the diffuse + Phong BRDF
+// ---------------------------------------------------------------------------
+gsrad_status gsrad_brdf_reflectance(const gsrad_bvh *bvh, const float *k, const float *albedo_d,
+                                    const float *albedo_s, const float *shininess, int32_t K, float *R_out,
+                                    void *stream) {
+    if (!bvh || !k || !albedo_d || !albedo_s || !shininess || !R_out)
+        return einval("gsrad_brdf_reflectance: null argument");
+    GS_TRY(usable(bvh, "gsrad_brdf_reflectance"));
+    if (!valid_K(K)) return einval("gsrad_brdf_reflectance: K must be 1, 4, 9 or 16");
+    return launch_brdf_reflectance(bvh->dev(), k, albedo_d, albedo_s, shininess, K, R_out, S(stream));
+}
+
+gsrad_status gsrad_brdf_backward(const gsrad_bvh *bvh, const float *k, const float *albedo_d, const float *albedo_s,
+                                 const float *shininess, int32_t K, const float *grad_R, float *grad_opacity,
+                                 float *grad_k, float *grad_albedo_d, float *grad_albedo_s, float *grad_shininess,
+                                 void *stream) {
+    if (!bvh || !k || !albedo_d || !albedo_s || !shininess || !grad_R)
+        return einval("gsrad_brdf_backward: null argument");
+    GS_TRY(usable(bvh, "gsrad_brdf_backward"));
+    if (!valid_K(K)) return einval("gsrad_brdf_backward: K must be 1, 4, 9 or 16");
+    return launch_brdf_backward(bvh->dev(), k, albedo_d, albedo_s, shininess, K, grad_R, grad_opacity, grad_k,
+                                grad_albedo_d, grad_albedo_s, grad_shininess, S(stream));
+}
+
+gsrad_status gsrad_direct_light_sh(const gsrad_bvh *bvh, const float *R, int32_t K, const float *light_pos,
+                                   const float *light_I, int32_t n_lights, float *E_out, void *stream) {
+    if (!bvh || !R || !light_pos || !light_I || !E_out) return einval("gsrad_direct_light_sh: null argument");
+    GS_TRY(usable(bvh, "gsrad_direct_light_sh"));
+    if (n_lights < 1) return einval("gsrad_direct_light_sh: n_lights must be >= 1");
+    if (!valid_K(K)) return einval("gsrad_direct_light_sh: K must be 1, 4, 9 or 16");
+    gsrad_bvh *h = const_cast<gsrad_bvh *>(bvh);
+    GS_TRY(h->height.ensure(64, "flags"));
+    ProfScope ps("direct_light_sh", S(stream));
+    return launch_direct_sh(bvh->dev(), R, light_pos, light_I, n_lights, K, E_out, h->height.as<int>() + 4, S(stream));
+}
+
+gsrad_status gsrad_transport_solve_sh(const gsrad_ff *ff, const gsrad_bvh *bvh, const float *R, const float *E,
+                                      int32_t n_lights, int32_t K, int32_t n_bounces, float *B_out,
+                                      gsrad_tape **tape, void *stream) {
+    if (!ff || !bvh || !R || !E || !B_out) return einval("gsrad_transport_solve_sh: null argument");
+    GS_TRY(usable(ff, "gsrad_transport_solve_sh"));
+    GS_TRY(usable(bvh, "gsrad_transport_solve_sh"));
+    if (bvh->n != ff->n) return einval("gsrad_transport_solve_sh: the BVH and F have different sizes");
+    if (n_lights < 1) return einval("gsrad_transport_solve_sh: n_lights must be >= 1");
+    if (!valid_K(K)) return einval("gsrad_transport_solve_sh: K must be 1, 4, 9 or 16");
+    if (n_bounces < 0 || n_bounces > 4096) return einval("gsrad_transport_solve_sh: n_bounces must be in [0, 4096]");
+    hipStream_t st = S(stream);
+    const int C = n_lights * K * 3;
+    const int64_t n = ff->n;
+    const size_t row_bytes = (size_t)n * C * sizeof(float);
+    gsrad_tape *tp = nullptr;
+    bool created = false;
+    if (tape) {
+        created = *tape == nullptr;
+        tp = created ? new gsrad_tape() : *tape;
+    }
+    auto fail = [&](gsrad_status e) {
+        if (created) delete tp;
+        return e;
+    };
+    gsrad_status e;
+    const BvhDev bv = bvh->dev();
+    const Csr F = ff->csr();
+    if (n_bounces == 0) {
+        if ((e = check_hip(hipMemcpyAsync(B_out, E, row_bytes, hipMemcpyDeviceToDevice, st), "solve copy")) != GSRAD_OK)
+            return fail(e);
+    } else {
+        float *slots = nullptr, *qs = nullptr;
+        if (tp) {
+            if ((e = tp->B.ensure(row_bytes * n_bounces, "forward tape")) != GSRAD_OK) return fail(e);
+            if ((e = tp->Q.ensure(row_bytes * n_bounces, "transfer tape")) != GSRAD_OK) return fail(e);
+            slots = tp->B.as<float>();
+            qs = tp->Q.as<float>();
+            if ((e = check_hip(hipMemcpyAsync(slots, E, row_bytes, hipMemcpyDeviceToDevice, st), "tape copy")) !=
+                GSRAD_OK)
+                return fail(e);
+        } else if (n_bounces > 1) {
+            gsrad_ff *m = const_cast<gsrad_ff *>(ff);
+            if ((e = m->slab.ensure(std::max(m->slab.bytes, row_bytes * 2), "ping-pong")) != GSRAD_OK) return fail(e);
+        }
+        const float *src = E;
+        for (int k = 0; k < n_bounces; ++k) {
+            float *dst;
+            if (k == n_bounces - 1) dst = B_out;
+            else if (tp) dst = slots + (size_t)(k + 1) * n * C;
+            else dst = const_cast<gsrad_ff *>(ff)->slab.as<float>() + (size_t)(k & 1) * n * C;
+            ProfScope ps("bounce_sh", st);
+            if ((e = launch_transfer_sh(bv, F, n_lights, K, src, E, R, qs ? qs + (size_t)k * n * C : nullptr, dst, 0,
+                                        st)) != GSRAD_OK)
+                return fail(e);
+            src = dst;
+        }
+    }
+    if (tp) {
+        tp->n = n;
+        tp->C = C;
+        tp->nb = n_bounces;
+        tp->Lt = n_lights;
+        tp->K = K;
+        tp->precision = kTapeSH;
+        tp->has_G = false;
+        tp->ff = ff;
+        *tape = tp;
+    }
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_transport_backward_sh(const gsrad_ff *ff, const gsrad_bvh *bvh, const gsrad_tape *tape,
+                                         const float *R, const float *grad_B, float *grad_E, float *grad_R,
+                                         float *grad_F, void *stream) {
+    if (!ff || !bvh || !tape || !R || !grad_B || !grad_E) return einval("gsrad_transport_backward_sh: null argument");
+    GS_TRY(usable(ff, "gsrad_transport_backward_sh"));
+    GS_TRY(usable(bvh, "gsrad_transport_backward_sh"));
+    if (tape->ff != ff || tape->n != ff->n || bvh->n != ff->n)
+        return einval("gsrad_transport_backward_sh: tape, F and BVH do not belong together");
+    if (tape->precision != kTapeSH)
+        return einval("gsrad_transport_backward_sh: the tape is not from gsrad_transport_solve_sh");
+    hipStream_t st = S(stream);
+    gsrad_ff *f = const_cast<gsrad_ff *>(ff);
+    gsrad_tape *tp = const_cast<gsrad_tape *>(tape);
+    const int64_t n = ff->n;
+    const int C = tape->C, nb = tape->nb, Lt = tape->Lt, K = tape->K;
+    const size_t row_bytes = (size_t)n * C * sizeof(float);
+    GS_TRY(check_hip(hipMemcpyAsync(grad_E, grad_B, row_bytes, hipMemcpyDeviceToDevice, st), "grad_E init"));
+    if (nb == 0) {
+        if (grad_R) GS_TRY(check_hip(hipMemsetAsync(grad_R, 0, (size_t)n * K * 12, st), "grad_R zero"));
+        if (grad_F && ff->nnz > 0)
+            GS_TRY(check_hip(hipMemsetAsync(grad_F, 0, (size_t)ff->nnz * 4, st), "grad_F zero"));
+        return GSRAD_OK;
+    }
+    {
+        ProfScope ps("transpose", st);
+        GS_TRY(ensure_transpose(f, st));
+    }
+    GS_TRY(tp->L.ensure(row_bytes * nb, "adjoint tape"));
+    GS_TRY(tp->lam0.ensure(row_bytes, "adjoint scratch"));
+    GS_TRY(tp->pp.ensure(row_bytes, "adjoint scaled rows"));
+    float *L = tp->L.as<float>();
+    float *u = tp->pp.as<float>();
+    GS_TRY(check_hip(hipMemcpyAsync(L + (size_t)(nb - 1) * n * C, grad_B, row_bytes, hipMemcpyDeviceToDevice, st),
+                     "adjoint seed"));
+    const BvhDev bv = bvh->dev();
+    const Csr FT = f->csr_t();
+    for (int k = nb - 1; k >= 0; --k) {
+        const float *lam_in = L + (size_t)k * n * C;   // lambda^(k+1)
+        float *lam_out = k >= 1 ? L + (size_t)(k - 1) * n * C : tp->lam0.as<float>();
+        ProfScope ps("adjoint_sh", st);
+        GS_TRY(launch_scale_rows(lam_in, R, n, Lt, K, u, st));
+        GS_TRY(launch_transfer_sh(bv, FT, Lt, K, u, nullptr, nullptr, lam_out, grad_E, 1, st));
+    }
+    ProfScope ps("sddmm_sh", st);
+    if (grad_R) GS_TRY(launch_grad_R(L, tp->Q.as<float>(), n, Lt, K, nb, grad_R, st));
+    if (grad_F) GS_TRY(launch_sddmm_sh(bv, ff->csr(), Lt, K, nb, tp->B.as<float>(), L, R, grad_F, st));
     return GSRAD_OK;
 }
 

@@ -1,0 +1,28 @@
+// Host launchers of the directional (spherical-harmonic) transfer kernels
+// (sh.hip) and of the direct light with the BRDF (trace.hip).
+#pragma once
+
+#include "gsrad_internal.h"
+#include "trace_api.h"
+
+namespace gsrad {
+
+// mode 0: out_a = T X (optional), out_b = E + R (.) (T X)
+// mode 1 (F = F^T): out_a = T^T X, out_b += out_a
+gsrad_status launch_transfer_sh(const BvhDev &bv, const Csr &F, int Lt, int K, const float *X, const float *E,
+                                const float *R, float *out_a, float *out_b, int mode, hipStream_t st);
+// u = R (.) lam (rows of Lt lights)
+gsrad_status launch_scale_rows(const float *lam, const float *R, int64_t n, int Lt, int K, float *u, hipStream_t st);
+gsrad_status launch_sddmm_sh(const BvhDev &bv, const Csr &F, int Lt, int K, int nb, const float *Btape,
+                             const float *Ltape, const float *R, float *grad_F, hipStream_t st);
+gsrad_status launch_grad_R(const float *Ltape, const float *Qtape, int64_t n, int Lt, int K, int nb, float *grad_R,
+                           hipStream_t st);
+gsrad_status launch_brdf_reflectance(const BvhDev &bv, const float *kd, const float *ad, const float *as,
+                                     const float *shin, int K, float *R, hipStream_t st);
+gsrad_status launch_brdf_backward(const BvhDev &bv, const float *kd, const float *ad, const float *as,
+                                  const float *shin, int K, const float *G, float *g_o, float *g_k, float *g_ad,
+                                  float *g_as, float *g_s, hipStream_t st);
+gsrad_status launch_direct_sh(const BvhDev &bv, const float *R, const float *lpos, const float *lI, int Lt, int K,
+                              float *E, int *err, hipStream_t st);
+
+}  // namespace gsrad

@@ -11,6 +11,8 @@
 // k_direct        one thread per (surfel, light): shadow-ray transmittance.
 // k_opacity_bwd   compositing backward, two recomputing passes.
 #include "gsrad_internal.h"
+#include "sh_api.h"
+#include "sh_basis.h"
 #include "trace_api.h"
 
 namespace gsrad {
@@ -166,7 +168,9 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
         float t, r2;
         bool front;
         if (!hit_test(r, ox, oy, oz, dx, dy, dz, t_lo, 1.0f, true, t, r2, front)) return;
-        T *= expf(-r.c.w * expf(-kKernelExp * r2));
+        // kernel value from the exact intersection (the FP32 hit point loses
+        // the offset from the centre when the centre is many radii away)
+        T = __fmul_rn(T, transmit(r.c.w, kernel_gamma(hit_r2_exact(r, ox, oy, oz, dx, dy, dz))));
     };
     if (bv.n == 1) {
         leaf(0);
@@ -659,6 +663,45 @@ __global__ void __launch_bounds__(128) k_direct(BvhDev bv, const float *__restri
     for (int c = 3; c < 3 * K; ++c) e[c] = 0.0f;
 }
 
+// Direct light with the BRDF: E_i,l = (R_i / pi) (.) Y(w^(i)) I_l max(0, n_i . w) / r^2 T_il
+// with w the unit direction to the light expressed in i's tangent frame.
+template <int K>
+__global__ void __launch_bounds__(128) k_direct_sh(BvhDev bv, const float *__restrict__ R,
+                                                   const float *__restrict__ lpos, const float *__restrict__ lI, int Lt,
+                                                   float *__restrict__ E, int *err) {
+    extern __shared__ uint32_t stack_mem[];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= bv.n * Lt) return;
+    const int64_t i = idx / Lt;
+    const int l = (int)(idx - i * Lt);
+    const SurfRec rr = bv.rec[bv.inv[i]];
+    float *e = E + ((i * Lt + l) * K) * 3;
+    const float dx = __fsub_rn(lpos[3 * l + 0], rr.a.x);
+    const float dy = __fsub_rn(lpos[3 * l + 1], rr.a.y);
+    const float dz = __fsub_rn(lpos[3 * l + 2], rr.a.z);
+    const float dd = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __fmul_rn(dx, dx)));
+    const float len = sqrt_rn(dd);
+    const float ndot = rr.b.x * dx + rr.b.y * dy + rr.b.z * dz;
+    float base = 0.0f;
+    float Y[K];
+    if (ndot > 0.0f && dd > 0.0f) {
+        const float t_lo = __fdiv_rn(bv.bounds[6], len);
+        const float T = trace_shadow(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, (uint32_t)i, t_lo,
+                                     stack_mem + threadIdx.x, blockDim.x, err);
+        base = lI[l] * (ndot / len) / dd * T * 0.318309886183791f;
+        const float il = 1.0f / len;
+        sh_eval<K>((dx * rr.c.x + dy * rr.c.y + dz * rr.c.z) * il, (dx * rr.d.x + dy * rr.d.y + dz * rr.d.z) * il,
+                   ndot * il, Y);
+    } else {
+#pragma unroll
+        for (int a = 0; a < K; ++a) Y[a] = 0.0f;
+    }
+    const float *Ri = R + i * K * 3;
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+        for (int c = 0; c < 3; ++c) e[3 * a + c] = Ri[3 * a + c] * Y[a] * base;
+}
+
 // ---------------------------------------------------------------------------
 // opacity backward (compositing backward, recomputing the hits)
 // ---------------------------------------------------------------------------
@@ -1042,6 +1085,21 @@ gsrad_status launch_opacity_scale(const float *gF, int64_t nnz, int64_t n, void 
 
 static const int *fx_exp_ptr(const BvhDev &bv, const void *acc) {
     return reinterpret_cast<const int *>(static_cast<const char *>(acc) + (size_t)8 * bv.n * 8 + 4);
+}
+
+gsrad_status launch_direct_sh(const BvhDev &bv, const float *R, const float *lpos, const float *lI, int Lt, int K,
+                              float *E, int *err, hipStream_t st) {
+    const int64_t total = bv.n * Lt;
+    const dim3 grid((unsigned)((total + 127) / 128));
+    const size_t smem = ff_stack_bytes(128);
+    switch (K) {
+        case 1: hipLaunchKernelGGL(k_direct_sh<1>, grid, dim3(128), smem, st, bv, R, lpos, lI, Lt, E, err); break;
+        case 4: hipLaunchKernelGGL(k_direct_sh<4>, grid, dim3(128), smem, st, bv, R, lpos, lI, Lt, E, err); break;
+        case 9: hipLaunchKernelGGL(k_direct_sh<9>, grid, dim3(128), smem, st, bv, R, lpos, lI, Lt, E, err); break;
+        case 16: hipLaunchKernelGGL(k_direct_sh<16>, grid, dim3(128), smem, st, bv, R, lpos, lI, Lt, E, err); break;
+        default: set_error("direct light: K must be 1, 4, 9 or 16"); return GSRAD_EINVAL;
+    }
+    return check_hip(hipGetLastError(), "SH direct light launch");
 }
 
 gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min,

@@ -25,7 +25,8 @@ SOA = ("px", "py", "pz", "tux", "tuy", "tuz", "tvx", "tvy", "tvz", "nx", "ny", "
 EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_info", "gsrad_bvh_height",
            "gsrad_effective_area", "gsrad_reflectance", "gsrad_form_factors", "gsrad_ff_info", "gsrad_ff_view",
            "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
-           "gsrad_transport_solve_noalloc",
+           "gsrad_transport_solve_noalloc", "gsrad_brdf_reflectance", "gsrad_brdf_backward",
+           "gsrad_direct_light_sh", "gsrad_transport_solve_sh", "gsrad_transport_backward_sh",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
@@ -85,6 +86,11 @@ def lib():
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
             "gsrad_transport_solve_noalloc": ([vp, vp, vp, i32, i32, i32, vp, vp], i32),
+            "gsrad_brdf_reflectance": ([vp, vp, vp, vp, vp, i32, vp, vp], i32),
+            "gsrad_brdf_backward": ([vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp], i32),
+            "gsrad_direct_light_sh": ([vp, vp, i32, vp, vp, i32, vp, vp], i32),
+            "gsrad_transport_solve_sh": ([vp, vp, vp, vp, i32, i32, i32, vp, pvp, vp], i32),
+            "gsrad_transport_backward_sh": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_transport_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_opacity_backward": ([vp, vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_ray_hits": ([vp, ctypes.POINTER(_FFParams), vp, i64, i32, vp, vp, vp, vp, vp, vp, vp], i32),
@@ -361,6 +367,76 @@ def transport_solve_noalloc(ff: FF, rho: torch.Tensor, E: torch.Tensor, n_bounce
     _check(lib().gsrad_transport_solve_noalloc(ff.h, _ptr(rho, name="rho"), _ptr(E, name="E"), Lt, K, int(n_bounces),
                                                _ptr(out, name="out"), _stream(stream)), "gsrad_transport_solve_noalloc")
     return out
+
+
+def brdf_reflectance(bvh: BVH, k: torch.Tensor, albedo_d: torch.Tensor, albedo_s: torch.Tensor,
+                     shininess: torch.Tensor, K: int, stream=None) -> torch.Tensor:
+    """R = pi o f^c [n, K, 3] of the diffuse + Phong BRDF (App. A), in each
+    surfel's tangent frame."""
+    R = torch.empty((bvh.n, int(K), 3), dtype=torch.float32, device="cuda")
+    _check(lib().gsrad_brdf_reflectance(bvh.h, _ptr(k, name="k"), _ptr(albedo_d, name="albedo_d"),
+                                        _ptr(albedo_s, name="albedo_s"), _ptr(shininess, name="shininess"), int(K),
+                                        _ptr(R), _stream(stream)), "gsrad_brdf_reflectance")
+    return R
+
+
+def brdf_backward(bvh: BVH, k, albedo_d, albedo_s, shininess, grad_R: torch.Tensor, stream=None):
+    """Gradients of sum(grad_R * R) with respect to (opacity, k, a^d, a^s, s)."""
+    n, K = bvh.n, int(grad_R.shape[1])
+    dev = torch.device("cuda")
+    go = torch.empty(n, dtype=torch.float32, device=dev)
+    gk = torch.empty(n, dtype=torch.float32, device=dev)
+    gad = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    gas = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    gs = torch.empty(n, dtype=torch.float32, device=dev)
+    _check(lib().gsrad_brdf_backward(bvh.h, _ptr(k, name="k"), _ptr(albedo_d, name="albedo_d"),
+                                     _ptr(albedo_s, name="albedo_s"), _ptr(shininess, name="shininess"), K,
+                                     _ptr(grad_R, name="grad_R"), _ptr(go), _ptr(gk), _ptr(gad), _ptr(gas), _ptr(gs),
+                                     _stream(stream)), "gsrad_brdf_backward")
+    return go, gk, gad, gas, gs
+
+
+def direct_light_sh(bvh: BVH, R: torch.Tensor, light_pos: torch.Tensor, light_I: torch.Tensor,
+                    out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """E [n, Lt, K, 3] from point lights through the BRDF coefficients R."""
+    Lt, K = int(light_pos.shape[0]), int(R.shape[1])
+    if light_pos.shape != (Lt, 3) or light_I.shape != (Lt,):
+        raise ValueError("light_pos must be [Lt, 3] and light_I [Lt]")
+    E = out if out is not None else torch.empty((bvh.n, Lt, K, 3), dtype=torch.float32, device="cuda")
+    _check(lib().gsrad_direct_light_sh(bvh.h, _ptr(R, name="R"), K, _ptr(light_pos, name="light_pos"),
+                                       _ptr(light_I, name="light_I"), Lt, _ptr(E, name="E"), _stream(stream)),
+           "gsrad_direct_light_sh")
+    return E
+
+
+def transport_solve_sh(ff: FF, bvh: BVH, R: torch.Tensor, E: torch.Tensor, n_bounces: int,
+                       tape: Optional[Tape] = None, keep_tape: bool = True, out: Optional[torch.Tensor] = None,
+                       stream=None):
+    """B = E + R (.) (T B) iterated n_bounces times (directional transfer).
+    Returns (B, tape)."""
+    if E.dim() != 4 or E.shape[3] != 3:
+        raise ValueError("E must be [n, Lt, K, 3]")
+    Lt, K = int(E.shape[1]), int(E.shape[2])
+    B = out if out is not None else torch.empty_like(E)
+    tp = tape if tape is not None else (Tape() if keep_tape else None)
+    _check(lib().gsrad_transport_solve_sh(ff.h, bvh.h, _ptr(R, name="R"), _ptr(E, name="E"), Lt, K, int(n_bounces),
+                                          _ptr(B, name="B"), ctypes.byref(tp.h) if tp is not None else None,
+                                          _stream(stream)), "gsrad_transport_solve_sh")
+    return B, tp
+
+
+def transport_backward_sh(ff: FF, bvh: BVH, tape: Tape, R: torch.Tensor, grad_B: torch.Tensor,
+                          want_grad_F: bool = True, stream=None):
+    """(grad_E, grad_R, grad_F) of the directional transfer."""
+    nnz = ff.info()[1]
+    grad_E = torch.empty_like(grad_B)
+    grad_R = torch.empty_like(R)
+    grad_F = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda") if want_grad_F else None
+    _check(lib().gsrad_transport_backward_sh(ff.h, bvh.h, tape.h, _ptr(R, name="R"), _ptr(grad_B, name="grad_B"),
+                                             _ptr(grad_E), _ptr(grad_R),
+                                             _ptr(grad_F) if grad_F is not None else None, _stream(stream)),
+           "gsrad_transport_backward_sh")
+    return grad_E, grad_R, (grad_F[:nnz] if grad_F is not None else None)
 
 
 def transport_backward(ff: FF, tape: Tape, rho: torch.Tensor, grad_B: torch.Tensor, want_grad_F: bool = True,

@@ -532,3 +532,13 @@ def seeded_csr(n: int, nnz_per_row: int, seed: int, row_sum: float = 0.6, n_cols
     scale[lens > 0] = row_sum / np.maximum(rs, 1e-30)
     v = v * np.repeat(scale, lens)
     return row_ptr, np.ascontiguousarray(c), np.ascontiguousarray(v.astype(np.float32))
+
+
+def phong_materials(n: int, seed: int, shininess=(1.0, 20.0)) -> Dict[str, np.ndarray]:
+    """Seeded diffuse + Phong materials per surfel (Eq. brdf parameters):
+    blend k ~ U[0, 1], diffuse and specular albedo ~ U[0.1, 0.9]^3 and
+    shininess ~ U[shininess], FP32."""
+    rng = np.random.default_rng(seed)
+    f32 = lambda a: np.ascontiguousarray(a.astype(np.float32))  # noqa: E731
+    return {"k": f32(rng.uniform(0.0, 1.0, n)), "albedo_d": f32(rng.uniform(0.1, 0.9, (n, 3))),
+            "albedo_s": f32(rng.uniform(0.1, 0.9, (n, 3))), "shininess": f32(rng.uniform(*shininess, n))}
