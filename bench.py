@@ -92,6 +92,8 @@ def parse():
                          "batch")
     ap.add_argument("--fp32-lights", type=int, default=10,
                     help="multi_light: lights timed on the plain FP32 per-light path (scaled to all lights)")
+    ap.add_argument("--batch-lights", type=int, nargs=2, default=[8, 100], metavar=("MIN", "MAX"),
+                    help="uneven_batch: lights per room drawn from U{MIN..MAX}")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain FP32 copy kernel of this size first (HBM counter calibration)")
     return ap.parse_args()
@@ -113,7 +115,7 @@ def main():
     if args.workload == "multi_light":
         return multi_light(args, g, scenes, torch, np)
     if args.workload == "uneven_batch":
-        return uneven_batch(args, g, scenes, torch, np)
+        return uneven_batch(args, g, scenes, torch, np, lights=tuple(args.batch_lights))
     sc = scenes.make_config("fruit_bowl", n=args.n)
     N, R, K, nb, topk, Lt = sc.n, sc.R, sc.K, sc.n_bounces, sc.topk, sc.n_lights
     dev = torch.device("cuda")
@@ -227,6 +229,8 @@ def main():
 
     if not args.no_check:
         result["err_vs_fp64"] = sampled_errors(g, sc, state, samp[:8], torch, np)
+        result["err_vs_fp64"]["timed_step_transport"] = step_errors(g, sc, state, out, E, B, gB, alb, torch, np)
+        result["err_vs_fp64"]["grad_opacity_sampled_rows"] = opacity_errors(g, sc, state, torch, np)
         result["err_vs_fp64"]["transport_full_size"] = slice_errors(g, sc, torch, np)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_receivers, nnz, np)
@@ -267,6 +271,59 @@ def sampled_errors(g, sc, state, recv, torch, np):
     e_err = float(np.max(np.abs(Eg - Eo)) / max(np.max(np.abs(Eo)), 1e-300))
     return {"F_rows": num / den if den > 0 else None, "F_topk_threshold_swaps": swaps, "E_rows": e_err,
             "rows_sampled": len(recv)}
+
+
+def _rel(np, x, ref):
+    return float(np.max(np.abs(np.asarray(x, np.float64) - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def step_errors(g, sc, state, out, E, B, gB, alb, torch, np):
+    """The last timed step's own transport against the FP64 oracle on its
+    own ray-cast F: E comes from point lights, so it has only the DC
+    coefficient, every B^(k) is DC-only, and the oracle's FP64 bounces and
+    adjoint on the 3 DC columns (with the step's grad_B restricted to them)
+    give the exact B, grad_E on those columns, grad_rho and every entry of
+    grad_F of the whole launch; the other columns of B must be 0."""
+    import oracle
+    import scipy.sparse as sp
+    ff, gE, grho, gF = out[0], out[1], out[2], out[3]
+    rp, col, val = (x.cpu().numpy() for x in ff.csr())
+    N = rp.shape[0] - 1
+    F = sp.csr_matrix((val.astype(np.float64), col, rp), shape=(N, N))
+    rho = g.reflectance(state["bvh"], alb).cpu().numpy()
+    Ed = E.cpu().numpy()[:, :, :1, :]
+    gBd = gB.cpu().numpy()[:, :, :1, :]
+    Bo, tp = oracle.bounce(F, rho, Ed, sc.n_bounces, keep_tape=True)
+    gEo, gro, gFo = oracle.adjoint(F, rho, tp, gBd)
+    Bg = B.cpu().numpy()
+    return {"B": _rel(np, Bg[:, :, :1, :], Bo), "B_non_dc_all_zero": bool(not Bg[:, :, 1:, :].any()),
+            "grad_E_dc": _rel(np, gE.cpu().numpy()[:, :, :1, :], gEo), "grad_rho": _rel(np, grho.cpu().numpy(), gro),
+            "grad_F": _rel(np, gF.cpu().numpy(), gFo), "entries": int(F.nnz)}
+
+
+def opacity_errors(g, sc, state, torch, np, n_rows=64):
+    """grad_opacity in the step's launch configuration with dL/dF non-zero on
+    n_rows sampled receiver rows: the oracle's brute-force compositing
+    backward over those receivers is the exact gradient of every surfel."""
+    import oracle
+    rp, col, _ = (x.cpu().numpy() for x in state["ff"].csr())
+    N = rp.shape[0] - 1
+    recv = np.sort(np.random.default_rng(19).choice(N, size=n_rows, replace=False)).astype(np.int64)
+    rng = np.random.default_rng(20)
+    gF = np.zeros(rp[-1], np.float32)
+    gp, gc, gv = [0], [], []
+    for i in recv:
+        v = rng.standard_normal(rp[i + 1] - rp[i]).astype(np.float32)
+        gF[rp[i]:rp[i + 1]] = v
+        gc.append(col[rp[i]:rp[i + 1]])
+        gv.append(v.astype(np.float64))
+        gp.append(gp[-1] + v.shape[0])
+    go = g.opacity_backward(state["bvh"], state["ff"], torch.from_numpy(gF).cuda(), None, None)[0].cpu().numpy()
+    te = oracle.default_t_eps(sc.surfels)
+    goo, _ = oracle.opacity_backward(sc.surfels, sc.albedo, sc.R, sc.seed, te, sc.t_min,
+                                     (np.asarray(gp, np.int64), np.concatenate(gc), np.concatenate(gv)),
+                                     receivers=recv)
+    return {"grad_opacity": _rel(np, go, goo), "rows": n_rows, "surfels_reached": int(np.count_nonzero(goo))}
 
 
 def slice_errors(g, sc, torch, np, slots=(0, 15)):
@@ -471,13 +528,14 @@ def multi_light(args, g, scenes, torch, np):
     print(json.dumps(result))
 
 
-def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
+def uneven_batch(args, g, scenes, torch, np, lights=(8, 100), topk=512):
     """64 cluster rooms with log-uniform surfel counts in [2048, 65536]
-    (1.19 M surfels, 152 M rays at R = 128), K = 9, 8 bounces, each room
-    lit by U{1..4} lights, F truncated to 512 entries per row.  A step is the
-    whole path: per-scene BVH, form factors and direct light, then one batch
-    solve and backward (persistent launches, tuned lanes per row, captured
-    bounce loop).  The same transport run scene by scene is timed beside it."""
+    (about 1.2 M surfels, 150 M rays at R = 128), K = 9, 8 bounces, each room
+    lit by U{8..100} point lights (its right-hand sides), F truncated to 512
+    entries per row.  A step is the whole path: per-scene BVH, form factors
+    and direct light, then one batch solve and backward (persistent
+    launches, tuned lanes per row, captured bounce and adjoint loops).  The
+    same transport run scene by scene is timed beside it."""
     rooms = scenes.uneven_batch(lights=lights)
     K, R, nb = rooms[0].K, rooms[0].R, rooms[0].n_bounces
     dev = torch.device("cuda")
@@ -493,7 +551,8 @@ def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
         for s, sc in enumerate(rooms):
             bvh = g.build_bvh(surs[s], st["bvh"][s])
             st["bvh"][s] = bvh
-            st["ff"][s] = g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, topk=topk, ff=st["ff"][s], records=False)
+            st["ff"][s] = g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, topk=topk, ff=st["ff"][s], records=False,
+                                         compact=True)
             Es.append(g.direct_light(bvh, albs[s], lps[s], lIs[s], K))
             rhos.append(g.reflectance(bvh, albs[s]))
         batch = g.batch_create(st["ff"], Lts, K, batch=st.get("batch"))
@@ -507,15 +566,22 @@ def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
         return B, out
 
     calibration_copy(args, torch, dev)
-    for _ in range(args.warmup):
+    print(f"uneven batch: {len(rooms)} rooms, {sum(sc.n for sc in rooms)} surfels, {sum(Lts)} lights",
+          file=sys.stderr, flush=True)
+    for w in range(args.warmup):
         step()
+        torch.cuda.synchronize()
+        print(f"warm-up step {w + 1} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     g.gsrad.profile_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step()
+        if args.steps > 1:
+            print(f"timed step {k + 1} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print(f"timed steps done: {(t1 - t0) / args.steps:.2f} s per step", file=sys.stderr, flush=True)
     prof = g.gsrad.profile_report()
     g.gsrad.profile_enable(False)
     ms = (t1 - t0) * 1e3 / args.steps
@@ -535,6 +601,7 @@ def uneven_batch(args, g, scenes, torch, np, lights=(1, 4), topk=512):
         g.transport_backward(st["ff"][s], tp, st["rhos"][s], gBs[s].contiguous())
     torch.cuda.synchronize()
     t_scene = (time.perf_counter() - t2) * 1e3
+    print(f"scene-by-scene transport done: {t_scene / 1e3:.2f} s", file=sys.stderr, flush=True)
     rays = sum(sc.n for sc in rooms) * R
     phases = {k: v["total_ms"] / args.steps for k, v in prof.items()}
     bb = prof.get("batch_bounces", {}).get("avg_ms", 0.0)

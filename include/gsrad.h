@@ -85,8 +85,13 @@ typedef struct gsrad_surfels {
  *   flags            GSRAD_FF_NO_RECORDS: do not keep the per-ray hit
  *                    records (the opacity backward then recomputes every
  *                    ray by traversal instead of reading them).
+ *                    GSRAD_FF_COMPACT: free the ray cast's scratch (hit
+ *                    records not kept for the backward, row staging) before
+ *                    returning, for many handles alive at once (batches of
+ *                    scenes); the next cast on the handle allocates again.
  */
 #define GSRAD_FF_NO_RECORDS 1
+#define GSRAD_FF_COMPACT 2
 typedef struct gsrad_ff_params {
     int32_t rays_per_surfel;
     int32_t topk;
@@ -297,8 +302,9 @@ gsrad_status gsrad_tape_grad_F_dense(const gsrad_tape *tape, float *grad_F_out, 
  * columns) first.  The lanes-per-row shape (16, 32 or 64) is chosen by
  * timing each candidate on the batch's own rows at the first solve (every
  * candidate adds each output in the same order, so the choice never
- * changes a result).  The bounce loop is captured once into a HIP graph
- * and replayed while the arguments stay the same.  The iterates are kept
+ * changes a result).  The bounce loop and the adjoint loop are each
+ * captured once into a HIP graph and replayed while their arguments stay
+ * the same.  The iterates are kept
  * in the batch for gsrad_batch_transport_backward, the exact adjoint
  * (same formulas as gsrad_transport_backward; grad_F in the block-diagonal
  * F's CSR order, see gsrad_batch_ff).  Calls on one batch must not overlap.
@@ -315,6 +321,14 @@ gsrad_status gsrad_batch_transport_solve(gsrad_batch *batch, const float *rho, c
                                          float *B_out, void *stream);
 gsrad_status gsrad_batch_transport_backward(gsrad_batch *batch, const float *rho, const float *grad_B,
                                             float *grad_E, float *grad_rho, float *grad_F, void *stream);
+/*
+ * Force the lanes per row of the batch's bounce and adjoint launches (16, 32
+ * or 64; 0 returns to the timed choice).  Every shape adds each output in
+ * the same order, so results are bit-identical whatever is chosen; for
+ * tests and tuning experiments.  The timed choice is remembered per batch
+ * shape (rows, stored entries, values) for the rest of the process.
+ */
+gsrad_status gsrad_batch_set_lanes(gsrad_batch *batch, int32_t lanes_bounce, int32_t lanes_adjoint);
 void gsrad_batch_destroy(gsrad_batch *batch);
 
 /*

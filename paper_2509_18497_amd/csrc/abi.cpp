@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -251,6 +252,13 @@ struct gsrad_batch {
     hipGraphExec_t exec = nullptr;
     const void *g_rho = nullptr, *g_E = nullptr, *g_B = nullptr, *g_tape = nullptr;
     int g_nb = -1, g_lpr = 0;
+    // captured adjoint loop and its arguments
+    hipGraph_t agraph = nullptr;
+    hipGraphExec_t aexec = nullptr;
+    const void *a_rho = nullptr, *a_gE = nullptr, *a_L = nullptr, *a_lam0 = nullptr, *a_ft[3] = {};
+    int a_nb = -1, a_lpr = 0;
+    // lanes per row forced by gsrad_batch_set_lanes (0: tuned)
+    int force_fwd = 0, force_adj = 0;
     gsrad::BatchDev dev() const {
         gsrad::BatchDev d;
         d.rows = rows;
@@ -268,6 +276,11 @@ struct gsrad_batch {
         exec = nullptr;
         graph = nullptr;
         g_nb = -1;
+        if (aexec) (void)hipGraphExecDestroy(aexec);
+        if (agraph) (void)hipGraphDestroy(agraph);
+        aexec = nullptr;
+        agraph = nullptr;
+        a_nb = -1;
     }
     ~gsrad_batch() {
         drop_graph();
@@ -348,6 +361,11 @@ gsrad_status ensure_transpose(gsrad_ff *ff, hipStream_t st) {
     GS_TRY(csr_transpose(ff->csr(), ff->t_row_ptr.as<int64_t>(), ff->t_col.as<int32_t>(), ff->t_val.as<float>(),
                          ff->perm.as<uint32_t>(), ff->t_temp.p, tb, st));
     ff->has_t = true;
+    // a large sort scratch (batches of many scenes) is not kept
+    if (tb > (size_t(2) << 30)) {
+        GS_TRY(check_hip(hipStreamSynchronize(st), "transpose sync"));
+        ff->t_temp.release();
+    }
     return GSRAD_OK;
 }
 
@@ -585,6 +603,15 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     h->deep_stack = deep;
     // most rows needed the largest table: start there next time
     h->agg_log2h = flags[2] > n / 4 ? kLog2TableMax : log2h;
+    if (p->flags & GSRAD_FF_COMPACT) {
+        // the stream must be done with the scratch before it is freed
+        if ((e = check_hip(hipStreamSynchronize(st), "ff compact sync")) != GSRAD_OK) return fail(e);
+        if (!keep) {
+            h->recs.release();
+            h->rcnt.release();
+        }
+        for (DevBuf *b : {&h->ell_col, &h->ell_val, &h->row_len, &h->redo, &h->scan_temp}) b->release();
+    }
     *ff = h;
     return GSRAD_OK;
 }
@@ -1464,8 +1491,8 @@ namespace {
 
 // Lanes per row for a ragged product: each candidate runs once on the
 // batch's own rows (into scratch) and the fastest is kept.
-gsrad_status autotune_lanes(gsrad_batch *b, const Csr &F, bool adjoint, const float *in, const float *rho,
-                            float *scratch, float *scratch2, hipStream_t st, int *best) {
+gsrad_status autotune_lanes_timed(gsrad_batch *b, const Csr &F, bool adjoint, const float *in, const float *rho,
+                                  float *scratch, float *scratch2, hipStream_t st, int *best) {
     hipEvent_t e0, e1;
     GS_TRY(check_hip(hipEventCreate(&e0), "tune event"));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1495,6 +1522,31 @@ gsrad_status autotune_lanes(gsrad_batch *b, const Csr &F, bool adjoint, const fl
     return e;
 }
 
+// Lanes per row chosen by timing, remembered per batch shape (rows, stored
+// entries, values of the ragged arrays, direction) for the process, so a
+// new batch of a shape already seen skips the timing runs.
+std::mutex g_tune_mu;
+std::map<std::tuple<int64_t, int64_t, int64_t, bool>, int> g_tune_cache;
+
+gsrad_status autotune_lanes(gsrad_batch *b, const Csr &F, bool adjoint, const float *in, const float *rho,
+                            float *scratch, float *scratch2, hipStream_t st, int *best) {
+    const auto key = std::make_tuple(b->rows, F.nnz, b->vals, adjoint);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *best = it->second;
+            return GSRAD_OK;
+        }
+    }
+    const gsrad_status r = autotune_lanes_timed(b, F, adjoint, in, rho, scratch, scratch2, st, best);
+    if (r == GSRAD_OK && *best != 0) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = *best;
+    }
+    return r;
+}
+
 }  // namespace
 
 gsrad_status gsrad_batch_transport_solve(gsrad_batch *b, const float *rho, const float *E, int32_t n_bounces,
@@ -1519,6 +1571,7 @@ gsrad_status gsrad_batch_transport_solve(gsrad_batch *b, const float *rho, const
         b->drop_graph();   // the captured loop writes into the old tape
         GS_TRY(b->Bt.ensure(tape_bytes, "batch forward tape"));
     }
+    if (b->force_fwd) b->lpr_fwd = b->force_fwd;
     if (b->lpr_fwd == 0) {
         ProfScope ps("batch_tune", st);
         GS_TRY(autotune_lanes(b, F, false, E, rho, B_out, nullptr, st, &b->lpr_fwd));
@@ -1587,6 +1640,7 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
     GS_TRY(check_hip(hipMemcpyAsync(L + (size_t)(nb - 1) * vals, grad_B, (size_t)vals * 4, hipMemcpyDeviceToDevice, st),
                      "adjoint seed"));
     const Csr FT = b->F->csr_t();
+    if (b->force_adj) b->lpr_adj = b->force_adj;
     if (b->lpr_adj == 0) {
         // timing runs write only into scratch: lam0 and the slot past the tape
         float *s2 = L + (size_t)nb * vals;
@@ -1594,12 +1648,48 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
         GS_TRY(check_hip(hipMemsetAsync(s2, 0, (size_t)vals * 4, st), "tune scratch"));
         GS_TRY(autotune_lanes(b, FT, true, grad_B, rho, b->lam0.as<float>(), s2, st, &b->lpr_adj));
     }
-    for (int k = nb - 1; k >= 0; --k) {
-        const float *in = L + (size_t)k * vals;   // lambda^(k+1)
-        float *out = k >= 1 ? L + (size_t)(k - 1) * vals : b->lam0.as<float>();
+    // the adjoint loop is captured once into a HIP graph and replayed while
+    // its arguments stay the same
+    float *lam0 = b->lam0.as<float>();
+    const bool hit = b->aexec && b->a_rho == rho && b->a_gE == grad_E && b->a_L == L && b->a_lam0 == lam0 &&
+                     b->a_nb == nb && b->a_lpr == b->lpr_adj && b->a_ft[0] == FT.row_ptr && b->a_ft[1] == FT.col &&
+                     b->a_ft[2] == FT.val;
+    if (!hit) {
+        if (b->aexec) (void)hipGraphExecDestroy(b->aexec);
+        if (b->agraph) (void)hipGraphDestroy(b->agraph);
+        b->aexec = nullptr;
+        b->agraph = nullptr;
+        b->a_nb = -1;
+        if (!b->cap) GS_TRY(check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream"));
+        GS_TRY(check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
+        gsrad_status e = GSRAD_OK;
+        for (int k = nb - 1; k >= 0 && e == GSRAD_OK; --k) {
+            const float *in = L + (size_t)k * vals;   // lambda^(k+1)
+            float *out = k >= 1 ? L + (size_t)(k - 1) * vals : lam0;
+            e = launch_ragged_spmm(b->dev(), FT, b->lpr_adj, true, in, nullptr, rho, out, grad_E,
+                                   b->counter.as<uint32_t>(), b->cap);
+        }
+        hipGraph_t gr = nullptr;
+        const gsrad_status ec = check_hip(hipStreamEndCapture(b->cap, &gr), "end capture");
+        if (e != GSRAD_OK || ec != GSRAD_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return e != GSRAD_OK ? e : ec;
+        }
+        b->agraph = gr;
+        GS_TRY(check_hip(hipGraphInstantiate(&b->aexec, gr, nullptr, nullptr, 0), "graph instantiate"));
+        b->a_rho = rho;
+        b->a_gE = grad_E;
+        b->a_L = L;
+        b->a_lam0 = lam0;
+        b->a_nb = nb;
+        b->a_lpr = b->lpr_adj;
+        b->a_ft[0] = FT.row_ptr;
+        b->a_ft[1] = FT.col;
+        b->a_ft[2] = FT.val;
+    }
+    {
         ProfScope ps("batch_adjoint", st);
-        GS_TRY(launch_ragged_spmm(b->dev(), FT, b->lpr_adj, true, in, nullptr, rho, out, grad_E,
-                                  b->counter.as<uint32_t>(), st));
+        GS_TRY(check_hip(hipGraphLaunch(b->aexec, st), "graph launch"));
     }
     if (grad_F || grad_rho) {
         ProfScope ps("batch_sddmm", st);
@@ -1607,6 +1697,20 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
         GS_TRY(launch_ragged_sddmm(b->dev(), b->F->csr(), nb, vals, max_C, b->Bt.as<float>(), L, rho, grad_F, grad_rho,
                                    b->counter.as<uint32_t>(), st));
     }
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_batch_set_lanes(gsrad_batch *b, int32_t lanes_bounce, int32_t lanes_adjoint) {
+    if (!b) return einval("gsrad_batch_set_lanes: null batch");
+    for (int v : {lanes_bounce, lanes_adjoint})
+        if (v != 0 && v != 16 && v != 32 && v != 64)
+            return einval("gsrad_batch_set_lanes: lanes per row must be 0 (tuned), 16, 32 or 64");
+    b->force_fwd = lanes_bounce;
+    b->force_adj = lanes_adjoint;
+    // the next solve / backward takes the forced (or re-tuned) shape
+    b->lpr_fwd = lanes_bounce;
+    b->lpr_adj = lanes_adjoint;
+    b->drop_graph();
     return GSRAD_OK;
 }
 

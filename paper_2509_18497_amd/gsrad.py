@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EHIP, ENAN, EOVERFLOW, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP32 = 0
 BF16 = 1
 FF_NO_RECORDS = 1
+FF_COMPACT = 2
 SOA = ("px", "py", "pz", "tux", "tuy", "tuz", "tvx", "tvy", "tvz", "nx", "ny", "nz", "su", "sv", "opacity")
 
 EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_info", "gsrad_bvh_height",
@@ -27,6 +28,7 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
            "gsrad_transport_solve_noalloc", "gsrad_brdf_reflectance", "gsrad_brdf_backward",
            "gsrad_direct_light_sh", "gsrad_transport_solve_sh", "gsrad_transport_backward_sh",
+           "gsrad_batch_set_lanes",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
@@ -82,6 +84,7 @@ def lib():
             "gsrad_batch_ff": ([vp, pvp], i32),
             "gsrad_batch_transport_solve": ([vp, vp, vp, i32, vp, vp], i32),
             "gsrad_batch_transport_backward": ([vp, vp, vp, vp, vp, vp, vp], i32),
+            "gsrad_batch_set_lanes": ([vp, i32, i32], i32),
             "gsrad_tape_grad_F_dense": ([vp, vp, vp], i32),
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
@@ -218,9 +221,10 @@ def reflectance(bvh: BVH, albedo: torch.Tensor, stream=None) -> torch.Tensor:
 
 
 def form_factors(bvh: BVH, rays_per_surfel: int, seed: int, t_min: float = 1e-4, t_eps: float = 0.0,
-                 topk: int = 0, ff: Optional[FF] = None, records: bool = True, stream=None) -> FF:
+                 topk: int = 0, ff: Optional[FF] = None, records: bool = True, compact: bool = False,
+                 stream=None) -> FF:
     p = _FFParams(int(rays_per_surfel), int(topk), int(seed) & 0xFFFFFFFFFFFFFFFF, float(t_min), float(t_eps),
-                  0 if records else FF_NO_RECORDS, 0)
+                  (0 if records else FF_NO_RECORDS) | (FF_COMPACT if compact else 0), 0)
     out = ff if ff is not None else FF()
     _check(lib().gsrad_form_factors(bvh.h, ctypes.byref(p), ctypes.byref(out.h), _stream(stream)),
            "gsrad_form_factors")
@@ -301,6 +305,11 @@ def batch_create(ffs, lights, K: int, batch: Optional[Batch] = None, stream=None
     return b
 
 
+def batch_set_lanes(batch: Batch, lanes_bounce: int, lanes_adjoint: int):
+    """Force the lanes per row of the batch launches (16, 32, 64; 0 = timed)."""
+    _check(lib().gsrad_batch_set_lanes(batch.h, int(lanes_bounce), int(lanes_adjoint)), "gsrad_batch_set_lanes")
+
+
 def batch_transport_solve(batch: Batch, rho: torch.Tensor, E: torch.Tensor, n_bounces: int,
                           out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """B = E + rho*(F B), n_bounces times, on every scene of the batch (flat E)."""
@@ -311,9 +320,10 @@ def batch_transport_solve(batch: Batch, rho: torch.Tensor, E: torch.Tensor, n_bo
 
 
 def batch_transport_backward(batch: Batch, rho: torch.Tensor, grad_B: torch.Tensor, want_grad_F: bool = True,
-                             stream=None):
-    """dL/dE (flat), dL/drho, dL/dF at the block-diagonal F's entries."""
-    grad_E = torch.empty_like(grad_B)
+                             out: Optional[torch.Tensor] = None, stream=None):
+    """dL/dE (flat, into out if given), dL/drho, dL/dF at the block-diagonal
+    F's entries."""
+    grad_E = out if out is not None else torch.empty_like(grad_B)
     grad_rho = torch.empty_like(rho)
     _, nnz = batch.ff().info()
     grad_F = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda") if want_grad_F else None

@@ -191,3 +191,59 @@ def test_batch_refill_keeps_shape_and_follows_new_values(g):
     for x, f2, Bb in zip(sc, ffs2, B):
         Bs, _ = g.transport_solve(f2, dev(x["rho"]), dev(x["E"]), nb, keep_tape=False)
         assert torch.equal(Bb, Bs)
+
+
+@pytest.mark.parametrize("lanes", [(16, 64), (32, 32), (64, 16)])
+def test_every_lanes_shape_is_bit_identical_to_the_per_scene_path(g, lanes):
+    """Each lanes-per-row variant the tuner can pick, forced for the bounce
+    and for the adjoint, reproduces the scene-by-scene results bit for bit."""
+    K, nb = 9, 3
+    sc = _scenes(g, K)
+    batch = g.batch_create([x["ff"] for x in sc], [x["lt"] for x in sc], K)
+    g.batch_set_lanes(batch, *lanes)
+    rho = dev(np.concatenate([x["rho"] for x in sc]))
+    E = _flat([x["E"] for x in sc])
+    gB = _flat([x["gB"] for x in sc])
+    B = batch.unpack(g.batch_transport_solve(batch, rho, E, nb))
+    gE, gr, gF = g.batch_transport_backward(batch, rho, gB)
+    info = batch.info()
+    assert (info["lanes_bounce"], info["lanes_adjoint"]) == lanes
+    gE = batch.unpack(gE)
+    r0 = e0 = 0
+    for x, Bb, gEb in zip(sc, B, gE):
+        Bs, tape = g.transport_solve(x["ff"], dev(x["rho"]), dev(x["E"]), nb)
+        gEs, grs, gFs = g.transport_backward(x["ff"], tape, dev(x["rho"]), dev(x["gB"]))
+        assert torch.equal(Bb, Bs)
+        assert torch.equal(gEb, gEs)
+        assert torch.equal(gr[r0:r0 + x["n"]], grs)
+        assert torch.equal(gF[e0:e0 + x["F"].nnz], gFs)
+        r0 += x["n"]
+        e0 += x["F"].nnz
+    with pytest.raises(g.GsradError):
+        g.batch_set_lanes(batch, 8, 0)
+
+
+def test_captured_adjoint_loop_replays_with_new_values(g):
+    """The adjoint loop is a captured graph too: replays with the same
+    arguments after eager updates of grad_B and rho follow the new values."""
+    K, nb = 4, 3
+    sc = _scenes(g, K)
+    batch = g.batch_create([x["ff"] for x in sc], [x["lt"] for x in sc], K)
+    rho = dev(np.concatenate([x["rho"] for x in sc]))
+    E = _flat([x["E"] for x in sc])
+    gB = _flat([x["gB"] for x in sc])
+    B = torch.empty_like(E)
+    g.batch_transport_solve(batch, rho, E, nb, out=B)
+    gE = torch.empty_like(E)
+    for rep in range(3):
+        out = g.batch_transport_backward(batch, rho, gB, out=gE)
+        torch.cuda.synchronize()
+        parts = batch.unpack(out[0])
+        gBs = batch.unpack(gB)
+        for x, gEb, gBb in zip(sc, parts, gBs):
+            rh = dev(x["rho"])
+            _, tape = g.transport_solve(x["ff"], rh, dev(x["E"]), nb)
+            gEs, _, _ = g.transport_backward(x["ff"], tape, rh, gBb.contiguous())
+            assert torch.equal(gEb, gEs), rep
+        gB.mul_(-0.5).add_(0.25)                                 # eager work between replays
+        torch.cuda.synchronize()
