@@ -573,3 +573,186 @@ void orc_opacity_backward(const orc_scene *s, const int64_t *recv, int64_t n_rec
         for (int64_t j = 0; j < s->n; ++j) grad_o[j] += part[(size_t)t * (size_t)s->n + j];
     free(part);
 }
+
+/* ------------------------------------------------------------------------
+ * Centre-to-centre form factors (Sec. 8, Eq. radiosity-approx-1, in the
+ * scalar Lambertian form of the transport): for each listed pair (i, j)
+ *   F_ij = lambda_j A_j T_ij |n_i . v| |n_j . v| / (pi |v|^4),  v = p_j - p_i
+ * (|n.w| / r^2 with the unit direction w = v / |v|), A_j the App. E
+ * effective area (given), and T_ij = prod (1 - alpha_k) over every surfel
+ * k != i, j whose support the open segment p_i + t v crosses at
+ * t in (eps, 1 - eps), eps = t_eps / |v| (D_hit decisions, both faces
+ * occlude; alpha from the FP64 intersection).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double t, u, w, gam, c;
+    double h[3];
+} orc_seg_hit;
+
+/* FP64 intersection of the segment o + t d (FP32 o, d) with surfel k. */
+static void seg_hit64(const orc_scene *s, const float o[3], const float d[3], int64_t k, orc_seg_hit *r) {
+    double n[3] = {s->nx[k], s->ny[k], s->nz[k]};
+    double q[3] = {(double)s->px[k] - o[0], (double)s->py[k] - o[1], (double)s->pz[k] - o[2]};
+    double den = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+    double t = (q[0] * n[0] + q[1] * n[1] + q[2] * n[2]) / den;
+    for (int a = 0; a < 3; ++a) r->h[a] = t * d[a] - q[a];
+    r->t = t;
+    r->u = (r->h[0] * s->tux[k] + r->h[1] * s->tuy[k] + r->h[2] * s->tuz[k]) / (double)s->su[k];
+    r->w = (r->h[0] * s->tvx[k] + r->h[1] * s->tvy[k] + r->h[2] * s->tvz[k]) / (double)s->sv[k];
+    r->gam = exp(-1.7 * (r->u * r->u + r->w * r->w));
+    r->c = -log1p(-(double)clamp_opacity(s->op[k]));
+}
+
+/* the segment's occluders (surfels k != i, j) and its transmittance */
+static double segment(const orc_scene *s, int64_t i, int64_t j, float t_eps, orc_hit **buf, int64_t *cap,
+                      int64_t *m_out, float o[3], float d[3], double *len2) {
+    o[0] = s->px[i]; o[1] = s->py[i]; o[2] = s->pz[i];
+    d[0] = s->px[j] - o[0]; d[1] = s->py[j] - o[1]; d[2] = s->pz[j] - o[2];
+    float len = sqrtf(fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0])));
+    *len2 = (double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2];
+    float t_lo = t_eps / len, t_hi = 1.0f - t_lo;
+    int64_t m = collect_hits(s, o, d, i, t_lo, t_hi, 1, buf, cap);
+    int64_t w = 0;
+    for (int64_t q = 0; q < m; ++q)
+        if ((*buf)[q].j != j) (*buf)[w++] = (*buf)[q];
+    *m_out = w;
+    double T = 1.0;
+    for (int64_t q = 0; q < w; ++q) {
+        orc_seg_hit h;
+        seg_hit64(s, o, d, (*buf)[q].j, &h);
+        T *= exp(-h.c * h.gam);
+    }
+    return T;
+}
+
+void orc_center_ff(const orc_scene *s, const int64_t *rows, const int32_t *cols, int64_t m, const double *lambda,
+                   const double *area, float t_eps, double *F_out, double *T_out, int32_t n_threads) {
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel
+    {
+        orc_hit *buf = NULL;
+        int64_t bcap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t e = 0; e < m; ++e) {
+            int64_t i = rows[e], j = cols[e], nh;
+            float o[3], d[3];
+            double len2;
+            double T = segment(s, i, j, t_eps, &buf, &bcap, &nh, o, d, &len2);
+            double a = s->nx[i] * (double)d[0] + s->ny[i] * (double)d[1] + s->nz[i] * (double)d[2];
+            double b = s->nx[j] * (double)d[0] + s->ny[j] * (double)d[1] + s->nz[j] * (double)d[2];
+            F_out[e] = lambda[j] * area[j] * T * fabs(a) * fabs(b) / (ORC_PI * len2 * len2);
+            if (T_out) T_out[e] = T;
+        }
+        free(buf);
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Gradients of L through the centre-to-centre form factors, given
+ * G_e = dL/dF_e for the listed pairs (the decay term of Eq. dl-dgeo-0 with
+ * the decay of Sec. 8): with F = kappa T Phi, kappa = lambda_j A_j / pi,
+ * Phi = |a| |b| / r^4, a = n_i . v, b = n_j . v, v = p_j - p_i,
+ *   dPhi/dp_j = (sgn(a)|b| n_i + |a| sgn(b) n_j) / r^4 - 4 |a||b| v / r^6 = -dPhi/dp_i
+ *   dPhi/dn_i = sgn(a) |b| v / r^4,  dPhi/dn_j = |a| sgn(b) v / r^4
+ *   dF/dlambda_j = A_j T Phi / pi,  dF/dA_j = lambda_j T Phi / pi
+ *   (A_j -> s_u, s_v, o_j through dA/ds_u = A/s_u, dA/do given);
+ * the transmittance, log T = -sum_k c_k gamma_k over the occluders k, with
+ * the segment crossing k's plane at t_k = (q . n_k)/(v . n_k), q = p_k - p_i,
+ * h = t_k v - q, u = h . t_u / s_u, w = h . t_v / s_v, gamma = e^(-1.7 (u^2+w^2)):
+ *   W = G F;  g_h = W 3.4 c gamma (u t_u / s_u + w t_v / s_v);  beta = (g_h . v)/(v . n_k)
+ *   g_q = beta n_k - g_h:  p_k += g_q,  p_i -= (1 - t_k) g_q,  p_j -= t_k g_q
+ *   n_k -= beta h;  t_u,k += W 3.4 c gamma u h / s_u;  t_v,k likewise with w
+ *   s_u,k -= W 3.4 c gamma u^2 / s_u;  s_v,k likewise;  o_k -= W gamma / (1 - o_k)
+ * (opacity terms only where the clamp is inactive).  grads is [n][15]:
+ * px py pz tux tuy tuz tvx tvy tvz nx ny nz su sv o, plus g_lambda [n].
+ * ---------------------------------------------------------------------- */
+void orc_center_backward(const orc_scene *s, const int64_t *rows, const int32_t *cols, int64_t m,
+                         const double *lambda, const double *area, const double *dA_do, float t_eps, const double *G,
+                         double *g_lambda, double *grads, int32_t n_threads) {
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    const int64_t n = s->n;
+    double *part = (double *)calloc((size_t)nth * (size_t)n * 16, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *acc = part + (size_t)tid * (size_t)n * 16;   /* [n][16]: 15 fields, lambda */
+        orc_hit *buf = NULL;
+        int64_t bcap = 0;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t e = 0; e < m; ++e) {
+            int64_t i = rows[e], j = cols[e], nh;
+            float o[3], d[3];
+            double len2;
+            double T = segment(s, i, j, t_eps, &buf, &bcap, &nh, o, d, &len2);
+            double v[3] = {d[0], d[1], d[2]};
+            double ni[3] = {s->nx[i], s->ny[i], s->nz[i]}, nj[3] = {s->nx[j], s->ny[j], s->nz[j]};
+            double a = ni[0] * v[0] + ni[1] * v[1] + ni[2] * v[2];
+            double b = nj[0] * v[0] + nj[1] * v[1] + nj[2] * v[2];
+            double r4 = len2 * len2, r6 = r4 * len2;
+            double Phi = fabs(a) * fabs(b) / r4;
+            double kappa = lambda[j] * area[j] / ORC_PI;
+            double F = kappa * T * Phi;
+            double Ge = G[e];
+            double sa = a > 0 ? 1.0 : (a < 0 ? -1.0 : 0.0), sb = b > 0 ? 1.0 : (b < 0 ? -1.0 : 0.0);
+            double kT = Ge * kappa * T;
+            for (int c = 0; c < 3; ++c) {
+                double dpj = (sa * fabs(b) * ni[c] + fabs(a) * sb * nj[c]) / r4 - 4.0 * fabs(a) * fabs(b) * v[c] / r6;
+                acc[j * 16 + c] += kT * dpj;
+                acc[i * 16 + c] -= kT * dpj;
+                acc[i * 16 + 9 + c] += kT * sa * fabs(b) * v[c] / r4;
+                acc[j * 16 + 9 + c] += kT * fabs(a) * sb * v[c] / r4;
+            }
+            acc[j * 16 + 15] += Ge * area[j] * T * Phi / ORC_PI;
+            double gA = Ge * lambda[j] * T * Phi / ORC_PI;
+            acc[j * 16 + 12] += gA * area[j] / s->su[j];
+            acc[j * 16 + 13] += gA * area[j] / s->sv[j];
+            acc[j * 16 + 14] += gA * dA_do[j];
+            double W = Ge * F;
+            for (int64_t q = 0; q < nh; ++q) {
+                int64_t k = buf[q].j;
+                orc_seg_hit h;
+                seg_hit64(s, o, d, k, &h);
+                double tu[3] = {s->tux[k], s->tuy[k], s->tuz[k]}, tv[3] = {s->tvx[k], s->tvy[k], s->tvz[k]};
+                double nk[3] = {s->nx[k], s->ny[k], s->nz[k]};
+                double su = s->su[k], sv = s->sv[k];
+                double f = W * 3.4 * h.c * h.gam;
+                double gh[3], gq[3];
+                for (int c = 0; c < 3; ++c) gh[c] = f * (h.u * tu[c] / su + h.w * tv[c] / sv);
+                double den = v[0] * nk[0] + v[1] * nk[1] + v[2] * nk[2];
+                double beta = (gh[0] * v[0] + gh[1] * v[1] + gh[2] * v[2]) / den;
+                for (int c = 0; c < 3; ++c) {
+                    gq[c] = beta * nk[c] - gh[c];
+                    acc[k * 16 + c] += gq[c];
+                    acc[i * 16 + c] -= (1.0 - h.t) * gq[c];
+                    acc[j * 16 + c] -= h.t * gq[c];
+                    acc[k * 16 + 9 + c] -= beta * h.h[c];
+                    acc[k * 16 + 3 + c] += f * h.u * h.h[c] / su;
+                    acc[k * 16 + 6 + c] += f * h.w * h.h[c] / sv;
+                }
+                acc[k * 16 + 12] -= f * h.u * h.u / su;
+                acc[k * 16 + 13] -= f * h.w * h.w / sv;
+                float ok = s->op[k];
+                if (ok > 0.0f && ok < ORC_OPACITY_MAX) acc[k * 16 + 14] -= W * h.gam / (1.0 - (double)ok);
+            }
+        }
+        free(buf);
+    }
+    for (int t = 0; t < nth; ++t)
+        for (int64_t k = 0; k < n; ++k) {
+            const double *p = part + ((size_t)t * (size_t)n + (size_t)k) * 16;
+            for (int f = 0; f < 15; ++f) grads[k * 15 + f] += p[f];
+            g_lambda[k] += p[15];
+        }
+    free(part);
+}
