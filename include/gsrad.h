@@ -401,6 +401,51 @@ gsrad_status gsrad_transport_backward_sh(const gsrad_ff *ff, const gsrad_bvh *bv
                                          float *grad_F, void *stream);
 
 /*
+ * Centre-to-centre form factors with a learnable scale (Sec. 8, Eq.
+ * radiosity-approx-1 and the approximated forward rendering equation; the
+ * effective area of App. E), on the pattern of an existing operator
+ * (typically the pairs a ray cast recorded as visible, Sec. 6): for every
+ * stored entry (i, j) of pattern,
+ *   F_ij = lambda_j A_j T_ij |n_i . w| |n_j . w| / (pi r^2),
+ *   w = (p_j - p_i) / r,  r = |p_j - p_i|,
+ * i.e. the scalar Lambertian form V_ji / pi of the paper's decay, with A_j
+ * the App. E area, lambda_j > 0 the per-surfel scale (device float [n]) and
+ * T_ij the product of (1 - alpha) over the surfels other than i and j whose
+ * support the segment between the centres crosses (both faces occlude; the
+ * segment's ends trimmed by the BVH's t_eps; one segment per entry).  The
+ * result is a new F handle (*ff created or refilled; it must differ from
+ * pattern) with pattern's sparsity, usable by every transport call.
+ * Deterministic.  EOVERFLOW: traversal stack overflow.
+ */
+gsrad_status gsrad_ff_center(const gsrad_bvh *bvh, const gsrad_ff *pattern, const float *lambda, gsrad_ff **ff,
+                             void *stream);
+
+/*
+ * Gradients of sum_e grad_F[e] F_e through gsrad_ff_center (the decay term
+ * of Eq. dl-dgeo-0 with the decay of Sec. 8, for every recorded pair), with
+ * respect to lambda and to the surfel fields of the pairs' ends and of every
+ * occluder on their segments: centres, tangent frames (t_u, t_v, n as given,
+ * not renormalised), scales and opacities (0 where the opacity clamp is
+ * active).  Each output is a device float [n], written (not accumulated);
+ * any may be NULL.  The sums are 64-bit fixed point with a per-field
+ * power-of-two scale from the largest contribution (two passes over the
+ * segments), bit-identical between runs.  ff must come from
+ * gsrad_ff_center on this bvh as it is now (EINVAL otherwise).
+ */
+typedef struct gsrad_surfel_grads {
+    float *px, *py, *pz;
+    float *tux, *tuy, *tuz;
+    float *tvx, *tvy, *tvz;
+    float *nx, *ny, *nz;
+    float *su, *sv;
+    float *opacity;
+} gsrad_surfel_grads;
+
+gsrad_status gsrad_ff_center_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *lambda,
+                                      const float *grad_F, float *grad_lambda, const gsrad_surfel_grads *grads,
+                                      void *stream);
+
+/*
  * Opacity and albedo gradients (Eq. dl-dgeo-0, decay term, restricted to
  * opacity; and rho = o a).  For every ray of every receiver i the hits of
  * the forward pass are recomputed and, with G_q = grad_F[i, j_q] / R on

@@ -137,7 +137,7 @@ struct gsrad_bvh {
     int64_t n = 0;               // 0 after a failed (re)build: unusable
     uint64_t gen = 0;            // unique per successful build
     hipStream_t stream = nullptr;
-    DevBuf rec, nodes, leafbox, leaf_parent, inv, cst, opc, opraw, area, bounds, height, temp;
+    DevBuf rec, nodes, leafbox, leaf_parent, inv, cst, opc, opraw, area, dado, bounds, height, temp;
     BvhBuffers B;
     BvhDev dev() const {
         BvhDev d;
@@ -149,11 +149,14 @@ struct gsrad_bvh {
         d.op = B.opc;
         d.raw_op = B.opraw;
         d.bounds = B.bounds;
+        d.area = B.area;
+        d.dado = B.dado;
         d.leaf_box_r = 0.0f;
         return d;
     }
     ~gsrad_bvh() {
-        for (DevBuf *b : {&rec, &nodes, &leafbox, &leaf_parent, &inv, &cst, &opc, &opraw, &area, &bounds, &height, &temp})
+        for (DevBuf *b : {&rec, &nodes, &leafbox, &leaf_parent, &inv, &cst, &opc, &opraw, &area, &dado, &bounds, &height,
+                          &temp})
             b->release();
     }
 };
@@ -171,6 +174,9 @@ struct gsrad_ff {
     // provenance for the opacity backward
     const gsrad_bvh *bvh = nullptr;
     uint64_t bvh_gen = 0;
+    // centre-to-centre values (gsrad_ff_center): the BVH they were made from
+    const gsrad_bvh *center_bvh = nullptr;
+    uint64_t center_gen = 0;
     int R = 0, topk = 0;
     uint64_t seed = 0;
     float t_eps = 0.0f, t_min = 0.0f;
@@ -183,7 +189,7 @@ struct gsrad_ff {
     // scratch of the ray-cast path
     DevBuf slab, ell_col, ell_val, row_len, err, scan_temp, redo;
     // opacity backward: per-XCD fixed-point accumulators and scale
-    DevBuf opac;
+    DevBuf opac, cacc;
     // dense BF16 copies (gsrad_ff_dense): F and F^T, hi and lo parts
     bool has_dense = false;
     int64_t Np = 0;
@@ -211,7 +217,8 @@ struct gsrad_ff {
     }
     ~gsrad_ff() {
         for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col, &redo, &row_order,
-                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl, &opac})
+                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl, &opac,
+                          &cacc})
             b->release();
     }
 };
@@ -334,6 +341,8 @@ void invalidate(gsrad_ff *f) {
     f->has_dense = false;
     f->bvh = nullptr;
     f->bvh_gen = 0;
+    f->center_bvh = nullptr;
+    f->center_gen = 0;
 }
 
 __global__ void k_max_u32(const uint32_t *__restrict__ v, int64_t n, int *out) {
@@ -407,6 +416,7 @@ gsrad_status gsrad_build_bvh(const gsrad_surfels *s, gsrad_bvh **bvh, void *stre
     ENS(opc, n * 4, "clamped opacity");
     ENS(opraw, n * 4, "opacity");
     ENS(area, n * 8, "areas");
+    ENS(dado, n * 4, "area derivatives");
     ENS(bounds, 64, "bounds");
     ENS(height, 64, "height");
     ENS(temp, bvh_temp_bytes(n), "bvh temp");
@@ -422,6 +432,7 @@ gsrad_status gsrad_build_bvh(const gsrad_surfels *s, gsrad_bvh **bvh, void *stre
     B.opc = h->opc.as<float>();
     B.opraw = h->opraw.as<float>();
     B.area = h->area.as<double>();
+    B.dado = h->dado.as<float>();
     B.bounds = h->bounds.as<float>();
     B.height = h->height.as<int>();
     B.temp = h->temp.p;
@@ -1210,6 +1221,93 @@ gsrad_status gsrad_transport_backward_sh(const gsrad_ff *ff, const gsrad_bvh *bv
     if (grad_R) GS_TRY(launch_grad_R(L, tp->Q.as<float>(), n, Lt, K, nb, grad_R, st));
     if (grad_F) GS_TRY(launch_sddmm_sh(bv, ff->csr(), Lt, K, nb, tp->B.as<float>(), L, R, grad_F, st));
     return GSRAD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// centre-to-centre form factors with a learnable scale (Sec. 8)
+// ---------------------------------------------------------------------------
+gsrad_status gsrad_ff_center(const gsrad_bvh *bvh, const gsrad_ff *pattern, const float *lambda, gsrad_ff **ff,
+                             void *stream) {
+    if (!bvh || !pattern || !lambda || !ff) return einval("gsrad_ff_center: null argument");
+    GS_TRY(usable(bvh, "gsrad_ff_center"));
+    GS_TRY(usable(pattern, "gsrad_ff_center"));
+    if (*ff == pattern) return einval("gsrad_ff_center: the output handle must differ from the pattern");
+    if (pattern->n != bvh->n) return einval("gsrad_ff_center: the BVH and the pattern have different sizes");
+    const bool created = *ff == nullptr;
+    gsrad_ff *h = created ? new gsrad_ff() : *ff;
+    invalidate(h);
+    auto fail = [&](gsrad_status e) {
+        if (created) delete h;
+        return e;
+    };
+    hipStream_t st = S(stream);
+    const int64_t n = pattern->n, nnz = pattern->nnz;
+    gsrad_status e;
+    if ((e = h->row_ptr.ensure((size_t)(n + 1) * 8, "row_ptr")) != GSRAD_OK) return fail(e);
+    if ((e = h->col.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "col")) != GSRAD_OK) return fail(e);
+    if ((e = h->val.ensure((size_t)std::max<int64_t>(nnz, 1) * 4, "val")) != GSRAD_OK) return fail(e);
+    if ((e = h->err.ensure(128, "flags")) != GSRAD_OK) return fail(e);
+    if ((e = check_hip(hipMemcpyAsync(h->row_ptr.p, pattern->row_ptr.p, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice,
+                                      st), "copy row_ptr")) != GSRAD_OK)
+        return fail(e);
+    if (nnz > 0 && (e = check_hip(hipMemcpyAsync(h->col.p, pattern->col.p, (size_t)nnz * 4, hipMemcpyDeviceToDevice,
+                                                 st), "copy col")) != GSRAD_OK)
+        return fail(e);
+    if (pattern->has_order) {
+        if ((e = h->row_order.ensure((size_t)n * 4, "row order")) != GSRAD_OK) return fail(e);
+        if ((e = check_hip(hipMemcpyAsync(h->row_order.p, pattern->row_order.p, (size_t)n * 4,
+                                          hipMemcpyDeviceToDevice, st), "copy row order")) != GSRAD_OK)
+            return fail(e);
+    }
+    if ((e = check_hip(hipMemsetAsync(h->err.p, 0, 64, st), "flags")) != GSRAD_OK) return fail(e);
+    h->n = n;
+    h->nnz = nnz;
+    h->has_order = pattern->has_order;
+    Csr P = h->csr();
+    {
+        ProfScope ps("ff_center", st);
+        if ((e = launch_ff_center(bvh->dev(), P, lambda, h->val.as<float>(), h->err.as<int>(), st)) != GSRAD_OK)
+            return fail(e);
+    }
+    int flag = 0;
+    if ((e = check_hip(hipMemcpyAsync(&flag, h->err.p, 4, hipMemcpyDeviceToHost, st), "flags copy")) != GSRAD_OK)
+        return fail(e);
+    if ((e = check_hip(hipStreamSynchronize(st), "ff_center sync")) != GSRAD_OK) return fail(e);
+    if (flag) {
+        invalidate(h);
+        set_error("gsrad_ff_center: traversal stack overflow");
+        if (created) delete h;
+        return GSRAD_EOVERFLOW;
+    }
+    h->max_row = pattern->max_row;
+    h->center_bvh = bvh;
+    h->center_gen = bvh->gen;
+    *ff = h;
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_ff_center_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *lambda,
+                                      const float *grad_F, float *grad_lambda, const gsrad_surfel_grads *grads,
+                                      void *stream) {
+    if (!bvh || !ff || !lambda || !grad_F) return einval("gsrad_ff_center_backward: null argument");
+    GS_TRY(usable(bvh, "gsrad_ff_center_backward"));
+    GS_TRY(usable(ff, "gsrad_ff_center_backward"));
+    if (ff->center_bvh != bvh || ff->center_gen != bvh->gen)
+        return einval("gsrad_ff_center_backward: F was not made by gsrad_ff_center from this BVH as it is now");
+    hipStream_t st = S(stream);
+    gsrad_ff *f = const_cast<gsrad_ff *>(ff);
+    const size_t bytes = center_acc_bytes(ff->n);
+    GS_TRY(f->cacc.ensure(bytes, "centre-to-centre gradient accumulators"));
+    GS_TRY(check_hip(hipMemsetAsync(f->cacc.p, 0, bytes, st), "accumulators zero"));
+    GS_TRY(f->err.ensure(128, "flags"));
+    CenterOutputs out;
+    const gsrad_surfel_grads z{};
+    const gsrad_surfel_grads &g = grads ? *grads : z;
+    float *fields[16] = {g.px, g.py, g.pz, g.tux, g.tuy, g.tuz, g.tvx, g.tvy, g.tvz, g.nx, g.ny, g.nz, g.su, g.sv,
+                         g.opacity, grad_lambda};
+    for (int k = 0; k < 16; ++k) out.p[k] = fields[k];
+    ProfScope ps("ff_center_backward", st);
+    return launch_center_backward(bvh->dev(), ff->csr(), lambda, grad_F, f->cacc.p, out, f->err.as<int>() + 8, st);
 }
 
 gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *grad_F,

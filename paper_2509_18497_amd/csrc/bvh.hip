@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(kThreads) k_records(gsrad_surfels sf, const ui
                                                       const float *__restrict__ bounds, SurfRec *__restrict__ rec,
                                                       float *__restrict__ leafbox, int32_t *__restrict__ inv,
                                                       float *__restrict__ cst, float *__restrict__ opc,
-                                                      float *__restrict__ opraw, double *__restrict__ area) {
+                                                      float *__restrict__ opraw, double *__restrict__ area,
+                                                      float *__restrict__ dado) {
     const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (s >= sf.n) return;
     const int64_t j = order[s];
@@ -154,7 +155,11 @@ __global__ void __launch_bounds__(kThreads) k_records(gsrad_surfels sf, const ui
         term *= -cd / (double)(k + 1);
         if (fabs(add) < 1e-18 * fabs(sum)) break;
     }
-    area[j] = (2.0 * 3.14159265358979323846 / 3.4) * (double)su * (double)sv * sum;
+    const double a0 = (2.0 * 3.14159265358979323846 / 3.4) * (double)su * (double)sv;
+    area[j] = a0 * sum;
+    // dA/do = a0 dEin/dc dc/do = a0 (1 - e^-c)/c / (1 - o), inside the clamp
+    const bool inside = oraw > 0.0f && oraw < kOpacityMax;
+    dado[j] = inside ? (float)(a0 * (cd > 1e-12 ? -expm1(-cd) / cd : 1.0) / (1.0 - (double)o)) : 0.0f;
 }
 
 __device__ __forceinline__ int delta(const uint32_t *__restrict__ keys, int64_t n, int64_t a, int64_t b) {
@@ -327,7 +332,7 @@ gsrad_status bvh_build(const gsrad_surfels &sf, BvhBuffers &B, hipStream_t st) {
     s = radix_sort_pairs(k_in, v_in, k_out, v_out, n, 30, rtemp, rbytes, st);
     if (s != GSRAD_OK) return s;
     hipLaunchKernelGGL(k_records, dim3(nblk(n)), dim3(kThreads), 0, st, sf, v_out, B.bounds, B.rec, B.leafbox, B.inv,
-                       B.cst, B.opc, B.opraw, B.area);
+                       B.cst, B.opc, B.opraw, B.area, B.dado);
     if (n >= 2) {
         hipLaunchKernelGGL(k_karras, dim3(nblk(n - 1)), dim3(kThreads), 0, st, k_out, n, B.nodes, B.leaf_parent);
         s = check_hip(hipMemsetAsync(counter, 0, (size_t)n * sizeof(int), st), "bvh memset");

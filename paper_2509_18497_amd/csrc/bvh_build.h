@@ -17,6 +17,7 @@ struct BvhBuffers {
     float *opc = nullptr;           // [n] clamped opacity
     float *opraw = nullptr;         // [n] opacity as given
     double *area = nullptr;         // [n] App. E effective area
+    float *dado = nullptr;          // [n] d area / d opacity (0 where the clamp is active)
     float *bounds = nullptr;        // [8]
     int *height = nullptr;          // [1] tree height
     void *temp = nullptr;

@@ -52,6 +52,8 @@ struct BvhDev {
     const float *op;         // [n] clamped opacity, original order
     const float *raw_op;     // [n] opacity as given, original order
     const float *bounds;     // [8]: lo.xyz, hi.xyz, t_eps, diag
+    const double *area;      // [n] App. E effective area, original order
+    const float *dado;       // [n] d area / d opacity, original order
     float leaf_box_r;        // unused padding for alignment
 };
 

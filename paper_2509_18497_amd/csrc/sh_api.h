@@ -25,4 +25,17 @@ gsrad_status launch_brdf_backward(const BvhDev &bv, const float *kd, const float
 gsrad_status launch_direct_sh(const BvhDev &bv, const float *R, const float *lpos, const float *lI, int Lt, int K,
                               float *E, int *err, hipStream_t st);
 
+// centre-to-centre form factors on a pattern (trace.hip)
+gsrad_status launch_ff_center(const BvhDev &bv, const Csr &P, const float *lambda, float *val, int *err,
+                              hipStream_t st);
+// gradients: accumulators of center_acc_bytes(n) zeroed first; out holds
+// 16 device output arrays [n] (fields px py pz tux tuy tuz tvx tvy tvz nx
+// ny nz su sv o, then lambda; NULL entries skipped)
+struct CenterOutputs {
+    float *p[16];
+};
+size_t center_acc_bytes(int64_t n);
+gsrad_status launch_center_backward(const BvhDev &bv, const Csr &F, const float *lambda, const float *gF, void *acc,
+                                    const CenterOutputs &out, int *err, hipStream_t st);
+
 }  // namespace gsrad

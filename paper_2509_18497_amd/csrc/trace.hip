@@ -951,6 +951,279 @@ __global__ void __launch_bounds__(256) k_opacity_finish(BvhDev bv, const unsigne
     }
 }
 
+// ---------------------------------------------------------------------------
+// centre-to-centre form factors (Sec. 8) and their gradients
+// ---------------------------------------------------------------------------
+// Every surfel other than skip_a and skip_b whose support the segment
+// o + t d, t in (t_lo, t_hi), crosses (D_hit, both faces occlude);
+// on_hit(record) per crossing, in traversal order.
+template <typename OnHit>
+__device__ __forceinline__ void trace_segment(const BvhDev &bv, float ox, float oy, float oz, float dx, float dy,
+                                              float dz, uint32_t skip_a, uint32_t skip_b, float t_lo, float t_hi,
+                                              uint32_t *stack, int stride, int *err, OnHit &&on_hit) {
+    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    const float t0 = t_lo * 0.99999f, t1 = t_hi * 1.00001f;
+    auto leaf = [&](int s) {
+        const SurfRec r = bv.rec[s];
+        const uint32_t j = __float_as_uint(r.d.w);
+        if (j == skip_a || j == skip_b) return;
+        float t, r2;
+        bool front;
+        if (!hit_test(r, ox, oy, oz, dx, dy, dz, t_lo, t_hi, true, t, r2, front)) return;
+        on_hit(r);
+    };
+    if (bv.n == 1) {
+        leaf(0);
+        return;
+    }
+    int sp = 0, node = 0;
+    for (;;) {
+        const Node nd = bv.nodes[node];
+        float tn0, tn1;
+        bool h0 = slab(nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, ox, oy, oz, ix, iy, iz, t0, t1, tn0);
+        bool h1 = slab(nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, ox, oy, oz, ix, iy, iz, t0, t1, tn1);
+        const int c0 = nd.ch.x, c1 = nd.ch.y;
+        if (h0 && c0 < 0) {
+            leaf(~c0);
+            h0 = false;
+        }
+        if (h1 && c1 < 0) {
+            leaf(~c1);
+            h1 = false;
+        }
+        if (h0 && h1) {
+            if (sp >= kStackDeep) {
+                atomicOr(err, kErrStack);
+                return;
+            }
+            stack[sp * stride] = (uint32_t)c1;
+            ++sp;
+            node = c0;
+        } else if (h0) {
+            node = c0;
+        } else if (h1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = (int)stack[sp * stride];
+        }
+    }
+}
+
+constexpr int kCenterThreads = 128;   // two rows (waves) per workgroup
+constexpr int kCenterFields = 16;     // p(3), t_u(3), t_v(3), n(3), s_u, s_v, o, lambda
+constexpr float kInvPi = 0.318309886183790672f;
+
+struct Segment {
+    float ox, oy, oz, dx, dy, dz, t_lo, t_hi;
+};
+
+// The segment between the centres of ri and rj, its ends trimmed by t_eps
+__device__ __forceinline__ Segment make_segment(const SurfRec &ri, const SurfRec &rj, float t_eps) {
+    Segment g;
+    g.ox = ri.a.x;
+    g.oy = ri.a.y;
+    g.oz = ri.a.z;
+    g.dx = __fsub_rn(rj.a.x, ri.a.x);
+    g.dy = __fsub_rn(rj.a.y, ri.a.y);
+    g.dz = __fsub_rn(rj.a.z, ri.a.z);
+    const float len = sqrt_rn(__builtin_fmaf(g.dz, g.dz, __builtin_fmaf(g.dy, g.dy, __fmul_rn(g.dx, g.dx))));
+    g.t_lo = __fdiv_rn(t_eps, len);
+    g.t_hi = __fsub_rn(1.0f, g.t_lo);
+    return g;
+}
+
+// F_ij = lambda_j A_j T_ij |n_i . v| |n_j . v| / (pi |v|^4) per stored entry
+// of the pattern (v = p_j - p_i); one wave per row, lanes over entries.
+__global__ void __launch_bounds__(kCenterThreads) k_ff_center(BvhDev bv, const int64_t *__restrict__ row_ptr,
+                                                              const int32_t *__restrict__ col, int64_t n,
+                                                              const float *__restrict__ lambda,
+                                                              float *__restrict__ val, int64_t nblocks,
+                                                              const int32_t *__restrict__ order, int *err) {
+    extern __shared__ uint32_t stack_mem[];
+    const int64_t idx = xcd_block(blockIdx.x, nblocks) * (kCenterThreads / 64) + threadIdx.x / 64;
+    if (idx >= n) return;
+    const int64_t row = order ? (int64_t)order[idx] : idx;
+    const int lane = __lane_id();
+    const SurfRec ri = bv.rec[bv.inv[row]];
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    const float t_eps = bv.bounds[6];
+    for (int64_t kk = b + lane; kk < e; kk += 64) {
+        const int32_t j = col[kk];
+        const SurfRec rj = bv.rec[bv.inv[j]];
+        const Segment g = make_segment(ri, rj, t_eps);
+        float T = 1.0f;
+        trace_segment(bv, g.ox, g.oy, g.oz, g.dx, g.dy, g.dz, (uint32_t)row, (uint32_t)j, g.t_lo, g.t_hi,
+                      stack_mem + threadIdx.x, kCenterThreads, err, [&](const SurfRec &r) {
+                          T = __fmul_rn(T, transmit(r.c.w, kernel_gamma(hit_r2_exact(r, g.ox, g.oy, g.oz, g.dx,
+                                                                                     g.dy, g.dz))));
+                      });
+        const float a = ri.b.x * g.dx + ri.b.y * g.dy + ri.b.z * g.dz;
+        const float bb = rj.b.x * g.dx + rj.b.y * g.dy + rj.b.z * g.dz;
+        const float r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
+        const float phi = (fabsf(a) * fabsf(bb)) / (r2 * r2);
+        val[kk] = lambda[j] * (float)bv.area[j] * T * phi * kInvPi;
+    }
+}
+
+// Gradients of sum_e G_e F_e (same decomposition as the oracle's): pass 0
+// finds max |contribution| per field, pass 1 adds the contributions in
+// 64-bit fixed point with a per-field power-of-two scale (integer adds
+// commute: bit-identical between runs) into one copy per XCD.
+template <int PASS>
+struct CenterSink {
+    float m[kCenterFields];
+    unsigned long long *acc;
+    const int *fx;
+    int64_t n;
+    __device__ __forceinline__ void add(int f, uint32_t surfel, float v) {
+        if (PASS == 0) {
+            m[f] = fmaxf(m[f], fabsf(v));
+        } else {
+            fx_add(acc + (int64_t)f * n + surfel, v, __builtin_ldexpf(1.0f, fx[f]));
+        }
+    }
+    __device__ __forceinline__ void add3(int f, uint32_t surfel, float x, float y, float z) {
+        add(f, surfel, x);
+        add(f + 1, surfel, y);
+        add(f + 2, surfel, z);
+    }
+};
+
+template <int PASS>
+__global__ void __launch_bounds__(kCenterThreads) k_center_bwd(BvhDev bv, const int64_t *__restrict__ row_ptr,
+                                                               const int32_t *__restrict__ col,
+                                                               const float *__restrict__ fval, int64_t n,
+                                                               const float *__restrict__ lambda,
+                                                               const float *__restrict__ gF, uint32_t *maxbits,
+                                                               const int *fx, unsigned long long *acc,
+                                                               int64_t nblocks, const int32_t *__restrict__ order,
+                                                               int *err) {
+    extern __shared__ uint32_t stack_mem[];
+    const int64_t idx = xcd_block(blockIdx.x, nblocks) * (kCenterThreads / 64) + threadIdx.x / 64;
+    CenterSink<PASS> sink;
+#pragma unroll
+    for (int f = 0; f < kCenterFields; ++f) sink.m[f] = 0.0f;
+    sink.acc = acc + (int64_t)xcc_id() * kCenterFields * n;
+    sink.fx = fx;
+    sink.n = n;
+    const float t_eps = bv.bounds[6];
+    if (idx < n) {
+        const int64_t row = order ? (int64_t)order[idx] : idx;
+        const uint32_t i = (uint32_t)row;
+        const SurfRec ri = bv.rec[bv.inv[row]];
+        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+        for (int64_t kk = b + __lane_id(); kk < e; kk += 64) {
+            const float G = gF[kk];
+            if (G == 0.0f) continue;
+            const uint32_t j = (uint32_t)col[kk];
+            const SurfRec rj = bv.rec[bv.inv[j]];
+            const Segment g = make_segment(ri, rj, t_eps);
+            const float W = G * fval[kk];
+            float T = 1.0f;
+            float gpi[3] = {0.0f, 0.0f, 0.0f}, gpj[3] = {0.0f, 0.0f, 0.0f};
+            trace_segment(bv, g.ox, g.oy, g.oz, g.dx, g.dy, g.dz, i, j, g.t_lo, g.t_hi, stack_mem + threadIdx.x,
+                          kCenterThreads, err, [&](const SurfRec &r) {
+                              // exact kernel value for T, FP32 geometry for the derivatives
+                              const float gam = kernel_gamma(hit_r2_exact(r, g.ox, g.oy, g.oz, g.dx, g.dy, g.dz));
+                              T = __fmul_rn(T, transmit(r.c.w, gam));
+                              const uint32_t k = __float_as_uint(r.d.w);
+                              const float qx = r.a.x - g.ox, qy = r.a.y - g.oy, qz = r.a.z - g.oz;
+                              const float den = g.dx * r.b.x + g.dy * r.b.y + g.dz * r.b.z;
+                              const float tk = (qx * r.b.x + qy * r.b.y + qz * r.b.z) / den;
+                              const float hx = tk * g.dx - qx, hy = tk * g.dy - qy, hz = tk * g.dz - qz;
+                              const float u = (hx * r.c.x + hy * r.c.y + hz * r.c.z) * r.a.w;
+                              const float w = (hx * r.d.x + hy * r.d.y + hz * r.d.z) * r.b.w;
+                              const float f = W * 3.4f * r.c.w * gam;
+                              const float fu = f * u * r.a.w, fw = f * w * r.b.w;
+                              const float ghx = fu * r.c.x + fw * r.d.x, ghy = fu * r.c.y + fw * r.d.y,
+                                          ghz = fu * r.c.z + fw * r.d.z;
+                              const float beta = (ghx * g.dx + ghy * g.dy + ghz * g.dz) / den;
+                              const float gqx = beta * r.b.x - ghx, gqy = beta * r.b.y - ghy,
+                                          gqz = beta * r.b.z - ghz;
+                              sink.add3(0, k, gqx, gqy, gqz);
+                              sink.add3(3, k, fu * hx, fu * hy, fu * hz);
+                              sink.add3(6, k, fw * hx, fw * hy, fw * hz);
+                              sink.add3(9, k, -beta * hx, -beta * hy, -beta * hz);
+                              sink.add(12, k, -fu * u);
+                              sink.add(13, k, -fw * w);
+                              const float ok = bv.raw_op[k];
+                              if (ok > 0.0f && ok < kOpacityMax) sink.add(14, k, -W * gam / (1.0f - ok));
+                              gpi[0] -= (1.0f - tk) * gqx;
+                              gpi[1] -= (1.0f - tk) * gqy;
+                              gpi[2] -= (1.0f - tk) * gqz;
+                              gpj[0] -= tk * gqx;
+                              gpj[1] -= tk * gqy;
+                              gpj[2] -= tk * gqz;
+                          });
+            // the pair's own terms: Phi = |a| |b| / r^4, kappa = lambda_j A_j / pi
+            const float a = ri.b.x * g.dx + ri.b.y * g.dy + ri.b.z * g.dz;
+            const float bb = rj.b.x * g.dx + rj.b.y * g.dy + rj.b.z * g.dz;
+            const float r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
+            const float r4 = r2 * r2;
+            const float aa = fabsf(a), ab = fabsf(bb);
+            const float sa = a > 0.0f ? 1.0f : (a < 0.0f ? -1.0f : 0.0f);
+            const float sb = bb > 0.0f ? 1.0f : (bb < 0.0f ? -1.0f : 0.0f);
+            const float A = (float)bv.area[j];
+            const float kT = G * lambda[j] * A * T * kInvPi;
+            const float c1 = kT * sa * ab / r4, c2 = kT * aa * sb / r4, c3 = 4.0f * kT * aa * ab / (r4 * r2);
+            const float dpx = c1 * ri.b.x + c2 * rj.b.x - c3 * g.dx;
+            const float dpy = c1 * ri.b.y + c2 * rj.b.y - c3 * g.dy;
+            const float dpz = c1 * ri.b.z + c2 * rj.b.z - c3 * g.dz;
+            sink.add3(0, j, dpx + gpj[0], dpy + gpj[1], dpz + gpj[2]);
+            sink.add3(0, i, gpi[0] - dpx, gpi[1] - dpy, gpi[2] - dpz);
+            sink.add3(9, i, c1 * g.dx, c1 * g.dy, c1 * g.dz);
+            sink.add3(9, j, c2 * g.dx, c2 * g.dy, c2 * g.dz);
+            const float phi = aa * ab / r4;
+            sink.add(15, j, G * A * T * phi * kInvPi);
+            const float gA = G * lambda[j] * T * phi * kInvPi;
+            sink.add(12, j, gA * A * rj.a.w);
+            sink.add(13, j, gA * A * rj.b.w);
+            sink.add(14, j, gA * bv.dado[j]);
+        }
+    }
+    if (PASS == 0) {
+#pragma unroll
+        for (int f = 0; f < kCenterFields; ++f) {
+            float v = sink.m[f];
+            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+            if (__lane_id() == 0 && v > 0.0f) atomicMax(maxbits + f, __float_as_uint(v));
+        }
+    }
+}
+
+// per-field exponent: (max contribution) * count < 2^62, count <= 2 nnz + 2
+__global__ void k_center_exp(const uint32_t *maxbits, int64_t nnz, int *fx) {
+    const int f = threadIdx.x;
+    if (f >= kCenterFields) return;
+    const float m = __uint_as_float(maxbits[f]);
+    int e = 0;
+    if (!(m <= 3.0e38f)) {
+        e = kFxNonFinite;
+    } else if (m > 0.0f) {
+        int ex;
+        (void)frexpf(m * (float)(2 * nnz + 2), &ex);
+        e = min(120, max(-120, 62 - ex));
+    }
+    fx[f] = e;
+}
+
+__global__ void __launch_bounds__(256) k_center_finish(const unsigned long long *__restrict__ acc, const int *fx,
+                                                       int64_t n, CenterOutputs out) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n * kCenterFields) return;
+    const int f = (int)(t / n);
+    const int64_t i = t - (int64_t)f * n;
+    float *o = out.p[f];
+    if (!o) return;
+    unsigned long long s = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) s += acc[((int64_t)x * kCenterFields + f) * n + i];
+    const int e = fx[f];
+    o[i] = e == kFxNonFinite ? __builtin_nanf("") : __builtin_ldexpf(__ll2float_rn((long long)s), -e);
+}
+
 // Composited hit list of every ray of the listed receivers (diagnostics and
 // parity tests): direction, count, and per hit (j, t, front).
 __global__ void __launch_bounds__(256) k_ray_hits(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
@@ -1085,6 +1358,36 @@ gsrad_status launch_opacity_scale(const float *gF, int64_t nnz, int64_t n, void 
 
 static const int *fx_exp_ptr(const BvhDev &bv, const void *acc) {
     return reinterpret_cast<const int *>(static_cast<const char *>(acc) + (size_t)8 * bv.n * 8 + 4);
+}
+
+gsrad_status launch_ff_center(const BvhDev &bv, const Csr &P, const float *lambda, float *val, int *err,
+                              hipStream_t st) {
+    if (P.n == 0) return GSRAD_OK;
+    const int64_t nb = (P.n + 1) / 2;
+    hipLaunchKernelGGL(k_ff_center, dim3((unsigned)nb), dim3(kCenterThreads),
+                       (size_t)kStackDeep * kCenterThreads * sizeof(uint32_t), st, bv, P.row_ptr, P.col, P.n, lambda,
+                       val, nb, P.order, err);
+    return check_hip(hipGetLastError(), "centre-to-centre form factor launch");
+}
+
+size_t center_acc_bytes(int64_t n) { return (size_t)8 * kCenterFields * n * 8 + 256; }
+
+gsrad_status launch_center_backward(const BvhDev &bv, const Csr &F, const float *lambda, const float *gF, void *acc,
+                                    const CenterOutputs &out, int *err, hipStream_t st) {
+    if (F.n == 0) return GSRAD_OK;
+    unsigned long long *a = static_cast<unsigned long long *>(acc);
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(static_cast<char *>(acc) + (size_t)8 * kCenterFields * F.n * 8);
+    int *fx = reinterpret_cast<int *>(maxbits + kCenterFields);
+    const int64_t nb = (F.n + 1) / 2;
+    const size_t smem = (size_t)kStackDeep * kCenterThreads * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_center_bwd<0>, dim3((unsigned)nb), dim3(kCenterThreads), smem, st, bv, F.row_ptr, F.col,
+                       F.val, F.n, lambda, gF, maxbits, fx, a, nb, F.order, err);
+    hipLaunchKernelGGL(k_center_exp, dim3(1), dim3(64), 0, st, maxbits, F.nnz, fx);
+    hipLaunchKernelGGL(k_center_bwd<1>, dim3((unsigned)nb), dim3(kCenterThreads), smem, st, bv, F.row_ptr, F.col,
+                       F.val, F.n, lambda, gF, maxbits, fx, a, nb, F.order, err);
+    const int64_t tot = F.n * kCenterFields;
+    hipLaunchKernelGGL(k_center_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, fx, F.n, out);
+    return check_hip(hipGetLastError(), "centre-to-centre backward launch");
 }
 
 gsrad_status launch_direct_sh(const BvhDev &bv, const float *R, const float *lpos, const float *lI, int Lt, int K,

@@ -28,7 +28,7 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
            "gsrad_transport_solve_noalloc", "gsrad_brdf_reflectance", "gsrad_brdf_backward",
            "gsrad_direct_light_sh", "gsrad_transport_solve_sh", "gsrad_transport_backward_sh",
-           "gsrad_batch_set_lanes",
+           "gsrad_batch_set_lanes", "gsrad_ff_center", "gsrad_ff_center_backward",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
@@ -43,6 +43,10 @@ class GsradError(RuntimeError):
 
 class _Surfels(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in SOA] + [("n", ctypes.c_int64)]
+
+
+class _SurfelGrads(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in SOA]
 
 
 class _FFParams(ctypes.Structure):
@@ -85,6 +89,8 @@ def lib():
             "gsrad_batch_transport_solve": ([vp, vp, vp, i32, vp, vp], i32),
             "gsrad_batch_transport_backward": ([vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_batch_set_lanes": ([vp, i32, i32], i32),
+            "gsrad_ff_center": ([vp, vp, vp, pvp, vp], i32),
+            "gsrad_ff_center_backward": ([vp, vp, vp, vp, vp, ctypes.POINTER(_SurfelGrads), vp], i32),
             "gsrad_tape_grad_F_dense": ([vp, vp, vp], i32),
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
@@ -332,6 +338,29 @@ def batch_transport_backward(batch: Batch, rho: torch.Tensor, grad_B: torch.Tens
                                                 _ptr(grad_F) if grad_F is not None else None, _stream(stream)),
            "gsrad_batch_transport_backward")
     return grad_E, grad_rho, (grad_F[:nnz] if grad_F is not None else None)
+
+
+def ff_center(bvh: BVH, pattern: FF, lam: torch.Tensor, ff: Optional[FF] = None, stream=None) -> FF:
+    """Centre-to-centre form factors lambda_j A_j T_ij |n_i.w||n_j.w| / (pi r^2)
+    on pattern's entries (Sec. 8)."""
+    out = ff if ff is not None else FF()
+    _check(lib().gsrad_ff_center(bvh.h, pattern.h, _ptr(lam, name="lambda"), ctypes.byref(out.h), _stream(stream)),
+           "gsrad_ff_center")
+    return out
+
+
+def ff_center_backward(bvh: BVH, ff: FF, lam: torch.Tensor, grad_F: torch.Tensor, stream=None):
+    """(dL/dlambda [n], {field: dL/dfield [n]} for the 15 surfel fields) of
+    sum grad_F * F through ff_center."""
+    n = bvh.n
+    dev = torch.device("cuda")
+    out = {f: torch.empty(n, dtype=torch.float32, device=dev) for f in SOA}
+    gl = torch.empty(n, dtype=torch.float32, device=dev)
+    sg = _SurfelGrads(*[out[f].data_ptr() for f in SOA])
+    gF = grad_F if grad_F.numel() > 0 else torch.zeros(1, dtype=torch.float32, device=dev)
+    _check(lib().gsrad_ff_center_backward(bvh.h, ff.h, _ptr(lam, name="lambda"), _ptr(gF, name="grad_F"), _ptr(gl),
+                                          ctypes.byref(sg), _stream(stream)), "gsrad_ff_center_backward")
+    return gl, out
 
 
 def ff_dense(ff: FF, stream=None) -> FF:
