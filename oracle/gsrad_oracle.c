@@ -756,3 +756,143 @@ void orc_center_backward(const orc_scene *s, const int64_t *rows, const int32_t 
         }
     free(part);
 }
+
+/* ------------------------------------------------------------------------
+ * Geometry gradients through the ray-cast form factors (Eq. dl-dgeo-0, the
+ * decay term with the recorded pairs, for every surfel field).  For
+ * receiver i and ray r (origin p_i, direction d = x t_u,i + y t_v,i + z n_i
+ * from the ray's disc sample) with composited hits q on surfels k_q, the
+ * F-part of the loss is sum_q G_q alpha_q T_q (G_q = gF[i, k_q] / R on front
+ * hits kept in F), so with the compositing backward's dL/dalpha_q:
+ *   alpha = 1 - e^(-c gamma):  dL/dgamma = dL/dalpha c (1 - alpha),
+ *   dL/dc = dL/dalpha gamma (1 - alpha) -> o_k: / (1 - o_k) inside the clamp
+ *   gamma = e^(-1.7 (u^2 + w^2)), u = h . t_u / s_u, w = h . t_v / s_v,
+ *   h = t d - q, q = p_k - p_i, t = (q . n_k)/(d . n_k):
+ *   g_h = dL/dgamma (-3.4 gamma) (u t_u / s_u + w t_v / s_v),
+ *   beta = (g_h . d)/(d . n_k), g_q = beta n_k - g_h:
+ *     p_k += g_q, p_i -= g_q, n_k -= beta h,
+ *     d += -t g_q  ->  t_u,i += x (-t g_q), t_v,i += y (-t g_q), n_i += z (-t g_q)
+ *     t_u,k += dL/du h / s_u, s_u,k -= dL/du u / s_u (likewise v).
+ * The hit set, its order and the cut are those of the forward pass.
+ * grads [n][15]: px py pz tux tuy tuz tvx tvy tvz nx ny nz su sv o.
+ * ---------------------------------------------------------------------- */
+static void ray_sample(const orc_scene *s, int64_t i, uint64_t r, uint64_t seed, float xyz[3]) {
+    for (uint64_t a = 0; a < ORC_RAY_MAX_ATTEMPTS; ++a) {
+        uint64_t ctr[4] = {r, (uint64_t)i, a, 0}, key[2] = {seed, 0}, w[4];
+        orc_philox4x64_10(ctr, key, w);
+        for (int p = 0; p < 2; ++p) {
+            float x = (float)(uint32_t)(w[2 * p] >> 40) * 0x1p-23f - 1.0f;
+            float y = (float)(uint32_t)(w[2 * p + 1] >> 40) * 0x1p-23f - 1.0f;
+            float s2 = x * x + y * y;
+            if (s2 < 1.0f) {
+                xyz[0] = x; xyz[1] = y; xyz[2] = sqrtf(1.0f - s2);
+                return;
+            }
+        }
+    }
+    xyz[0] = 0.0f; xyz[1] = 0.0f; xyz[2] = 1.0f;
+}
+
+void orc_geometry_backward(const orc_scene *s, const int64_t *recv, int64_t n_recv, const int64_t *gptr,
+                           const int32_t *gcol, const double *gval, int32_t R, uint64_t seed, float t_eps,
+                           float t_min, double *grads, int32_t n_threads) {
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    const int64_t n = s->n;
+    double *part = (double *)calloc((size_t)nth * (size_t)n * 15, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *acc = part + (size_t)tid * (size_t)n * 15;
+        double *G = (double *)calloc((size_t)n, sizeof(double));
+        orc_hit *buf = NULL;
+        int64_t bcap = 0;
+        double *a = NULL, *T = NULL, *gw = NULL;
+        int64_t acap = 0;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t kr = 0; kr < n_recv; ++kr) {
+            int64_t i = recv[kr];
+            for (int64_t e = gptr[kr]; e < gptr[kr + 1]; ++e) G[gcol[e]] = gval[e] / (double)R;
+            float o[3] = {s->px[i], s->py[i], s->pz[i]};
+            for (int32_t r = 0; r < R; ++r) {
+                float d[3], xyz[3];
+                orc_ray_direction(s, i, (uint64_t)r, seed, 0, d);
+                ray_sample(s, i, (uint64_t)r, seed, xyz);
+                int64_t m = collect_hits(s, o, d, i, t_eps, 0.0f, 0, &buf, &bcap);
+                if (m > acap) {
+                    acap = m;
+                    a = (double *)realloc(a, (size_t)acap * sizeof(double));
+                    T = (double *)realloc(T, (size_t)acap * sizeof(double));
+                    gw = (double *)realloc(gw, (size_t)acap * sizeof(double));
+                }
+                double Tc = 1.0;
+                float T32 = 1.0f;
+                int64_t mc = 0;
+                for (int64_t q = 0; q < m; ++q) {
+                    int64_t k = buf[q].j;
+                    orc_seg_hit h;
+                    seg_hit64(s, o, d, k, &h);
+                    a[q] = -expm1(-h.c * h.gam);
+                    T[q] = Tc;
+                    gw[q] = buf[q].front ? G[k] * a[q] * Tc : 0.0;
+                    Tc *= exp(-h.c * h.gam);
+                    T32 = T32 * stop_factor(s, o, d, &buf[q]);
+                    mc = q + 1;
+                    if (T32 < t_min) break;
+                }
+                double suffix = 0.0;
+                for (int64_t q = mc - 1; q >= 0; --q) {
+                    int64_t k = buf[q].j;
+                    double Gq = buf[q].front ? G[k] : 0.0;
+                    double dLda = Gq * T[q] - suffix / (1.0 - a[q]);
+                    suffix += gw[q];
+                    orc_seg_hit h;
+                    seg_hit64(s, o, d, k, &h);
+                    double dLdg = dLda * h.c * (1.0 - a[q]);
+                    float ok = s->op[k];
+                    if (ok > 0.0f && ok < ORC_OPACITY_MAX)
+                        acc[k * 15 + 14] += dLda * h.gam * (1.0 - a[q]) / (1.0 - (double)ok);
+                    double su = s->su[k], sv = s->sv[k];
+                    double du = dLdg * (-3.4 * h.gam) * h.u, dw = dLdg * (-3.4 * h.gam) * h.w;
+                    double tu[3] = {s->tux[k], s->tuy[k], s->tuz[k]}, tv[3] = {s->tvx[k], s->tvy[k], s->tvz[k]};
+                    double nk[3] = {s->nx[k], s->ny[k], s->nz[k]};
+                    double gh[3], gq[3];
+                    for (int c = 0; c < 3; ++c) gh[c] = du * tu[c] / su + dw * tv[c] / sv;
+                    double den = d[0] * nk[0] + d[1] * nk[1] + d[2] * nk[2];
+                    double beta = (gh[0] * d[0] + gh[1] * d[1] + gh[2] * d[2]) / den;
+                    for (int c = 0; c < 3; ++c) {
+                        gq[c] = beta * nk[c] - gh[c];
+                        acc[k * 15 + c] += gq[c];
+                        acc[i * 15 + c] -= gq[c];
+                        acc[k * 15 + 9 + c] -= beta * h.h[c];
+                        acc[k * 15 + 3 + c] += du * h.h[c] / su;
+                        acc[k * 15 + 6 + c] += dw * h.h[c] / sv;
+                        double gd = -h.t * gq[c];
+                        acc[i * 15 + 3 + c] += xyz[0] * gd;
+                        acc[i * 15 + 6 + c] += xyz[1] * gd;
+                        acc[i * 15 + 9 + c] += xyz[2] * gd;
+                    }
+                    acc[k * 15 + 12] -= du * h.u / su;
+                    acc[k * 15 + 13] -= dw * h.w / sv;
+                }
+            }
+            for (int64_t e = gptr[kr]; e < gptr[kr + 1]; ++e) G[gcol[e]] = 0.0;
+        }
+        free(G);
+        free(buf);
+        free(a);
+        free(T);
+        free(gw);
+    }
+    for (int t = 0; t < nth; ++t)
+        for (size_t k = 0; k < (size_t)n * 15; ++k) grads[k] += part[(size_t)t * (size_t)n * 15 + k];
+    free(part);
+}

@@ -71,6 +71,7 @@ def lib():
         L.orc_opacity_backward.argtypes = [P(_Scene), P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_int64),
                                            P(ctypes.c_int32), P(ctypes.c_double), ctypes.c_int32, ctypes.c_uint64,
                                            ctypes.c_float, ctypes.c_float, P(ctypes.c_double), ctypes.c_int32]
+        L.orc_geometry_backward.argtypes = L.orc_opacity_backward.argtypes
         _lib = L
     return _lib
 
@@ -376,3 +377,30 @@ def opacity_backward(surfels, albedo, R: int, seed: int, t_eps: float, t_min: fl
         go += np.where(inside, (np.asarray(grad_rho) * alb).sum(axis=1), 0.0)
         ga = np.asarray(grad_rho, np.float64) * clamp_opacity(o).astype(np.float64)[:, None]
     return go, ga
+
+
+GEOMETRY_FIELDS = ("px", "py", "pz", "tux", "tuy", "tuz", "tvx", "tvy", "tvz", "nx", "ny", "nz", "su", "sv",
+                   "opacity")
+
+
+def geometry_backward(surfels, R: int, seed: int, t_eps: float, t_min: float, gF_rows, receivers=None,
+                      n_threads: Optional[int] = None):
+    """Gradients of sum G F (ray-cast F of the listed receivers, G given as
+    CSR rows over them) with respect to every surfel field: the decay term
+    of Eq. dl-dgeo-0 through the compositing weights of the recorded hits,
+    the hit points' dependence on the hit surfel's centre, frame and scales,
+    and on the receiver's centre and frame (ray origin and direction).
+    Returns {field: gradient [n]}."""
+    sc = _SceneRef(surfels)
+    n = sc.n
+    recv = np.ascontiguousarray(np.arange(n, dtype=np.int64) if receivers is None else np.asarray(receivers, np.int64))
+    gp, gc, gv = gF_rows
+    gp = np.ascontiguousarray(np.asarray(gp, np.int64))
+    gc = np.ascontiguousarray(np.asarray(gc, np.int32))
+    gv = np.ascontiguousarray(np.asarray(gv, np.float64))
+    out = np.zeros(n * 15)
+    lib().orc_geometry_backward(sc.ref, _ptr(recv, ctypes.c_int64), recv.shape[0], _ptr(gp, ctypes.c_int64),
+                                _ptr(gc, ctypes.c_int32), _ptr(gv, ctypes.c_double), int(R), int(seed),
+                                float(t_eps), float(t_min), _ptr(out, ctypes.c_double), _nthreads(n_threads))
+    out = out.reshape(n, 15)
+    return {f: out[:, k] for k, f in enumerate(GEOMETRY_FIELDS)}

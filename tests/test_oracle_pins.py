@@ -684,3 +684,69 @@ def test_fp32_hit_decisions_against_fp64_at_workload_scale(orc, name, n, receive
     assert n_rays == receivers * rays and n_hits > 10 * n_rays
     if name == "fruit_bowl":
         assert moved <= 1e-4 * mass
+
+
+# ---------------------------------------------------------------------------
+# geometry gradients through the ray-cast form factors (Eq. dl-dgeo-0)
+# ---------------------------------------------------------------------------
+def _layers_scene():
+    """Four small receivers on z = 0 under three broad, tilted,
+    semi-transparent layers (one facing up: it only occludes); the layers are
+    so large that the rays cross them far inside their support."""
+    p, nrm, s, o = [], [], [], []
+    for k, tilt in enumerate([0.0, 0.15, -0.1, 0.25]):
+        p.append([0.2 * k, 0.1 * (k % 2), 0.0])
+        nrm.append([math.sin(tilt), 0.05 * k, math.cos(tilt)])
+        s.append(0.02)
+        o.append(0.9)
+    for z, nn, op in [(0.3, [0.1, -0.2, -1.0], 0.45), (0.6, [-0.2, 0.1, 1.0], 0.35), (0.95, [0.15, 0.1, -1.0], 0.6)]:
+        p.append([0.3, 0.05, z])
+        nrm.append(nn)
+        s.append(6.0)
+        o.append(op)
+    nrm = np.array(nrm, float)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    tu, tv = scenes.onb_from_normal(nrm)
+    ang = np.linspace(0.2, 1.3, len(p))
+    tu2 = np.cos(ang)[:, None] * tu + np.sin(ang)[:, None] * tv
+    tv2 = -np.sin(ang)[:, None] * tu + np.cos(ang)[:, None] * tv
+    return scenes.surfels_from_arrays(np.array(p, float), nrm, tu2, tv2, s, np.array(s) * 1.1, o)
+
+
+def test_geometry_gradients_through_ray_cast_form_factors_match_central_differences(orc):
+    """dL/d(every surfel field) of L = sum_ij G_ij F_ij (ray-cast F, no
+    compositing cut) against central differences of the oracle's own form
+    factors; steps are the actual FP32 changes of the perturbed inputs."""
+    sur = _layers_scene()
+    n = sur["px"].shape[0]
+    recv = np.arange(4)
+    R, seed, te = 48, 21, 1e-6
+    rp, co, vo, _ = orc.ff_rows(sur, recv, R, seed, te, 0.0, 0)
+    rng = np.random.default_rng(6)
+    Gd = rng.standard_normal((4, n))
+    gv = Gd[np.repeat(np.arange(4), np.diff(rp)), co]
+    grads = orc.geometry_backward(sur, R, seed, te, 0.0, (rp, co, gv), receivers=recv)
+
+    def L(s_):
+        rp_, co_, vo_, _ = orc.ff_rows(s_, recv, R, seed, te, 0.0, 0)
+        return float(np.sum(Gd[np.repeat(np.arange(4), np.diff(rp_)), co_] * vo_))
+
+    # the opacity part equals the compositing backward's
+    go, _ = orc.opacity_backward(sur, np.zeros((n, 3)), R, seed, te, 0.0, (rp, co, gv), receivers=recv)
+    assert np.allclose(grads["opacity"], go, rtol=1e-12, atol=1e-15)
+    scale = max(np.max(np.abs(v)) for v in grads.values())
+    checked = 0
+    for f in orc.GEOMETRY_FIELDS:
+        for k in range(n):
+            x0 = np.float32(sur[f][k])
+            step = np.float32(max(abs(float(x0)), 0.05) * 1e-3)
+            sp_, sm_ = dict(sur), dict(sur)
+            sp_[f] = sur[f].copy()
+            sm_[f] = sur[f].copy()
+            sp_[f][k] = np.float32(x0 + step)
+            sm_[f][k] = np.float32(x0 - step)
+            d = float(sp_[f][k]) - float(sm_[f][k])
+            fd = (L(sp_) - L(sm_)) / d
+            assert abs(fd - grads[f][k]) <= 2e-3 * (abs(fd) + 1e-3 * scale), (f, k, fd, grads[f][k])
+            checked += 1
+    assert checked == 15 * n
