@@ -446,6 +446,24 @@ gsrad_status gsrad_ff_center_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, 
                                       void *stream);
 
 /*
+ * Geometry gradients through the ray-cast form factors (Eq. dl-dgeo-0, the
+ * decay term over the recorded pairs, Sec. 6): for grad_F = dL/dF [nnz] in
+ * F's CSR order, the gradient of sum_e grad_F[e] F_e with respect to every
+ * surfel field of the hit surfels (the hit point u, v on each through its
+ * centre, frame and scales; its opacity through c) and of the receivers
+ * (ray origin p_i, ray direction x t_u + y t_v + z n_i from the ray's disc
+ * sample), with the compositing backward's dL/dalpha per recorded hit; the
+ * hit sets, their order and the cut are those of the forward pass.  The
+ * opacity output is the F part of gsrad_opacity_backward's (without the
+ * receiver term).  Outputs device float [n] each (written; NULL skipped).
+ * Needs the per-ray hit records (GSRAD_ESTATE without them).  64-bit fixed
+ * point sums with per-field scales from a first pass: bit-identical between
+ * runs.
+ */
+gsrad_status gsrad_geometry_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *grad_F,
+                                     const gsrad_surfel_grads *grads, void *stream);
+
+/*
  * Opacity and albedo gradients (Eq. dl-dgeo-0, decay term, restricted to
  * opacity; and rho = o a).  For every ray of every receiver i the hits of
  * the forward pass are recomputed and, with G_q = grad_F[i, j_q] / R on

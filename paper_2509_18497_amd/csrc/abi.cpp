@@ -1310,6 +1310,40 @@ gsrad_status gsrad_ff_center_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, 
     return launch_center_backward(bvh->dev(), ff->csr(), lambda, grad_F, f->cacc.p, out, f->err.as<int>() + 8, st);
 }
 
+gsrad_status gsrad_geometry_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *grad_F,
+                                     const gsrad_surfel_grads *grads, void *stream) {
+    if (!bvh || !ff || !grad_F || !grads) return einval("gsrad_geometry_backward: null argument");
+    GS_TRY(usable(bvh, "gsrad_geometry_backward"));
+    GS_TRY(usable(ff, "gsrad_geometry_backward"));
+    if (ff->bvh != bvh || ff->bvh_gen != bvh->gen || ff->n != bvh->n)
+        return einval("gsrad_geometry_backward: the F handle was not made by gsrad_form_factors from this BVH as it "
+                      "is now");
+    if (!ff->has_records) {
+        set_error("gsrad_geometry_backward: needs the per-ray hit records (cast F without GSRAD_FF_NO_RECORDS "
+                  "and within the record budget)");
+        return GSRAD_ESTATE;
+    }
+    hipStream_t st = S(stream);
+    gsrad_ff *f = const_cast<gsrad_ff *>(ff);
+    const size_t bytes = center_acc_bytes(ff->n);
+    GS_TRY(f->cacc.ensure(bytes, "geometry gradient accumulators"));
+    GS_TRY(check_hip(hipMemsetAsync(f->cacc.p, 0, bytes, st), "accumulators zero"));
+    const gsrad_surfel_grads &g = *grads;
+    CenterOutputs out;
+    float *fields[16] = {g.px, g.py, g.pz, g.tux, g.tuy, g.tuz, g.tvx, g.tvy, g.tvz, g.nx, g.ny, g.nz, g.su, g.sv,
+                         g.opacity, nullptr};
+    for (int k = 0; k < 16; ++k) out.p[k] = fields[k];
+    if (f->nnz == 0) {
+        for (int k = 0; k < 15; ++k)
+            if (fields[k]) GS_TRY(check_hip(hipMemsetAsync(fields[k], 0, (size_t)ff->n * 4, st), "zero gradient"));
+        return GSRAD_OK;
+    }
+    ProfScope ps("geometry_backward", st);
+    return launch_geometry_rec(bvh->dev(), f->R, f->seed, f->recs.as<uint2>(), f->rcnt.as<uint32_t>(), f->rec_cap,
+                               f->row_ptr.as<int64_t>(), f->col.as<int32_t>(), grad_F, std::max(f->max_row, 1),
+                               f->cacc.p, out, st);
+}
+
 gsrad_status gsrad_opacity_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *grad_F,
                                     const float *grad_rho, const float *albedo, float *grad_opacity,
                                     float *grad_albedo, void *stream) {

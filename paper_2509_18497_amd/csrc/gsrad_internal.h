@@ -123,6 +123,31 @@ __device__ __forceinline__ int ray_direction(float tux, float tuy, float tuz, fl
     return kRayMaxAttempts;
 }
 
+// The disc sample (x, y) and z = sqrt(1 - x^2 - y^2) behind ray_direction's
+// direction d = x t_u + y t_v + z n (same draws and roundings).
+__device__ __forceinline__ void ray_sample(uint64_t ray, uint64_t recv, uint64_t seed, uint64_t tag, float &x_out,
+                                           float &y_out, float &z_out) {
+    for (int a = 0; a < kRayMaxAttempts; ++a) {
+        uint64_t w[4];
+        philox4x64_10(ray, recv, (uint64_t)a, tag, seed, 0ULL, w);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const float x = __fsub_rn(__fmul_rn((float)(uint32_t)(w[2 * p] >> 40), 0x1p-23f), 1.0f);
+            const float y = __fsub_rn(__fmul_rn((float)(uint32_t)(w[2 * p + 1] >> 40), 0x1p-23f), 1.0f);
+            const float s2 = __fadd_rn(__fmul_rn(x, x), __fmul_rn(y, y));
+            if (s2 < 1.0f) {
+                x_out = x;
+                y_out = y;
+                z_out = sqrt_rn(__fsub_rn(1.0f, s2));
+                return;
+            }
+        }
+    }
+    x_out = 0.0f;
+    y_out = 0.0f;
+    z_out = 1.0f;
+}
+
 // Hit decision (FP32, fixed order).  Returns true and (t, r2, front) when
 // the ray o + t d crosses surfel `s` with t_lo < t (< t_hi if bounded) and
 // u^2 + v^2 <= 9.

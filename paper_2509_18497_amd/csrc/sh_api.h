@@ -38,4 +38,10 @@ size_t center_acc_bytes(int64_t n);
 gsrad_status launch_center_backward(const BvhDev &bv, const Csr &F, const float *lambda, const float *gF, void *acc,
                                     const CenterOutputs &out, int *err, hipStream_t st);
 
+// geometry gradients through the ray-cast F from the recorded hits
+// (accumulators of center_acc_bytes(n) zeroed first; out.p[0..14])
+gsrad_status launch_geometry_rec(const BvhDev &bv, int R, uint64_t seed, const uint2 *recs, const uint32_t *rcnt,
+                                 int rcap, const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row,
+                                 void *acc, const CenterOutputs &out, hipStream_t st);
+
 }  // namespace gsrad

@@ -1224,6 +1224,150 @@ __global__ void __launch_bounds__(256) k_center_finish(const unsigned long long 
     o[i] = e == kFxNonFinite ? __builtin_nanf("") : __builtin_ldexpf(__ll2float_rn((long long)s), -e);
 }
 
+// ---------------------------------------------------------------------------
+// geometry gradients through the ray-cast form factors (recorded hits)
+// ---------------------------------------------------------------------------
+// The compositing backward's dL/dalpha per recorded hit (as k_opacity_rec)
+// chained to the hit surfel's centre, frame, scales and opacity and to the
+// receiver's centre and frame (ray origin p_i, direction
+// d = x t_u + y t_v + z n): alpha = 1 - e^(-c gamma), gamma = e^(-1.7 (u^2+w^2)),
+// u = h . t_u / s_u, w = h . t_v / s_v, h = t d - q, q = p_k - p_i,
+// t = (q . n_k)/(d . n_k).  The hit point is the FP64 intersection.  Sums in
+// 64-bit fixed point with per-field scales from a first pass (bit-identical
+// between runs), one copy per XCD; fields px..o as in CenterOutputs.
+template <int PASS>
+__global__ void __launch_bounds__(256) k_geometry_rec(BvhDev bv, int R, uint64_t seed, const uint2 *__restrict__ recs,
+                                                      const uint32_t *__restrict__ rcnt, int rcap, int64_t nblocks,
+                                                      const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col, const float *__restrict__ gF,
+                                                      int log2h, uint32_t *maxbits, const int *fx,
+                                                      unsigned long long *acc) {
+    extern __shared__ uint32_t sm4[];
+    const int H = 1 << log2h;
+    uint32_t *hk = sm4;
+    float *hv = reinterpret_cast<float *>(sm4 + H);
+    const int64_t b = xcd_block(blockIdx.x, nblocks);
+    const int tid = threadIdx.x;
+    const SurfRec ri = bv.rec[b];
+    const uint32_t i = __float_as_uint(ri.d.w);
+    for (int k = tid; k < H; k += blockDim.x) hk[k] = kEmpty;
+    __syncthreads();
+    const int64_t e0 = row_ptr[i];
+    const int len = (int)(row_ptr[i + 1] - e0);
+    const float invR = 1.0f / (float)R;
+    for (int k = tid; k < len; k += blockDim.x) {
+        const uint32_t j = (uint32_t)col[e0 + k];
+        uint32_t h = hash_slot(j, log2h);
+        while (atomicCAS(&hk[h], kEmpty, j) != kEmpty) h = (h + 1) & (uint32_t)(H - 1);
+        hv[h] = gF[e0 + k] * invR;
+    }
+    __syncthreads();
+    CenterSink<PASS> sink;
+#pragma unroll
+    for (int f = 0; f < kCenterFields; ++f) sink.m[f] = 0.0f;
+    sink.acc = acc + (int64_t)xcc_id() * kCenterFields * bv.n;
+    sink.fx = fx;
+    sink.n = bv.n;
+    for (int r = tid; r < R; r += blockDim.x) {
+        const uint32_t m = rcnt[(int64_t)i * R + r];
+        if (m > (uint32_t)rcap) continue;
+        const uint2 *in = recs + (int64_t)i * rcap * R + r;
+        DF W{0.0f, 0.0f};
+        float T = 1.0f;
+        for (uint32_t q = 0; q < m; ++q) {
+            const uint2 h = in[(int64_t)q * R];
+            const float gs = __uint_as_float(h.y);
+            const float x = bv.c[h.x] * fabsf(gs);
+            if (gs > 0.0f) {
+                const float G = row_hash_lookup(hk, hv, log2h, h.x);
+                if (G != 0.0f) W = df_add(W, df_prod3(G, -expm1f(-x), T));
+            }
+            T = __fmul_rn(T, exp_fx(-x));
+        }
+        if (W.hi == 0.0f) continue;
+        float dx, dy, dz, sx, sy, sz;
+        ray_direction(ri.c.x, ri.c.y, ri.c.z, ri.d.x, ri.d.y, ri.d.z, ri.b.x, ri.b.y, ri.b.z, (uint64_t)r,
+                      (uint64_t)i, seed, 0, dx, dy, dz);
+        ray_sample((uint64_t)r, (uint64_t)i, seed, 0, sx, sy, sz);
+        float gd[3] = {0.0f, 0.0f, 0.0f}, gpi[3] = {0.0f, 0.0f, 0.0f};
+        DF P{0.0f, 0.0f};
+        T = 1.0f;
+        for (uint32_t q = 0; q < m; ++q) {
+            const uint2 h = in[(int64_t)q * R];
+            const float gs = __uint_as_float(h.y);
+            const float g = fabsf(gs);
+            const uint32_t k = h.x;
+            const float c = bv.c[k];
+            const float x = c * g;
+            const float f = exp_fx(-x);
+            const float alpha = -expm1f(-x);
+            const float G = gs > 0.0f ? row_hash_lookup(hk, hv, log2h, k) : 0.0f;
+            if (G != 0.0f) P = df_add(P, df_prod3(G, alpha, T));
+            const DF Sd = df_add(W, DF{-P.hi, -P.lo});
+            const float dLda = G * T - Sd.hi / f;
+            T = __fmul_rn(T, f);
+            if (dLda == 0.0f) continue;
+            const float ok = bv.raw_op[k];
+            if (ok > 0.0f && ok < kOpacityMax) sink.add(14, k, dLda * g * f / (1.0f - ok));
+            // the FP64 hit point of the FP32 ray on k's plane
+            const SurfRec rk = bv.rec[bv.inv[k]];
+            const double nx = rk.b.x, ny = rk.b.y, nz = rk.b.z;
+            const double qx = (double)rk.a.x - ri.a.x, qy = (double)rk.a.y - ri.a.y, qz = (double)rk.a.z - ri.a.z;
+            const double den = (double)dx * nx + (double)dy * ny + (double)dz * nz;
+            const double tk = (qx * nx + qy * ny + qz * nz) / den;
+            const float hx = (float)(tk * dx - qx), hy = (float)(tk * dy - qy), hz = (float)(tk * dz - qz);
+            const float u = (hx * rk.c.x + hy * rk.c.y + hz * rk.c.z) * rk.a.w;
+            const float w = (hx * rk.d.x + hy * rk.d.y + hz * rk.d.z) * rk.b.w;
+            const float dLdg = dLda * c * f;
+            const float du = dLdg * (-3.4f) * g * u * rk.a.w, dw = dLdg * (-3.4f) * g * w * rk.b.w;
+            const float ghx = du * rk.c.x + dw * rk.d.x, ghy = du * rk.c.y + dw * rk.d.y, ghz = du * rk.c.z + dw * rk.d.z;
+            const float beta = (ghx * dx + ghy * dy + ghz * dz) / (float)den;
+            const float gqx = beta * rk.b.x - ghx, gqy = beta * rk.b.y - ghy, gqz = beta * rk.b.z - ghz;
+            sink.add3(0, k, gqx, gqy, gqz);
+            sink.add3(3, k, du * hx, du * hy, du * hz);
+            sink.add3(6, k, dw * hx, dw * hy, dw * hz);
+            sink.add3(9, k, -beta * hx, -beta * hy, -beta * hz);
+            sink.add(12, k, -du * u);
+            sink.add(13, k, -dw * w);
+            const float tf = (float)tk;
+            gpi[0] -= gqx;
+            gpi[1] -= gqy;
+            gpi[2] -= gqz;
+            gd[0] -= tf * gqx;
+            gd[1] -= tf * gqy;
+            gd[2] -= tf * gqz;
+        }
+        sink.add3(0, i, gpi[0], gpi[1], gpi[2]);
+        sink.add3(3, i, sx * gd[0], sx * gd[1], sx * gd[2]);
+        sink.add3(6, i, sy * gd[0], sy * gd[1], sy * gd[2]);
+        sink.add3(9, i, sz * gd[0], sz * gd[1], sz * gd[2]);
+    }
+    if (PASS == 0) {
+#pragma unroll
+        for (int f = 0; f < kCenterFields; ++f) {
+            float v = sink.m[f];
+            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+            if (__lane_id() == 0 && v > 0.0f) atomicMax(maxbits + f, __float_as_uint(v));
+        }
+    }
+}
+
+// per-field exponent for the recorded hits: count <= n R + n
+__global__ void k_geometry_exp(const uint32_t *maxbits, int64_t count, int *fx) {
+    const int f = threadIdx.x;
+    if (f >= kCenterFields) return;
+    const float m = __uint_as_float(maxbits[f]);
+    int e = 0;
+    if (!(m <= 3.0e38f)) {
+        e = kFxNonFinite;
+    } else if (m > 0.0f) {
+        int ex;
+        (void)frexpf(m * (float)count, &ex);
+        e = min(120, max(-120, 62 - ex));
+    }
+    fx[f] = e;
+}
+
 // Composited hit list of every ray of the listed receivers (diagnostics and
 // parity tests): direction, count, and per hit (j, t, front).
 __global__ void __launch_bounds__(256) k_ray_hits(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
@@ -1388,6 +1532,39 @@ gsrad_status launch_center_backward(const BvhDev &bv, const Csr &F, const float 
     const int64_t tot = F.n * kCenterFields;
     hipLaunchKernelGGL(k_center_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, fx, F.n, out);
     return check_hip(hipGetLastError(), "centre-to-centre backward launch");
+}
+
+gsrad_status launch_geometry_rec(const BvhDev &bv, int R, uint64_t seed, const uint2 *recs, const uint32_t *rcnt,
+                                 int rcap, const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row,
+                                 void *acc, const CenterOutputs &out, hipStream_t st) {
+    const int threads = R >= 256 ? 256 : ((R + 63) / 64) * 64;
+    int log2h = 4;
+    while ((1 << log2h) < 2 * max_row) ++log2h;
+    const size_t smem = (size_t)(1 << log2h) * 8;
+    if (smem > 150 * 1024) {
+        set_error("geometry backward: row of %d entries is too long for the LDS row table", max_row);
+        return GSRAD_EINVAL;
+    }
+    static bool attr_set = false;
+    if (!attr_set) {
+        for (const void *fn : {reinterpret_cast<const void *>(&k_geometry_rec<0>),
+                               reinterpret_cast<const void *>(&k_geometry_rec<1>)})
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+        attr_set = true;
+    }
+    unsigned long long *a = static_cast<unsigned long long *>(acc);
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(static_cast<char *>(acc) + (size_t)8 * kCenterFields * bv.n * 8);
+    int *fx = reinterpret_cast<int *>(maxbits + kCenterFields);
+    hipLaunchKernelGGL(k_geometry_rec<0>, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, seed, recs, rcnt, rcap,
+                       bv.n, row_ptr, col, gF, log2h, maxbits, fx, a);
+    hipLaunchKernelGGL(k_geometry_exp, dim3(1), dim3(64), 0, st, maxbits, bv.n * (int64_t)R + bv.n, fx);
+    hipLaunchKernelGGL(k_geometry_rec<1>, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, seed, recs, rcnt, rcap,
+                       bv.n, row_ptr, col, gF, log2h, maxbits, fx, a);
+    CenterOutputs o15 = out;
+    o15.p[15] = nullptr;
+    const int64_t tot = bv.n * kCenterFields;
+    hipLaunchKernelGGL(k_center_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, fx, bv.n, o15);
+    return check_hip(hipGetLastError(), "geometry backward launch");
 }
 
 gsrad_status launch_direct_sh(const BvhDev &bv, const float *R, const float *lpos, const float *lI, int Lt, int K,

@@ -29,6 +29,7 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_transport_solve_noalloc", "gsrad_brdf_reflectance", "gsrad_brdf_backward",
            "gsrad_direct_light_sh", "gsrad_transport_solve_sh", "gsrad_transport_backward_sh",
            "gsrad_batch_set_lanes", "gsrad_ff_center", "gsrad_ff_center_backward",
+           "gsrad_geometry_backward",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
@@ -91,6 +92,7 @@ def lib():
             "gsrad_batch_set_lanes": ([vp, i32, i32], i32),
             "gsrad_ff_center": ([vp, vp, vp, pvp, vp], i32),
             "gsrad_ff_center_backward": ([vp, vp, vp, vp, vp, ctypes.POINTER(_SurfelGrads), vp], i32),
+            "gsrad_geometry_backward": ([vp, vp, vp, ctypes.POINTER(_SurfelGrads), vp], i32),
             "gsrad_tape_grad_F_dense": ([vp, vp, vp], i32),
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
@@ -361,6 +363,18 @@ def ff_center_backward(bvh: BVH, ff: FF, lam: torch.Tensor, grad_F: torch.Tensor
     _check(lib().gsrad_ff_center_backward(bvh.h, ff.h, _ptr(lam, name="lambda"), _ptr(gF, name="grad_F"), _ptr(gl),
                                           ctypes.byref(sg), _stream(stream)), "gsrad_ff_center_backward")
     return gl, out
+
+
+def geometry_backward(bvh: BVH, ff: FF, grad_F: torch.Tensor, stream=None) -> Dict[str, torch.Tensor]:
+    """{field: dL/dfield [n]} for the 15 surfel fields through the ray-cast F
+    (from its recorded hits) for dL/dF = grad_F."""
+    n = bvh.n
+    out = {f: torch.empty(n, dtype=torch.float32, device="cuda") for f in SOA}
+    sg = _SurfelGrads(*[out[f].data_ptr() for f in SOA])
+    gF = grad_F if grad_F.numel() > 0 else torch.zeros(1, dtype=torch.float32, device="cuda")
+    _check(lib().gsrad_geometry_backward(bvh.h, ff.h, _ptr(gF, name="grad_F"), ctypes.byref(sg), _stream(stream)),
+           "gsrad_geometry_backward")
+    return out
 
 
 def ff_dense(ff: FF, stream=None) -> FF:
