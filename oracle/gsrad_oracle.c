@@ -896,3 +896,120 @@ void orc_geometry_backward(const orc_scene *s, const int64_t *recv, int64_t n_re
         for (size_t k = 0; k < (size_t)n * 15; ++k) grads[k] += part[(size_t)t * (size_t)n * 15 + k];
     free(part);
 }
+
+/* ------------------------------------------------------------------------
+ * Gradients of the direct light (Eq. forward rendering equation, direct
+ * illumination) with respect to the lights' positions and intensities, the
+ * albedo, and the surfel fields of the receivers and of the occluders on the
+ * shadow segments (Sec. 9's light-position optimisation): with v = x_l - p_i,
+ * r = |v|, ndot = n_i . v > 0,
+ *   E_i,l,00,c = o_i a_i,c kappa I_l ndot T_il / r^3,  kappa = 2/sqrt(pi),
+ *   S = sum_c dL/dE_i,l,00,c a_i,c,  Q = S o_i kappa I_l T_il:
+ *   dL/dI_l += S o_i kappa ndot T / r^3,  dL/da_i,c += dL/dE_c o_i kappa I ndot T / r^3,
+ *   dL/do_i += S kappa I ndot T / r^3 (inside the clamp),
+ *   g_v = Q (n_i / r^3 - 3 ndot v / r^5):  x_l += g_v,  p_i -= g_v,  n_i += Q v / r^3,
+ * and the transmittance as for a centre-to-centre segment with W = S o kappa I ndot T / r^3
+ * (the light in the role of the far end).  grads [n][15] as in
+ * orc_geometry_backward, g_lpos [Lt][3], g_lI [Lt], g_alb [n][3].
+ * ---------------------------------------------------------------------- */
+void orc_direct_light_backward(const orc_scene *s, const float *albedo, const float *lpos, const float *lI,
+                               int32_t Lt, int32_t K, float t_eps, const double *gE, double *g_lpos, double *g_lI,
+                               double *g_alb, double *grads, int32_t n_threads) {
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    const int64_t n = s->n;
+    const size_t per = (size_t)n * 15 + (size_t)Lt * 4;
+    double *part = (double *)calloc((size_t)nth * per, sizeof(double));
+    const double kappa = 2.0 / sqrt(ORC_PI);
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *acc = part + (size_t)tid * per;
+        double *accl = acc + (size_t)n * 15;
+        orc_hit *buf = NULL;
+        int64_t bcap = 0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < n; ++i) {
+            float o[3] = {s->px[i], s->py[i], s->pz[i]};
+            double oc = (double)clamp_opacity(s->op[i]);
+            float oraw = s->op[i];
+            for (int32_t l = 0; l < Lt; ++l) {
+                float d[3] = {lpos[3 * l + 0] - o[0], lpos[3 * l + 1] - o[1], lpos[3 * l + 2] - o[2]};
+                double v[3] = {d[0], d[1], d[2]};
+                double r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                double ni[3] = {s->nx[i], s->ny[i], s->nz[i]};
+                double ndot = ni[0] * v[0] + ni[1] * v[1] + ni[2] * v[2];
+                if (!(ndot > 0.0) || !(r2 > 0.0)) continue;
+                double r = sqrt(r2), r3 = r2 * r, r5 = r3 * r2;
+                float len = sqrtf(fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0])));
+                float t_lo = t_eps / len;
+                int64_t m = collect_hits(s, o, d, i, t_lo, 1.0f, 1, &buf, &bcap);
+                double T = 1.0;
+                for (int64_t q = 0; q < m; ++q) {
+                    orc_seg_hit h;
+                    seg_hit64(s, o, d, buf[q].j, &h);
+                    T *= exp(-h.c * h.gam);
+                }
+                const double *ge = gE + (((size_t)i * Lt + l) * K) * 3;
+                double S = 0.0;
+                for (int c = 0; c < 3; ++c) S += ge[c] * (double)albedo[3 * i + c];
+                double base = kappa * (double)lI[l] * ndot * T / r3;
+                accl[(size_t)Lt * 3 + l] += S * oc * kappa * ndot * T / r3;
+                for (int c = 0; c < 3; ++c) g_alb[3 * i + c] += ge[c] * oc * base;   /* row i is this thread's */
+                if (oraw > 0.0f && oraw < ORC_OPACITY_MAX) acc[i * 15 + 14] += S * base;
+                double Q = S * oc * kappa * (double)lI[l] * T;
+                for (int c = 0; c < 3; ++c) {
+                    double gv = Q * (ni[c] / r3 - 3.0 * ndot * v[c] / r5);
+                    accl[3 * l + c] += gv;
+                    acc[i * 15 + c] -= gv;
+                    acc[i * 15 + 9 + c] += Q * v[c] / r3;
+                }
+                double W = S * oc * base;
+                for (int64_t q = 0; q < m; ++q) {
+                    int64_t k = buf[q].j;
+                    orc_seg_hit h;
+                    seg_hit64(s, o, d, k, &h);
+                    double tu[3] = {s->tux[k], s->tuy[k], s->tuz[k]}, tv[3] = {s->tvx[k], s->tvy[k], s->tvz[k]};
+                    double nk[3] = {s->nx[k], s->ny[k], s->nz[k]};
+                    double su = s->su[k], sv = s->sv[k];
+                    double f = W * 3.4 * h.c * h.gam;
+                    double gh[3], gq[3];
+                    for (int c = 0; c < 3; ++c) gh[c] = f * (h.u * tu[c] / su + h.w * tv[c] / sv);
+                    double den = v[0] * nk[0] + v[1] * nk[1] + v[2] * nk[2];
+                    double beta = (gh[0] * v[0] + gh[1] * v[1] + gh[2] * v[2]) / den;
+                    for (int c = 0; c < 3; ++c) {
+                        gq[c] = beta * nk[c] - gh[c];
+                        acc[k * 15 + c] += gq[c];
+                        acc[i * 15 + c] -= (1.0 - h.t) * gq[c];
+                        accl[3 * l + c] -= h.t * gq[c];
+                        acc[k * 15 + 9 + c] -= beta * h.h[c];
+                        acc[k * 15 + 3 + c] += f * h.u * h.h[c] / su;
+                        acc[k * 15 + 6 + c] += f * h.w * h.h[c] / sv;
+                    }
+                    acc[k * 15 + 12] -= f * h.u * h.u / su;
+                    acc[k * 15 + 13] -= f * h.w * h.w / sv;
+                    float ok = s->op[k];
+                    if (ok > 0.0f && ok < ORC_OPACITY_MAX) acc[k * 15 + 14] -= W * h.gam / (1.0 - (double)ok);
+                }
+            }
+        }
+        free(buf);
+    }
+    for (int t = 0; t < nth; ++t) {
+        const double *p = part + (size_t)t * per;
+        for (size_t k = 0; k < (size_t)n * 15; ++k) grads[k] += p[k];
+        for (int32_t l = 0; l < Lt; ++l) {
+            for (int c = 0; c < 3; ++c) g_lpos[3 * l + c] += p[(size_t)n * 15 + 3 * l + c];
+            g_lI[l] += p[(size_t)n * 15 + (size_t)Lt * 3 + l];
+        }
+    }
+    free(part);
+}

@@ -72,6 +72,10 @@ def lib():
                                            P(ctypes.c_int32), P(ctypes.c_double), ctypes.c_int32, ctypes.c_uint64,
                                            ctypes.c_float, ctypes.c_float, P(ctypes.c_double), ctypes.c_int32]
         L.orc_geometry_backward.argtypes = L.orc_opacity_backward.argtypes
+        L.orc_direct_light_backward.argtypes = [P(_Scene), P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float),
+                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P(ctypes.c_double),
+                                                P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                                                P(ctypes.c_double), ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -404,3 +408,30 @@ def geometry_backward(surfels, R: int, seed: int, t_eps: float, t_min: float, gF
                                 float(t_eps), float(t_min), _ptr(out, ctypes.c_double), _nthreads(n_threads))
     out = out.reshape(n, 15)
     return {f: out[:, k] for k, f in enumerate(GEOMETRY_FIELDS)}
+
+
+def direct_light_backward(surfels, albedo, light_pos, light_I, grad_E, t_eps: Optional[float] = None,
+                          n_threads: Optional[int] = None):
+    """Gradients of sum(grad_E * E) through ``direct_light`` (DC part):
+    (dL/dlight_pos [Lt, 3], dL/dlight_I [Lt], dL/dalbedo [n, 3],
+    {field: dL/dfield [n]} for the receivers' and occluders' surfel fields)."""
+    sc = _SceneRef(surfels)
+    n = sc.n
+    if t_eps is None:
+        t_eps = default_t_eps(surfels)
+    lp = np.ascontiguousarray(np.asarray(light_pos, np.float32).reshape(-1, 3))
+    li = np.ascontiguousarray(np.asarray(light_I, np.float32).reshape(-1))
+    alb = np.ascontiguousarray(np.asarray(albedo, np.float32).reshape(-1, 3))
+    Lt = lp.shape[0]
+    gE = np.ascontiguousarray(np.asarray(grad_E, np.float64))
+    K = gE.shape[2]
+    g_lp = np.zeros(Lt * 3)
+    g_li = np.zeros(Lt)
+    g_alb = np.zeros(n * 3)
+    gr = np.zeros(n * 15)
+    lib().orc_direct_light_backward(sc.ref, _ptr(alb, ctypes.c_float), _ptr(lp, ctypes.c_float),
+                                    _ptr(li, ctypes.c_float), Lt, int(K), float(t_eps), _ptr(gE, ctypes.c_double),
+                                    _ptr(g_lp, ctypes.c_double), _ptr(g_li, ctypes.c_double),
+                                    _ptr(g_alb, ctypes.c_double), _ptr(gr, ctypes.c_double), _nthreads(n_threads))
+    gr = gr.reshape(n, 15)
+    return g_lp.reshape(Lt, 3), g_li, g_alb.reshape(n, 3), {f: gr[:, k] for k, f in enumerate(GEOMETRY_FIELDS)}

@@ -750,3 +750,52 @@ def test_geometry_gradients_through_ray_cast_form_factors_match_central_differen
             assert abs(fd - grads[f][k]) <= 2e-3 * (abs(fd) + 1e-3 * scale), (f, k, fd, grads[f][k])
             checked += 1
     assert checked == 15 * n
+
+
+def test_direct_light_gradients_match_central_differences(orc):
+    """Light positions and intensities, albedo, receivers' and occluders'
+    surfel fields through the direct light (with shadowing), against central
+    differences of the oracle's own direct light."""
+    sur = _layers_scene()
+    n = sur["px"].shape[0]
+    alb = np.random.default_rng(8).uniform(0.2, 0.8, (n, 3)).astype(np.float32)
+    lp = np.array([[0.4, 0.2, 1.6], [-0.3, 0.4, 1.3]], np.float32)
+    lI = np.array([3.0, 1.5], np.float32)
+    te = 1e-6
+    K = 4
+    gE = np.random.default_rng(9).standard_normal((n, 2, K, 3))
+    g_lp, g_li, g_alb, grads = orc.direct_light_backward(sur, alb, lp, lI, gE, t_eps=te)
+
+    def L(s_=sur, alb_=alb, lp_=lp, li_=lI):
+        return float(np.sum(gE * orc.direct_light(s_, alb_, lp_, li_, K, te)))
+
+    def fd_of(arr, idx, call):
+        x0 = np.float32(arr[idx])
+        step = np.float32(max(abs(float(x0)), 0.05) * 1e-3)
+        ap, am = arr.copy(), arr.copy()
+        ap[idx] = np.float32(x0 + step)
+        am[idx] = np.float32(x0 - step)
+        return (call(ap) - call(am)) / (float(ap[idx]) - float(am[idx]))
+
+    scale = max(np.max(np.abs(g_lp)), max(np.max(np.abs(v)) for v in grads.values()))
+    for l in range(2):
+        for c in range(3):
+            fd = fd_of(lp, (l, c), lambda a: L(lp_=a))
+            assert abs(fd - g_lp[l, c]) <= 2e-3 * (abs(fd) + 1e-3 * scale), ("light", l, c)
+        fd = fd_of(lI, l, lambda a: L(li_=a))
+        assert abs(fd - g_li[l]) <= 1e-5 * abs(fd)
+    for i in range(n):
+        for c in range(3):
+            fd = fd_of(alb, (i, c), lambda a: L(alb_=a))
+            assert abs(fd - g_alb[i, c]) <= 1e-5 * (abs(fd) + 1e-6)
+    checked = 0
+    for f in orc.GEOMETRY_FIELDS:
+        for k in range(n):
+            def call(a, f=f):
+                s_ = dict(sur)
+                s_[f] = a
+                return L(s_=s_)
+            fd = fd_of(sur[f], k, call)
+            assert abs(fd - grads[f][k]) <= 2e-3 * (abs(fd) + 1e-3 * scale), (f, k, fd, grads[f][k])
+            checked += 1
+    assert checked == 15 * n
