@@ -464,6 +464,23 @@ gsrad_status gsrad_geometry_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, c
                                      const gsrad_surfel_grads *grads, void *stream);
 
 /*
+ * Gradients through gsrad_direct_light (Eq. forward rendering equation,
+ * direct illumination; the light-position optimisation of Sec. 9) for
+ * grad_E = dL/dE [n][Lt][K][3] (only its DC coefficients matter): with
+ * v = x_l - p_i, r = |v|, E_c = o_i a_c (2/sqrt(pi)) I_l max(0, n_i . v) T_il / r^3,
+ * the gradients with respect to the light positions grad_light_pos
+ * [Lt][3], intensities grad_light_I [Lt], the albedo grad_albedo [n][3],
+ * and the surfel fields of the receivers (centre, normal, opacity) and of
+ * every occluder on the shadow segments (as in gsrad_ff_center_backward),
+ * in grads.  Every output is written (NULL skipped).  Fixed-point sums with
+ * per-field scales from a first pass: bit-identical between runs.
+ */
+gsrad_status gsrad_direct_light_backward(const gsrad_bvh *bvh, const float *albedo, const float *light_pos,
+                                         const float *light_I, int32_t n_lights, int32_t K, const float *grad_E,
+                                         float *grad_light_pos, float *grad_light_I, float *grad_albedo,
+                                         const gsrad_surfel_grads *grads, void *stream);
+
+/*
  * Opacity and albedo gradients (Eq. dl-dgeo-0, decay term, restricted to
  * opacity; and rho = o a).  For every ray of every receiver i the hits of
  * the forward pass are recomputed and, with G_q = grad_F[i, j_q] / R on

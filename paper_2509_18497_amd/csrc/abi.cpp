@@ -137,7 +137,7 @@ struct gsrad_bvh {
     int64_t n = 0;               // 0 after a failed (re)build: unusable
     uint64_t gen = 0;            // unique per successful build
     hipStream_t stream = nullptr;
-    DevBuf rec, nodes, leafbox, leaf_parent, inv, cst, opc, opraw, area, dado, bounds, height, temp;
+    DevBuf rec, nodes, leafbox, leaf_parent, inv, cst, opc, opraw, area, dado, bounds, height, temp, lacc;
     BvhBuffers B;
     BvhDev dev() const {
         BvhDev d;
@@ -156,7 +156,7 @@ struct gsrad_bvh {
     }
     ~gsrad_bvh() {
         for (DevBuf *b : {&rec, &nodes, &leafbox, &leaf_parent, &inv, &cst, &opc, &opraw, &area, &dado, &bounds, &height,
-                          &temp})
+                          &temp, &lacc})
             b->release();
     }
 };
@@ -1308,6 +1308,31 @@ gsrad_status gsrad_ff_center_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, 
     for (int k = 0; k < 16; ++k) out.p[k] = fields[k];
     ProfScope ps("ff_center_backward", st);
     return launch_center_backward(bvh->dev(), ff->csr(), lambda, grad_F, f->cacc.p, out, f->err.as<int>() + 8, st);
+}
+
+gsrad_status gsrad_direct_light_backward(const gsrad_bvh *bvh, const float *albedo, const float *light_pos,
+                                         const float *light_I, int32_t n_lights, int32_t K, const float *grad_E,
+                                         float *grad_light_pos, float *grad_light_I, float *grad_albedo,
+                                         const gsrad_surfel_grads *grads, void *stream) {
+    if (!bvh || !albedo || !light_pos || !light_I || !grad_E) return einval("gsrad_direct_light_backward: null argument");
+    GS_TRY(usable(bvh, "gsrad_direct_light_backward"));
+    if (n_lights < 1) return einval("gsrad_direct_light_backward: n_lights must be >= 1");
+    if (!valid_K(K)) return einval("gsrad_direct_light_backward: K must be 1, 4, 9 or 16");
+    hipStream_t st = S(stream);
+    gsrad_bvh *h = const_cast<gsrad_bvh *>(bvh);
+    const size_t bytes = light_acc_bytes(bvh->n, n_lights);
+    GS_TRY(h->lacc.ensure(bytes, "direct light gradient accumulators"));
+    GS_TRY(check_hip(hipMemsetAsync(h->lacc.p, 0, bytes, st), "accumulators zero"));
+    GS_TRY(h->height.ensure(64, "flags"));
+    const gsrad_surfel_grads z{};
+    const gsrad_surfel_grads &g = grads ? *grads : z;
+    CenterOutputs out;
+    float *fields[16] = {g.px, g.py, g.pz, g.tux, g.tuy, g.tuz, g.tvx, g.tvy, g.tvz, g.nx, g.ny, g.nz, g.su, g.sv,
+                         g.opacity, nullptr};
+    for (int k = 0; k < 16; ++k) out.p[k] = fields[k];
+    ProfScope ps("direct_light_backward", st);
+    return launch_direct_backward(bvh->dev(), albedo, light_pos, light_I, n_lights, K, grad_E, h->lacc.p,
+                                  grad_light_pos, grad_light_I, grad_albedo, out, h->height.as<int>() + 12, st);
 }
 
 gsrad_status gsrad_geometry_backward(const gsrad_bvh *bvh, const gsrad_ff *ff, const float *grad_F,

@@ -44,4 +44,11 @@ gsrad_status launch_geometry_rec(const BvhDev &bv, int R, uint64_t seed, const u
                                  int rcap, const int64_t *row_ptr, const int32_t *col, const float *gF, int max_row,
                                  void *acc, const CenterOutputs &out, hipStream_t st);
 
+// direct-light gradients (accumulators of light_acc_bytes(n, Lt) zeroed
+// first; out.p[0..14] surfel fields)
+size_t light_acc_bytes(int64_t n, int Lt);
+gsrad_status launch_direct_backward(const BvhDev &bv, const float *albedo, const float *lpos, const float *lI, int Lt,
+                                    int K, const float *gE, void *acc, float *g_lpos, float *g_lI, float *g_alb,
+                                    const CenterOutputs &out, int *err, hipStream_t st);
+
 }  // namespace gsrad

@@ -1368,6 +1368,197 @@ __global__ void k_geometry_exp(const uint32_t *maxbits, int64_t count, int *fx) 
     fx[f] = e;
 }
 
+// ---------------------------------------------------------------------------
+// direct-light gradients: light positions and intensities, albedo, surfel
+// fields of the receivers and of the occluders on the shadow segments
+// ---------------------------------------------------------------------------
+// One thread per receiver, lights in turn.  With v = x_l - p_i, r = |v|,
+// ndot = n_i . v > 0, E_c = o a_c kappa I ndot T / r^3 (kappa = 2/sqrt(pi)),
+// S = sum_c dL/dE_c a_c, Q = S o kappa I T:
+//   dL/dI += S o kappa ndot T / r^3, dL/da_c += dL/dE_c o kappa I ndot T / r^3,
+//   dL/do_i += S kappa I ndot T / r^3, g_v = Q (n/r^3 - 3 ndot v/r^5):
+//   x_l += g_v, p_i -= g_v, n_i += Q v / r^3,
+// and the shadow segment's occluders as for a centre-to-centre segment with
+// W = S o kappa I ndot T / r^3.  Fields 0..14 surfel (px..o), 15..18 the
+// light (x, y, z, I) in their own accumulators; fixed point as above.
+constexpr int kLightFields = 19;
+
+template <int PASS>
+struct LightSink {
+    float m[kLightFields];
+    unsigned long long *acc;     // surfel fields [16][n] of this XCD
+    unsigned long long *lacc;    // light fields [4][Lt] of this XCD
+    const int *fx;
+    int64_t n;
+    int Lt;
+    __device__ __forceinline__ void add(int f, uint32_t surfel, float v) {
+        if (PASS == 0) m[f] = fmaxf(m[f], fabsf(v));
+        else fx_add(acc + (int64_t)f * n + surfel, v, __builtin_ldexpf(1.0f, fx[f]));
+    }
+    __device__ __forceinline__ void add3(int f, uint32_t surfel, float x, float y, float z) {
+        add(f, surfel, x);
+        add(f + 1, surfel, y);
+        add(f + 2, surfel, z);
+    }
+};
+
+template <int PASS>
+__global__ void __launch_bounds__(128) k_direct_bwd(BvhDev bv, const float *__restrict__ albedo,
+                                                    const float *__restrict__ lpos, const float *__restrict__ lI,
+                                                    int Lt, int K, const float *__restrict__ gE, uint32_t *maxbits,
+                                                    const int *fx, unsigned long long *acc, unsigned long long *lacc,
+                                                    float *__restrict__ g_alb, int *err) {
+    extern __shared__ uint32_t stack_mem[];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    LightSink<PASS> sink;
+#pragma unroll
+    for (int f = 0; f < kLightFields; ++f) sink.m[f] = 0.0f;
+    const int xcc = xcc_id();
+    sink.acc = acc + (int64_t)xcc * kCenterFields * bv.n;
+    sink.lacc = lacc + (int64_t)xcc * 4 * Lt;
+    sink.fx = fx;
+    sink.n = bv.n;
+    sink.Lt = Lt;
+    const bool live = i < bv.n;
+    const SurfRec rr = live ? bv.rec[bv.inv[i]] : bv.rec[0];
+    const float oc = live ? bv.op[i] : 0.0f;
+    const float oraw = live ? bv.raw_op[i] : 0.0f;
+    const bool inside = oraw > 0.0f && oraw < kOpacityMax;
+    float ga[3] = {0.0f, 0.0f, 0.0f};
+    const float a0 = live ? albedo[3 * i] : 0.0f, a1 = live ? albedo[3 * i + 1] : 0.0f,
+                a2 = live ? albedo[3 * i + 2] : 0.0f;
+    for (int l = 0; l < Lt; ++l) {
+        float gl[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float *ge = gE + ((i * Lt + l) * K) * 3;
+        const float S = live ? ge[0] * a0 + ge[1] * a1 + ge[2] * a2 : 0.0f;
+        const float dx = __fsub_rn(lpos[3 * l + 0], rr.a.x);
+        const float dy = __fsub_rn(lpos[3 * l + 1], rr.a.y);
+        const float dz = __fsub_rn(lpos[3 * l + 2], rr.a.z);
+        const float dd = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __fmul_rn(dx, dx)));
+        const float ndot = rr.b.x * dx + rr.b.y * dy + rr.b.z * dz;
+        if (live && ndot > 0.0f && dd > 0.0f && S != 0.0f) {
+            const float len = sqrt_rn(dd);
+            const float t_lo = __fdiv_rn(bv.bounds[6], len);
+            const float r3 = dd * len, r5 = r3 * dd;
+            // the transmittance first (the occluders' weight W needs it)
+            float T = 1.0f;
+            trace_segment(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, (uint32_t)i, (uint32_t)i, t_lo, 1.0f,
+                          stack_mem + threadIdx.x, blockDim.x, err, [&](const SurfRec &r) {
+                              T = __fmul_rn(T, transmit(r.c.w, kernel_gamma(hit_r2_exact(r, rr.a.x, rr.a.y, rr.a.z,
+                                                                                         dx, dy, dz))));
+                          });
+            const float kI = 1.1283791670955126f * lI[l];
+            const float base = kI * ndot * T / r3;
+            gl[3] = S * oc * 1.1283791670955126f * ndot * T / r3;
+            ga[0] += ge[0] * oc * base;
+            ga[1] += ge[1] * oc * base;
+            ga[2] += ge[2] * oc * base;
+            if (inside) sink.add(14, (uint32_t)i, S * base);
+            const float Q = S * oc * kI * T;
+            const float gvx = Q * (rr.b.x / r3 - 3.0f * ndot * dx / r5);
+            const float gvy = Q * (rr.b.y / r3 - 3.0f * ndot * dy / r5);
+            const float gvz = Q * (rr.b.z / r3 - 3.0f * ndot * dz / r5);
+            float gpi[3] = {-gvx, -gvy, -gvz};
+            gl[0] = gvx;
+            gl[1] = gvy;
+            gl[2] = gvz;
+            sink.add3(9, (uint32_t)i, Q * dx / r3, Q * dy / r3, Q * dz / r3);
+            const float W = S * oc * base;
+            trace_segment(bv, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz, (uint32_t)i, (uint32_t)i, t_lo, 1.0f,
+                          stack_mem + threadIdx.x, blockDim.x, err, [&](const SurfRec &r) {
+                              const float gam = kernel_gamma(hit_r2_exact(r, rr.a.x, rr.a.y, rr.a.z, dx, dy, dz));
+                              const uint32_t k = __float_as_uint(r.d.w);
+                              const float qx = r.a.x - rr.a.x, qy = r.a.y - rr.a.y, qz = r.a.z - rr.a.z;
+                              const float den = dx * r.b.x + dy * r.b.y + dz * r.b.z;
+                              const float tk = (qx * r.b.x + qy * r.b.y + qz * r.b.z) / den;
+                              const float hx = tk * dx - qx, hy = tk * dy - qy, hz = tk * dz - qz;
+                              const float u = (hx * r.c.x + hy * r.c.y + hz * r.c.z) * r.a.w;
+                              const float w = (hx * r.d.x + hy * r.d.y + hz * r.d.z) * r.b.w;
+                              const float f = W * 3.4f * r.c.w * gam;
+                              const float fu = f * u * r.a.w, fw = f * w * r.b.w;
+                              const float ghx = fu * r.c.x + fw * r.d.x, ghy = fu * r.c.y + fw * r.d.y,
+                                          ghz = fu * r.c.z + fw * r.d.z;
+                              const float beta = (ghx * dx + ghy * dy + ghz * dz) / den;
+                              const float gqx = beta * r.b.x - ghx, gqy = beta * r.b.y - ghy,
+                                          gqz = beta * r.b.z - ghz;
+                              sink.add3(0, k, gqx, gqy, gqz);
+                              sink.add3(3, k, fu * hx, fu * hy, fu * hz);
+                              sink.add3(6, k, fw * hx, fw * hy, fw * hz);
+                              sink.add3(9, k, -beta * hx, -beta * hy, -beta * hz);
+                              sink.add(12, k, -fu * u);
+                              sink.add(13, k, -fw * w);
+                              const float ok = bv.raw_op[k];
+                              if (ok > 0.0f && ok < kOpacityMax) sink.add(14, k, -W * gam / (1.0f - ok));
+                              gpi[0] -= (1.0f - tk) * gqx;
+                              gpi[1] -= (1.0f - tk) * gqy;
+                              gpi[2] -= (1.0f - tk) * gqz;
+                              gl[0] -= tk * gqx;
+                              gl[1] -= tk * gqy;
+                              gl[2] -= tk * gqz;
+                          });
+            sink.add3(0, (uint32_t)i, gpi[0], gpi[1], gpi[2]);
+        }
+        // the light's fields: one wave sum, then one fixed-point add per wave
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (PASS == 0) {
+                sink.m[15 + q] = fmaxf(sink.m[15 + q], fabsf(gl[q]));
+            } else {
+                const long long fxv = __float2ll_rn(gl[q] * __builtin_ldexpf(1.0f, fx[15 + q]));
+                unsigned long long tot = (unsigned long long)fxv;
+                for (int off = 32; off > 0; off >>= 1) tot += (unsigned long long)__shfl_xor((long long)tot, off, 64);
+                if (__lane_id() == 0 && tot != 0)
+                    __hip_atomic_fetch_add(sink.lacc + (int64_t)q * Lt + l, tot, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    if (PASS == 1 && live && g_alb) {
+        g_alb[3 * i + 0] = ga[0];
+        g_alb[3 * i + 1] = ga[1];
+        g_alb[3 * i + 2] = ga[2];
+    }
+    if (PASS == 0) {
+#pragma unroll
+        for (int f = 0; f < kLightFields; ++f) {
+            float v = sink.m[f];
+            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+            if (__lane_id() == 0 && v > 0.0f) atomicMax(maxbits + f, __float_as_uint(v));
+        }
+    }
+}
+
+__global__ void k_light_exp(const uint32_t *maxbits, int64_t count_surfel, int64_t count_light, int *fx) {
+    const int f = threadIdx.x;
+    if (f >= kLightFields) return;
+    const float m = __uint_as_float(maxbits[f]);
+    int e = 0;
+    if (!(m <= 3.0e38f)) {
+        e = kFxNonFinite;
+    } else if (m > 0.0f) {
+        int ex;
+        (void)frexpf(m * (float)(f < 15 ? count_surfel : count_light), &ex);
+        e = min(120, max(-120, 62 - ex));
+    }
+    fx[f] = e;
+}
+
+__global__ void k_light_finish(const unsigned long long *__restrict__ lacc, const int *fx, int Lt, float *g_lpos,
+                               float *g_lI) {
+    const int t = threadIdx.x + blockIdx.x * blockDim.x;
+    if (t >= 4 * Lt) return;
+    const int q = t / Lt, l = t % Lt;
+    unsigned long long s = 0;
+    for (int x = 0; x < 8; ++x) s += lacc[((int64_t)x * 4 + q) * Lt + l];
+    const int e = fx[15 + q];
+    const float v = e == kFxNonFinite ? __builtin_nanf("") : __builtin_ldexpf(__ll2float_rn((long long)s), -e);
+    if (q < 3) {
+        if (g_lpos) g_lpos[3 * l + q] = v;
+    } else if (g_lI) {
+        g_lI[l] = v;
+    }
+}
+
 // Composited hit list of every ray of the listed receivers (diagnostics and
 // parity tests): direction, count, and per hit (j, t, front).
 __global__ void __launch_bounds__(256) k_ray_hits(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
@@ -1565,6 +1756,32 @@ gsrad_status launch_geometry_rec(const BvhDev &bv, int R, uint64_t seed, const u
     const int64_t tot = bv.n * kCenterFields;
     hipLaunchKernelGGL(k_center_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, fx, bv.n, o15);
     return check_hip(hipGetLastError(), "geometry backward launch");
+}
+
+size_t light_acc_bytes(int64_t n, int Lt) {
+    return (size_t)8 * kCenterFields * n * 8 + (size_t)8 * 4 * Lt * 8 + 256;
+}
+
+gsrad_status launch_direct_backward(const BvhDev &bv, const float *albedo, const float *lpos, const float *lI, int Lt,
+                                    int K, const float *gE, void *acc, float *g_lpos, float *g_lI, float *g_alb,
+                                    const CenterOutputs &out, int *err, hipStream_t st) {
+    unsigned long long *a = static_cast<unsigned long long *>(acc);
+    unsigned long long *la = a + (size_t)8 * kCenterFields * bv.n;
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(la + (size_t)8 * 4 * Lt);
+    int *fx = reinterpret_cast<int *>(maxbits + 32);
+    const dim3 grid((unsigned)((bv.n + 127) / 128));
+    const size_t smem = ff_stack_bytes(128);
+    hipLaunchKernelGGL(k_direct_bwd<0>, grid, dim3(128), smem, st, bv, albedo, lpos, lI, Lt, K, gE, maxbits, fx, a, la,
+                       g_alb, err);
+    hipLaunchKernelGGL(k_light_exp, dim3(1), dim3(64), 0, st, maxbits, bv.n * (int64_t)Lt + bv.n, bv.n, fx);
+    hipLaunchKernelGGL(k_direct_bwd<1>, grid, dim3(128), smem, st, bv, albedo, lpos, lI, Lt, K, gE, maxbits, fx, a, la,
+                       g_alb, err);
+    CenterOutputs o15 = out;
+    o15.p[15] = nullptr;
+    const int64_t tot = bv.n * kCenterFields;
+    hipLaunchKernelGGL(k_center_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, fx, bv.n, o15);
+    hipLaunchKernelGGL(k_light_finish, dim3((unsigned)((4 * Lt + 63) / 64)), dim3(64), 0, st, la, fx, Lt, g_lpos, g_lI);
+    return check_hip(hipGetLastError(), "direct light backward launch");
 }
 
 gsrad_status launch_direct_sh(const BvhDev &bv, const float *R, const float *lpos, const float *lI, int Lt, int K,

@@ -29,7 +29,7 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_transport_solve_noalloc", "gsrad_brdf_reflectance", "gsrad_brdf_backward",
            "gsrad_direct_light_sh", "gsrad_transport_solve_sh", "gsrad_transport_backward_sh",
            "gsrad_batch_set_lanes", "gsrad_ff_center", "gsrad_ff_center_backward",
-           "gsrad_geometry_backward",
+           "gsrad_geometry_backward", "gsrad_direct_light_backward",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
@@ -93,6 +93,8 @@ def lib():
             "gsrad_ff_center": ([vp, vp, vp, pvp, vp], i32),
             "gsrad_ff_center_backward": ([vp, vp, vp, vp, vp, ctypes.POINTER(_SurfelGrads), vp], i32),
             "gsrad_geometry_backward": ([vp, vp, vp, ctypes.POINTER(_SurfelGrads), vp], i32),
+            "gsrad_direct_light_backward": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.POINTER(_SurfelGrads),
+                                             vp], i32),
             "gsrad_tape_grad_F_dense": ([vp, vp, vp], i32),
             "gsrad_direct_light": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "gsrad_transport_solve": ([vp, vp, vp, i32, i32, i32, i32, vp, pvp, vp], i32),
@@ -375,6 +377,24 @@ def geometry_backward(bvh: BVH, ff: FF, grad_F: torch.Tensor, stream=None) -> Di
     _check(lib().gsrad_geometry_backward(bvh.h, ff.h, _ptr(gF, name="grad_F"), ctypes.byref(sg), _stream(stream)),
            "gsrad_geometry_backward")
     return out
+
+
+def direct_light_backward(bvh: BVH, albedo: torch.Tensor, light_pos: torch.Tensor, light_I: torch.Tensor,
+                          grad_E: torch.Tensor, stream=None):
+    """(dL/dlight_pos [Lt, 3], dL/dlight_I [Lt], dL/dalbedo [n, 3],
+    {field: dL/dfield [n]}) through direct_light for dL/dE = grad_E."""
+    n, Lt, K = bvh.n, int(light_pos.shape[0]), int(grad_E.shape[2])
+    dev = torch.device("cuda")
+    glp = torch.empty((Lt, 3), dtype=torch.float32, device=dev)
+    gli = torch.empty(Lt, dtype=torch.float32, device=dev)
+    gal = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    out = {f: torch.empty(n, dtype=torch.float32, device=dev) for f in SOA}
+    sg = _SurfelGrads(*[out[f].data_ptr() for f in SOA])
+    _check(lib().gsrad_direct_light_backward(bvh.h, _ptr(albedo, name="albedo"), _ptr(light_pos, name="light_pos"),
+                                             _ptr(light_I, name="light_I"), Lt, K, _ptr(grad_E, name="grad_E"),
+                                             _ptr(glp), _ptr(gli), _ptr(gal), ctypes.byref(sg), _stream(stream)),
+           "gsrad_direct_light_backward")
+    return glp, gli, gal, out
 
 
 def ff_dense(ff: FF, stream=None) -> FF:

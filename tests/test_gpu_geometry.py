@@ -60,3 +60,33 @@ def test_geometry_backward_needs_records(g):
     with pytest.raises(g.GsradError) as ei:
         g.geometry_backward(bvh, ff, dev(np.ones(ff.info()[1], np.float32)))
     assert ei.value.status == g.gsrad.ESTATE
+
+
+@pytest.mark.parametrize("name,n,Lt", [("fruit_bowl", 2000, 2), ("box_room", 1500, 3), ("layers", None, 2)])
+def test_direct_light_gradients_match_oracle(g, orc, name, n, Lt):
+    if name == "layers":
+        sur = scenes.layer_stack()
+        nn = sur["px"].shape[0]
+        alb = np.full((nn, 3), 0.5, np.float32)
+        lp = np.array([[0.0, 0.0, 2.5], [0.3, -0.2, 3.0]], np.float32)
+    else:
+        sc = scenes.make_config(name, n=n)
+        sur, alb, nn = sc.surfels, sc.albedo, sc.n
+        lp = np.random.default_rng(3).uniform(-0.5, 0.5, (Lt, 3)).astype(np.float32)
+        lp[:, 1] += 1.2 if name == "fruit_bowl" else 2.5
+    lI = np.linspace(1.0, 3.0, Lt).astype(np.float32)
+    K = 4
+    gE = np.random.default_rng(4).standard_normal((nn, Lt, K, 3)).astype(np.float32)
+    bvh = g.build_bvh(dev_surfels(sur))
+    glp, gli, gal, gs = g.direct_light_backward(bvh, dev(alb), dev(lp), dev(lI), dev(gE))
+    te = orc.default_t_eps(sur)
+    rlp, rli, ral, rs = orc.direct_light_backward(sur, alb, lp, lI, gE, t_eps=te)
+    assert rel_err(glp.cpu().numpy(), rlp) < TOL
+    assert rel_err(gli.cpu().numpy(), rli) < TOL
+    assert rel_err(gal.cpu().numpy(), ral) < TOL
+    for f in orc.GEOMETRY_FIELDS:
+        assert rel_err(gs[f].cpu().numpy(), rs[f]) < TOL, f
+    again = g.direct_light_backward(bvh, dev(alb), dev(lp), dev(lI), dev(gE))
+    assert torch.equal(again[0], glp) and torch.equal(again[1], gli)
+    for f in orc.GEOMETRY_FIELDS:
+        assert torch.equal(again[3][f], gs[f]), f
