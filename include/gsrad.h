@@ -106,6 +106,7 @@ typedef struct gsrad_bvh gsrad_bvh;   /* prepared surfels + LBVH            */
 typedef struct gsrad_ff gsrad_ff;     /* sparse transport matrix F (CSR)    */
 typedef struct gsrad_tape gsrad_tape;   /* forward iterates for the backward  */
 typedef struct gsrad_batch gsrad_batch; /* scenes sharing one block-diagonal F */
+typedef struct gsrad_mc gsrad_mc;       /* Monte-Carlo solver state and surfel groups */
 
 /* Library version string (static storage). */
 const char *gsrad_version(void);
@@ -330,6 +331,50 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *batch, const float *rho
  */
 gsrad_status gsrad_batch_set_lanes(gsrad_batch *batch, int32_t lanes_bounce, int32_t lanes_adjoint);
 void gsrad_batch_destroy(gsrad_batch *batch);
+/*
+ * Monte-Carlo solver (Sec. 7, Alg. Monte-Carlo Solver, App. D) of the
+ * scalar Lambertian transport B = E + rho (F B) with the centre-to-centre
+ * decay of Sec. 8 (F_ij = lambda_j A_j T_ij |n_i.w||n_j.w| / (pi r^2), its
+ * transmittance from one segment per drawn pair).  With E the direct light
+ * (the lights' radiance already shot to every surfel) this is the paper's
+ * hybrid scheme: the Monte-Carlo steps solve the remaining transport.
+ *
+ * gsrad_mc_create groups the surfels by K-Means on their centres (groups
+ * <= 0: round(sqrt(n)); kmeans_iters Lloyd iterations from every
+ * (n/groups)-th surfel in Morton order), each group keeping its mean centre
+ * and normal.  The handle follows the BVH (a rebuild needs a new handle).
+ *
+ * gsrad_mc_estimate: one next event for every receiver a given the current
+ * radiance B [n][Lt][K][3]: a group g drawn with probability proportional
+ * to L_g (|n_a.w_g| + 0.05)(|nbar_g.w_g| + 0.05) / max(r_g^2, (0.01 diag)^2)
+ * (L_g the summed luminance of its members' DC radiance), a member j != a
+ * proportional to lum(B_j) |n_a.v||n_j.v| / |v|^4 (Eq. importance-sampling),
+ * both by the inverse of their running sums (the same distribution as the
+ * streaming weighted reservoir), and the one-point estimate (Eq.
+ * one-point-estimator) delta_a = E_a + rho_a F_aj B_j / Pr[j] (E_a alone if
+ * nothing can be drawn), written to delta_out [n][Lt][K][3].  Its
+ * expectation is E + rho (F B) over the pairs with Pr > 0.  Draws:
+ * Philox4x64-10 counter (receiver, step, 0, 2), key (seed, 0).
+ *
+ * gsrad_mc_solve: steps rounds of the TD(0) update (Eq. update) from zero:
+ * the receivers are every surfel for the first 8 rounds, then n draws with
+ * replacement in proportion to each surfel's tracked variance (summed over
+ * the columns; stratified inverse CDF of 2^24-level integer weights,
+ * counter (slot, step, 1, 1)); each receiver averages its estimates
+ * (S_a += delta, S2_a += delta^2, D_a += 1, B_a = S_a / D_a).  B_out
+ * [n][Lt][K][3]; visits_out [n] (uint32, may be NULL) the D_a.  Bit
+ * identical between runs with the same seed.
+ */
+gsrad_status gsrad_mc_create(const gsrad_bvh *bvh, int32_t groups, int32_t kmeans_iters, gsrad_mc **mc,
+                             void *stream);
+gsrad_status gsrad_mc_estimate(gsrad_mc *mc, const float *lambda, const float *rho, const float *E, const float *B,
+                               int32_t n_lights, int32_t K, uint64_t seed, int32_t step, float *delta_out,
+                               void *stream);
+gsrad_status gsrad_mc_solve(gsrad_mc *mc, const float *lambda, const float *rho, const float *E, int32_t n_lights,
+                            int32_t K, int32_t steps, uint64_t seed, float *B_out, uint32_t *visits_out,
+                            void *stream);
+void gsrad_mc_destroy(gsrad_mc *mc);
+
 
 /*
  * Directional transfer with the diffuse + Phong BRDF (Eq. final-radiosity

@@ -10,4 +10,4 @@ from .gsrad import (BF16, BVH, FF, FP32, Batch, GsradError, RadiosityFn, Tape, b
                     ray_hits, reflectance, tape_grad_F_dense, transport_backward, transport_solve, transport_solve_noalloc,
                     version, brdf_reflectance, brdf_backward, direct_light_sh, transport_solve_sh,
                     transport_backward_sh, batch_set_lanes, ff_center, ff_center_backward,
-                    geometry_backward, direct_light_backward)
+                    geometry_backward, direct_light_backward, MC, mc_create, mc_estimate, mc_solve)

@@ -298,6 +298,48 @@ struct gsrad_batch {
     }
 };
 
+struct gsrad_mc {
+    const gsrad_bvh *bvh = nullptr;
+    uint64_t gen = 0;
+    int64_t n = 0;
+    int G = 0;
+    float rmin2 = 0.0f;
+    DevBuf cent, gnrm, L, key, ids, skey, members, count, goff, rtemp, stemp;
+    DevBuf S, S2, B, delta, var, D, q, maxbits, recv, cdf, err;
+    gsrad::McBuffers mb() const {
+        gsrad::McBuffers m;
+        m.cent = cent.as<float>();
+        m.gnrm = gnrm.as<float>();
+        m.L = L.as<float>();
+        m.key = key.as<uint32_t>();
+        m.ids = ids.as<uint32_t>();
+        m.skey = skey.as<uint32_t>();
+        m.members = members.as<uint32_t>();
+        m.count = count.as<uint32_t>();
+        m.goff = goff.as<int64_t>();
+        m.rtemp = rtemp.p;
+        m.rtemp_bytes = rtemp.bytes;
+        m.stemp = stemp.p;
+        m.stemp_bytes = stemp.bytes;
+        m.S = S.as<float>();
+        m.S2 = S2.as<float>();
+        m.B = B.as<float>();
+        m.delta = delta.as<float>();
+        m.var = var.as<float>();
+        m.D = D.as<uint32_t>();
+        m.q = q.as<uint32_t>();
+        m.maxbits = maxbits.as<uint32_t>();
+        m.recv = recv.as<int32_t>();
+        m.cdf = cdf.as<int64_t>();
+        return m;
+    }
+    ~gsrad_mc() {
+        for (DevBuf *b : {&cent, &gnrm, &L, &key, &ids, &skey, &members, &count, &goff, &rtemp, &stemp, &S, &S2, &B,
+                          &delta, &var, &D, &q, &maxbits, &recv, &cdf, &err})
+            b->release();
+    }
+};
+
 namespace {
 
 #define GS_TRY(expr)                          \
@@ -1870,6 +1912,109 @@ gsrad_status gsrad_batch_set_lanes(gsrad_batch *b, int32_t lanes_bounce, int32_t
     b->drop_graph();
     return GSRAD_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Monte-Carlo TD(0) solver (Sec. 7, App. D)
+// ---------------------------------------------------------------------------
+gsrad_status gsrad_mc_create(const gsrad_bvh *bvh, int32_t groups, int32_t kmeans_iters, gsrad_mc **mc,
+                             void *stream) {
+    if (!bvh || !mc) return einval("gsrad_mc_create: null argument");
+    GS_TRY(usable(bvh, "gsrad_mc_create"));
+    const int64_t n = bvh->n;
+    int G = groups > 0 ? groups : (int)std::lround(std::sqrt((double)n));
+    if (G < 1 || G > n || G > (1 << 20)) return einval("gsrad_mc_create: groups must be in [1, min(n, 2^20)]");
+    if (kmeans_iters < 1 || kmeans_iters > 100) return einval("gsrad_mc_create: kmeans_iters must be in [1, 100]");
+    hipStream_t st = S(stream);
+    gsrad_mc *h = new gsrad_mc();
+    auto fail = [&](gsrad_status e) {
+        delete h;
+        return e;
+    };
+    gsrad_status e;
+#define ENS(buf, bytes, what) \
+    if ((e = h->buf.ensure((size_t)(bytes), what)) != GSRAD_OK) return fail(e);
+    ENS(cent, (size_t)G * 12, "group centres");
+    ENS(gnrm, (size_t)G * 12, "group normals");
+    ENS(L, (size_t)G * 4, "group luminance");
+    ENS(key, n * 4, "k-means keys");
+    ENS(ids, n * 4, "k-means ids");
+    ENS(skey, n * 4, "k-means keys");
+    ENS(members, n * 4, "group members");
+    ENS(count, (size_t)G * 4, "group counts");
+    ENS(goff, ((size_t)G + 1) * 8, "group offsets");
+    ENS(rtemp, radix_temp_bytes(n), "k-means sort temp");
+    ENS(stemp, scan_temp_bytes(std::max<int64_t>(n, G)), "scan temp");
+    ENS(err, 64, "flags");
+#undef ENS
+    if ((e = check_hip(hipMemsetAsync(h->err.p, 0, 64, st), "flags")) != GSRAD_OK) return fail(e);
+    if ((e = check_hip(hipMemsetAsync(h->gnrm.p, 0, (size_t)G * 12, st), "group normals")) != GSRAD_OK) return fail(e);
+    gsrad::McBuffers m = h->mb();
+    if ((e = mc_kmeans(bvh->dev(), G, kmeans_iters, m, st)) != GSRAD_OK) return fail(e);
+    float b[8];
+    if ((e = check_hip(hipStreamSynchronize(st), "mc sync")) != GSRAD_OK) return fail(e);
+    if ((e = check_hip(hipStreamSynchronize(bvh->stream), "mc sync")) != GSRAD_OK) return fail(e);
+    if ((e = check_hip(hipMemcpy(b, bvh->B.bounds, sizeof(b), hipMemcpyDeviceToHost), "bounds")) != GSRAD_OK)
+        return fail(e);
+    h->bvh = bvh;
+    h->gen = bvh->gen;
+    h->n = n;
+    h->G = G;
+    h->rmin2 = (0.01f * b[7]) * (0.01f * b[7]);
+    if (*mc) delete *mc;
+    *mc = h;
+    return GSRAD_OK;
+}
+
+static gsrad_status mc_ready(gsrad_mc *mc, int Lt, int K, const char *fn) {
+    if (!mc->bvh || mc->bvh->n != mc->n || mc->bvh->gen != mc->gen) {
+        set_error("%s: the BVH changed since gsrad_mc_create", fn);
+        return GSRAD_ESTATE;
+    }
+    if (Lt < 1 || !valid_K(K)) {
+        set_error("%s: bad n_lights or K", fn);
+        return GSRAD_EINVAL;
+    }
+    const size_t row = (size_t)mc->n * Lt * K * 3 * 4;
+    for (DevBuf *b : {&mc->S, &mc->S2, &mc->B, &mc->delta}) GS_TRY(b->ensure(row, "mc state"));
+    GS_TRY(mc->var.ensure((size_t)mc->n * 4, "mc variance"));
+    GS_TRY(mc->D.ensure((size_t)mc->n * 4, "mc visits"));
+    GS_TRY(mc->q.ensure((size_t)mc->n * 4, "mc weights"));
+    GS_TRY(mc->maxbits.ensure(64, "mc max"));
+    GS_TRY(mc->recv.ensure((size_t)mc->n * 4, "mc receivers"));
+    GS_TRY(mc->cdf.ensure(((size_t)mc->n + 1) * 8, "mc cdf"));
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_mc_estimate(gsrad_mc *mc, const float *lambda, const float *rho, const float *E, const float *B,
+                               int32_t n_lights, int32_t K, uint64_t seed, int32_t step, float *delta_out,
+                               void *stream) {
+    if (!mc || !lambda || !rho || !E || !B || !delta_out) return einval("gsrad_mc_estimate: null argument");
+    GS_TRY(mc_ready(mc, n_lights, K, "gsrad_mc_estimate"));
+    gsrad::McBuffers m = mc->mb();
+    return mc_step(mc->bvh->dev(), m, mc->G, mc->rmin2, lambda, rho, E, B, n_lights, K, seed, step, nullptr,
+                   delta_out, mc->err.as<int>(), S(stream));
+}
+
+gsrad_status gsrad_mc_solve(gsrad_mc *mc, const float *lambda, const float *rho, const float *E, int32_t n_lights,
+                            int32_t K, int32_t steps, uint64_t seed, float *B_out, uint32_t *visits_out,
+                            void *stream) {
+    if (!mc || !lambda || !rho || !E || !B_out) return einval("gsrad_mc_solve: null argument");
+    if (steps < 1 || steps > (1 << 20)) return einval("gsrad_mc_solve: steps must be in [1, 2^20]");
+    GS_TRY(mc_ready(mc, n_lights, K, "gsrad_mc_solve"));
+    hipStream_t st = S(stream);
+    gsrad::McBuffers m = mc->mb();
+    {
+        ProfScope ps("mc_solve", st);
+        GS_TRY(mc_solve(mc->bvh->dev(), m, mc->G, mc->rmin2, lambda, rho, E, n_lights, K, steps, seed, B_out,
+                        mc->err.as<int>(), st));
+    }
+    if (visits_out)
+        GS_TRY(check_hip(hipMemcpyAsync(visits_out, mc->D.p, (size_t)mc->n * 4, hipMemcpyDeviceToDevice, st),
+                         "visits copy"));
+    return GSRAD_OK;
+}
+
+void gsrad_mc_destroy(gsrad_mc *mc) { delete mc; }
 
 void gsrad_batch_destroy(gsrad_batch *batch) { delete batch; }
 

@@ -51,4 +51,24 @@ gsrad_status launch_direct_backward(const BvhDev &bv, const float *albedo, const
                                     int K, const float *gE, void *acc, float *g_lpos, float *g_lI, float *g_alb,
                                     const CenterOutputs &out, int *err, hipStream_t st);
 
+// Monte-Carlo TD(0) solver (trace.hip): device buffers owned by the handle
+struct McBuffers {
+    float *cent = nullptr, *gnrm = nullptr, *L = nullptr;   // [G][3], [G][3], [G]
+    uint32_t *key = nullptr, *ids = nullptr, *skey = nullptr, *members = nullptr, *count = nullptr;
+    int64_t *goff = nullptr;                                  // [G + 1]
+    void *rtemp = nullptr, *stemp = nullptr;
+    size_t rtemp_bytes = 0, stemp_bytes = 0;
+    float *S = nullptr, *S2 = nullptr, *B = nullptr, *delta = nullptr, *var = nullptr;   // [n][C], [n]
+    uint32_t *D = nullptr, *q = nullptr, *maxbits = nullptr;
+    int32_t *recv = nullptr;
+    int64_t *cdf = nullptr;                                   // [n + 1]
+};
+gsrad_status mc_kmeans(const BvhDev &bv, int G, int iters, McBuffers &mb, hipStream_t st);
+gsrad_status mc_step(const BvhDev &bv, const McBuffers &mb, int G, float rmin2, const float *lambda, const float *rho,
+                     const float *E, const float *B, int Lt, int K, uint64_t seed, int step, const int32_t *recv,
+                     float *delta, int *err, hipStream_t st);
+gsrad_status mc_solve(const BvhDev &bv, const McBuffers &mb, int G, float rmin2, const float *lambda,
+                      const float *rho, const float *E, int Lt, int K, int T, uint64_t seed, float *B_out,
+                      int *err, hipStream_t st);
+
 }  // namespace gsrad

@@ -29,7 +29,8 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_transport_solve_noalloc", "gsrad_brdf_reflectance", "gsrad_brdf_backward",
            "gsrad_direct_light_sh", "gsrad_transport_solve_sh", "gsrad_transport_backward_sh",
            "gsrad_batch_set_lanes", "gsrad_ff_center", "gsrad_ff_center_backward",
-           "gsrad_geometry_backward", "gsrad_direct_light_backward",
+           "gsrad_geometry_backward", "gsrad_direct_light_backward", "gsrad_mc_create", "gsrad_mc_estimate",
+           "gsrad_mc_solve", "gsrad_mc_destroy",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
            "gsrad_check", "gsrad_check_reciprocity", "gsrad_profile_enable", "gsrad_profile_report", "gsrad_bvh_destroy", "gsrad_ff_destroy",
            "gsrad_tape_destroy", "gsrad_batch_create", "gsrad_batch_info", "gsrad_batch_ff",
@@ -114,6 +115,10 @@ def lib():
             "gsrad_ff_destroy": ([vp], None),
             "gsrad_tape_destroy": ([vp], None),
             "gsrad_batch_destroy": ([vp], None),
+            "gsrad_mc_create": ([vp, i32, i32, pvp, vp], i32),
+            "gsrad_mc_estimate": ([vp, vp, vp, vp, vp, i32, i32, ctypes.c_uint64, i32, vp, vp], i32),
+            "gsrad_mc_solve": ([vp, vp, vp, vp, i32, i32, i32, ctypes.c_uint64, vp, vp, vp], i32),
+            "gsrad_mc_destroy": ([vp], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -395,6 +400,41 @@ def direct_light_backward(bvh: BVH, albedo: torch.Tensor, light_pos: torch.Tenso
                                              _ptr(glp), _ptr(gli), _ptr(gal), ctypes.byref(sg), _stream(stream)),
            "gsrad_direct_light_backward")
     return glp, gli, gal, out
+
+
+class MC(_Handle):
+    """Monte-Carlo TD(0) solver state (surfel groups) of one BVH."""
+    _destroy = "gsrad_mc_destroy"
+
+
+def mc_create(bvh: BVH, groups: int = 0, kmeans_iters: int = 8, stream=None) -> MC:
+    out = MC()
+    _check(lib().gsrad_mc_create(bvh.h, int(groups), int(kmeans_iters), ctypes.byref(out.h), _stream(stream)),
+           "gsrad_mc_create")
+    out.n = bvh.n
+    return out
+
+
+def mc_estimate(mc: MC, lam: torch.Tensor, rho: torch.Tensor, E: torch.Tensor, B: torch.Tensor, seed: int,
+                step: int = 0, stream=None) -> torch.Tensor:
+    """One next-event estimate per receiver given the current radiance B."""
+    Lt, K = int(E.shape[1]), int(E.shape[2])
+    out = torch.empty_like(E)
+    _check(lib().gsrad_mc_estimate(mc.h, _ptr(lam, name="lambda"), _ptr(rho, name="rho"), _ptr(E, name="E"),
+                                   _ptr(B, name="B"), Lt, K, int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), _ptr(out),
+                                   _stream(stream)), "gsrad_mc_estimate")
+    return out
+
+
+def mc_solve(mc: MC, lam: torch.Tensor, rho: torch.Tensor, E: torch.Tensor, steps: int, seed: int, stream=None):
+    """(B, visits) after `steps` TD(0) rounds."""
+    Lt, K = int(E.shape[1]), int(E.shape[2])
+    B = torch.empty_like(E)
+    visits = torch.empty(mc.n, dtype=torch.int32, device="cuda")
+    _check(lib().gsrad_mc_solve(mc.h, _ptr(lam, name="lambda"), _ptr(rho, name="rho"), _ptr(E, name="E"), Lt, K,
+                                int(steps), int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(B), _ptr(visits, torch.int32),
+                                _stream(stream)), "gsrad_mc_solve")
+    return B, visits
 
 
 def ff_dense(ff: FF, stream=None) -> FF:
