@@ -86,10 +86,15 @@ def parse():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=500,
                     help="receivers of the bounded oracle sample (about 15 s of host work)")
-    ap.add_argument("--workload", default="fruit_bowl", choices=["fruit_bowl", "multi_light", "uneven_batch"],
+    ap.add_argument("--workload", default="fruit_bowl",
+                    choices=["fruit_bowl", "multi_light", "uneven_batch", "sh_transfer", "center", "mc"],
                     help="fruit_bowl: the 100k sparse path (default); multi_light: the 32k box room with 100 "
                          "lights on the dense BF16 path; uneven_batch: 64 cluster rooms of 2k-65k surfels in one "
-                         "batch")
+                         "batch; sh_transfer: the directional SH transfer with the diffuse + Phong BRDF and the "
+                         "geometry and light gradients on the fruit bowl's ray-cast F; center: centre-to-centre "
+                         "form factors with a learnable scale, transport and gradients on the same pattern; mc: "
+                         "Monte-Carlo TD(0) rounds on the fruit bowl")
+    ap.add_argument("--mc-rounds", type=int, default=32, help="mc: TD(0) rounds per step")
     ap.add_argument("--fp32-lights", type=int, default=10,
                     help="multi_light: lights timed on the plain FP32 per-light path (scaled to all lights)")
     ap.add_argument("--batch-lights", type=int, nargs=2, default=[8, 100], metavar=("MIN", "MAX"),
@@ -116,6 +121,8 @@ def main():
         return multi_light(args, g, scenes, torch, np)
     if args.workload == "uneven_batch":
         return uneven_batch(args, g, scenes, torch, np, lights=tuple(args.batch_lights))
+    if args.workload in ("sh_transfer", "center", "mc"):
+        return paper_rows(args, g, scenes, torch, np)
     sc = scenes.make_config("fruit_bowl", n=args.n)
     N, R, K, nb, topk, Lt = sc.n, sc.R, sc.K, sc.n_bounces, sc.topk, sc.n_lights
     dev = torch.device("cuda")
@@ -405,6 +412,224 @@ def cpu_baseline(sc, n_recv, nnz, np):
 
 
 PEAK_BF16_TFLOPS = 2500.0
+
+
+def _timed(args, torch, g, step):
+    """Warm-up, then the timed steps with the library's phase events."""
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.gsrad.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.gsrad.profile_report()
+    g.gsrad.profile_enable(False)
+    return out, prof, (t1 - t0) * 1e3 / args.steps
+
+
+def paper_rows(args, g, scenes, torch, np):
+    """The paper's own extensions of the path on the 100k fruit bowl, with
+    its ray-cast F (R=128, top-512) made once outside the timed region:
+      sh_transfer  diffuse + Phong BRDF coefficients (K=16), direct light
+                   through the BRDF, 8 directional bounces with tape, their
+                   adjoint (dL/dE, dL/dR, dL/dF), the BRDF backward, the
+                   geometry gradients through the ray-cast F for that dL/dF
+                   and the light gradients for dL/dE;
+      center       centre-to-centre F with a learnable scale on the ray-cast
+                   pattern, 8 bounces + adjoint, and its gradients (scale and
+                   the 15 surfel fields of pair ends and occluders);
+      mc           --mc-rounds TD(0) rounds of the Monte-Carlo solver (groups
+                   made once) with the centre-to-centre decay at scale 0.3."""
+    sc = scenes.make_config("fruit_bowl", n=args.n)
+    N, R, K, nb, topk, Lt = sc.n, sc.R, sc.K, sc.n_bounces, sc.topk, sc.n_lights
+    dev = torch.device("cuda")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+    sur = {k: d(v) for k, v in sc.surfels.items()}
+    alb, lpos, lI = d(sc.albedo), d(sc.light_pos), d(sc.light_I)
+    bvh = g.build_bvh(sur)
+    ff = g.form_factors(bvh, R, sc.seed, t_min=sc.t_min, topk=topk, compact=True)
+    _, nnz = ff.info()
+    gB = d(scenes.seeded_array((N, Lt, K, 3), seed=99, lo=-1e-6, hi=1e-6))
+    C = Lt * K * 3
+    wl = args.workload
+    extra = {}
+    if wl == "sh_transfer":
+        mat = {k: d(v) for k, v in scenes.phong_materials(N, seed=7).items()}
+        state = {"tape": None}
+
+        def step():
+            Rm = g.brdf_reflectance(bvh, mat["k"], mat["albedo_d"], mat["albedo_s"], mat["shininess"], K)
+            E = g.direct_light_sh(bvh, Rm, lpos, lI)
+            B, tape = g.transport_solve_sh(ff, bvh, Rm, E, nb, tape=state["tape"])
+            state["tape"] = tape
+            gE, gR, gF = g.transport_backward_sh(ff, bvh, tape, Rm, gB)
+            gb = g.brdf_backward(bvh, mat["k"], mat["albedo_d"], mat["albedo_s"], mat["shininess"], gR)
+            gg = g.geometry_backward(bvh, ff, gF)
+            gl = g.direct_light_backward(bvh, alb, lpos, lI, gE)
+            return B, gb, gg, gl
+
+        unit, what = "fwd+bwd solves/s", (f"fruit bowl {N} surfels, ray-cast F (R={R}, top-{topk}, made once), diffuse "
+                                          f"+ Phong BRDF, K={K}, {Lt} light, {nb} directional bounces, fwd+bwd with "
+                                          "geometry and light gradients")
+        samp = torch.from_numpy(np.sort(np.random.default_rng(7).choice(N, 64, replace=False))).to(dev)
+        h_avg = float(g.ray_hits(bvh, samp, R, sc.seed, t_min=sc.t_min, max_hits=1)["count"].float().mean())
+        recs = N * R * h_avg
+        work = {"bounce_sh": ("hbm", nnz * 8 + N * 64 + 3 * N * C * 4),
+                "adjoint_sh": ("hbm", nnz * 8 + N * 64 + 3 * N * C * 4),
+                "sddmm_sh": ("hbm", nnz * 12 + N * 64 + 2 * nb * N * C * 4),
+                # two passes over the hit records (8 B each), the surfel
+                # records (64 B each) and dL/dF, 15 gradient fields written
+                "geometry_backward": ("hbm", 2 * (recs * 8 + N * 64 + nnz * 4) + N * 15 * 4)}
+        extra["hits_per_ray"] = h_avg
+    elif wl == "center":
+        lam = d(np.full(N, 0.8, np.float32))
+        rho = g.reflectance(bvh, alb)
+        E = g.direct_light(bvh, alb, lpos, lI, K)
+        state = {"fc": None, "tape": None}
+
+        def step():
+            fc = g.ff_center(bvh, ff, lam, ff=state["fc"])
+            state["fc"] = fc
+            B, tape = g.transport_solve(fc, rho, E, nb, tape=state["tape"])
+            state["tape"] = tape
+            gE, grho, gF = g.transport_backward(fc, tape, rho, gB)
+            gl, gs = g.ff_center_backward(bvh, fc, lam, gF)
+            return B, gl, gs
+
+        unit, what = "fwd+bwd solves/s", (f"fruit bowl {N} surfels, centre-to-centre F (scale 0.8) on the ray-cast "
+                                          f"pattern (R={R}, top-{topk}, {nnz} pairs), K={K}, {Lt} light, {nb} "
+                                          "bounces, fwd+bwd with scale and geometry gradients")
+        flop_seg = 2 * math.log2(N) * FLOP_BOX
+        work = {"ff_center": ("alu", nnz * flop_seg), "ff_center_backward": ("alu", 2 * nnz * flop_seg)}
+        extra["segments_per_launch"] = nnz
+    else:
+        lam = d(np.full(N, 0.3, np.float32))
+        rho = g.reflectance(bvh, alb)
+        E = g.direct_light(bvh, alb, lpos, lI, K)
+        mc = g.mc_create(bvh)
+        T = args.mc_rounds
+        state = {"seed": 0}
+
+        def step():
+            state["seed"] += 1
+            return g.mc_solve(mc, lam, rho, E, T, seed=state["seed"])
+
+        G = int(round(math.sqrt(N)))
+        unit, what = "receiver updates/s", (f"fruit bowl {N} surfels, {G} K-Means groups, {T} TD(0) rounds per step "
+                                            f"(one next event per receiver per round), centre-to-centre decay at "
+                                            f"scale 0.3, K={K}, {Lt} light")
+        # per receiver: G group weights + the drawn group's members (n/G on
+        # average) at ~20 flop each, and one segment walk
+        flop_recv = (G + N / G) * 20 + 2 * math.log2(N) * FLOP_BOX
+        work = {"mc_solve": ("alu", T * N * flop_recv)}
+        extra["rounds_per_step"] = T
+    out, prof, ms = _timed(args, torch, g, step)
+    phases = {k: v["total_ms"] / args.steps for k, v in prof.items()}
+    dom = max((k for k in phases if k in work), key=phases.get)
+    bound, amount = work[dom]
+    dom_ms = prof[dom]["avg_ms"]
+    if bound == "hbm":
+        ach = amount / (dom_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": amount}
+    else:
+        ach = amount / (dom_ms * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_TFLOPS, "traffic": None, "flop_per_launch": amount}
+    value = (N * args.mc_rounds / (ms * 1e-3)) if wl == "mc" else 1e3 / ms
+    result = {"metric": f"{wl}: {unit} at 100k surfels", "value": value, "unit": unit, "n_gpus": 1,
+              "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+              "config": {"workload": what, "surfels": N, "nnz": nnz, "K": K, "lights": Lt, "bounces": nb},
+              "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())}, "roofline": roof}
+    result.update(extra)
+    if wl == "center" and not args.no_check:
+        result["err_vs_fp64"] = center_errors(g, sc, bvh, state["fc"], torch, np)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = rows_cpu_baseline(wl, sc, nnz, np, T=args.mc_rounds)
+    print(json.dumps(result))
+
+
+def center_errors(g, sc, bvh, fc, torch, np, n_rows=8):
+    """Centre-to-centre rows of the timed launch against the oracle on the
+    pairs the oracle's own ray cast records for those receivers (entries on
+    both sides compared; top-k threshold swaps counted, not scored)."""
+    import oracle
+    from oracle import center
+    te = oracle.default_t_eps(sc.surfels)
+    recv = np.sort(np.random.default_rng(23).choice(sc.n, size=n_rows, replace=False)).astype(np.int64)
+    rpo, co, _, _ = oracle.ff_rows(sc.surfels, recv, sc.R, sc.seed, te, sc.t_min, sc.topk)
+    rows = np.repeat(recv, np.diff(rpo))
+    lam = np.full(sc.n, np.float32(0.8), np.float64)
+    Fo, _ = center.center_ff(sc.surfels, rows, co, lam, t_eps=te)
+    rp, col, val = (x.cpu().numpy() for x in fc.csr())
+    num = den = 0.0
+    common = other = 0
+    for k, i in enumerate(recv):
+        a = dict(zip(col[rp[i]:rp[i + 1]].tolist(), val[rp[i]:rp[i + 1]].tolist()))
+        for j, v in zip(co[rpo[k]:rpo[k + 1]].tolist(), Fo[rpo[k]:rpo[k + 1]].tolist()):
+            den = max(den, abs(v))
+            if j in a:
+                num = max(num, abs(a[j] - v))
+                common += 1
+            else:
+                other += 1
+    return {"F_center_rows": num / den if den > 0 else None, "pairs_compared": common,
+            "pairs_only_in_one_pattern": other, "rows_sampled": n_rows}
+
+
+def rows_cpu_baseline(wl, sc, nnz, np, T=32):
+    """The FP64 oracle of the same row on the host cores, on a bounded
+    sample scaled to one step."""
+    import scipy.sparse as sp
+
+    import oracle
+    from oracle import center
+    from oracle import sh as osh
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rng = np.random.default_rng(13)
+    N = sc.n
+    if wl == "sh_transfer":
+        # 8 directional bounces + the adjoint on the first m rows' entries of a
+        # seeded operator with the workload's row length, scaled by entries
+        import scenes
+        m = 2000
+        rp, c, v = scenes.seeded_csr(m, sc.topk, seed=5)
+        F = sp.csr_matrix((v.astype(np.float64), c, rp), shape=(m, m))
+        sub = {k: np.ascontiguousarray(a[:m]) for k, a in sc.surfels.items()}
+        Rm = rng.uniform(0, 1, (m, sc.K, 3))
+        E = rng.uniform(0, 1, (m, sc.n_lights, sc.K, 3))
+        t0 = time.perf_counter()
+        _, tape = osh.bounce(F, sub, Rm, E, sc.n_bounces, keep_tape=True)
+        osh.adjoint(F, sub, Rm, tape, E)
+        dt = time.perf_counter() - t0
+        return {"value": 1.0 / (dt * nnz / F.nnz), "unit": "fwd+bwd solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"directional bounces + adjoint on a {m}-row seeded operator ({F.nnz} entries) scaled to "
+                          f"nnz={nnz}", "seconds_measured": dt}
+    te = oracle.default_t_eps(sc.surfels)
+    ns = 20000 if wl == "center" else 4000
+    rows = rng.integers(0, N, ns).astype(np.int64)
+    cols = rng.integers(0, N, ns).astype(np.int32)
+    keep = rows != cols
+    rows, cols = rows[keep], cols[keep]
+    lam = np.ones(N)
+    t0 = time.perf_counter()
+    center.center_ff(sc.surfels, rows, cols, lam, t_eps=te, n_threads=threads)
+    dt = time.perf_counter() - t0
+    per = dt / rows.size
+    if wl == "center":
+        t_step = per * nnz * 3     # forward and the two-pass backward, one segment each
+        return {"value": 1.0 / t_step, "unit": "fwd+bwd solves/s", "cores": threads, "kind": "oracle",
+                "sample": f"{rows.size} random pairs' centre-to-centre F (brute-force segment over all surfels), "
+                          f"scaled to 3 segment passes over nnz={nnz} (the transport is not counted)",
+                "seconds_measured": dt}
+    return {"value": 1.0 / per, "unit": "receiver updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows.size} random pairs' centre-to-centre F (one segment each, the cost of one next event "
+                      "without the weight scans), scaled per receiver update", "seconds_measured": dt}
 
 
 def multi_light(args, g, scenes, torch, np):
