@@ -35,13 +35,32 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t g) {
     return x * per + (x < rem ? x : rem) + q;
 }
 
+// Keys (t bits, j) of the k-buffer.  t > 0 is a finite FP32 value, so the
+// 64-bit key has a clear sign bit and an exponent field below all ones: read
+// as an FP64 number it is a positive finite double, and positive finite
+// doubles order exactly as their bit patterns.  The sorted insertion then
+// takes one FP64 min and one max per entry instead of a 64-bit compare and
+// four selects.  The empty entry is the largest finite double.
+constexpr uint64_t kKeyEmpty = 0x7fefffffffffffffull;
+
+__device__ __forceinline__ uint64_t key_bits(double k) { return (uint64_t)__double_as_longlong(k); }
+
+// One step of the insertion: (a, x) <- (min(a, x), max(a, x)).  Written as
+// the two VALU instructions: keys are never NaN, so the input quieting the
+// compiler would add before an IEEE min/max is not needed.
+__device__ __forceinline__ void key_insert_step(double &a, double &x) {
+    double hi;
+    asm volatile("v_max_f64 %1, %0, %2\n\tv_min_f64 %0, %0, %2" : "+v"(a), "=&v"(hi) : "v"(x));
+    x = hi;
+}
+
 // Leaf visit of the sorted traversal: FP32 hit decision, then insertion
 // into the ascending k-buffer of keys (t bits, j).  The kernel value and
 // the face of a hit are found only for the hits that end up buffered.
 template <int KB>
 __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int s, uint32_t self, float ox, float oy,
                                            float oz, float dx, float dy, float dz, float t_eps, uint64_t last,
-                                           uint64_t (&key)[KB], int &found, float &t1) {
+                                           double (&key)[KB], int &found, float &t1) {
     const SurfRec r = rec[s];
     const uint32_t j = __float_as_uint(r.d.w);
     if (j == self) return;
@@ -51,16 +70,11 @@ __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int 
     const uint64_t kk = ((uint64_t)__float_as_uint(t) << 32) | (uint64_t)j;
     if (kk <= last) return;
     ++found;
-    if (kk >= key[KB - 1]) return;
-    uint64_t x = kk;
+    if (kk >= key_bits(key[KB - 1])) return;
+    double x = __longlong_as_double((long long)kk);
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        const bool lt = x < key[k];
-        const uint64_t tk = key[k];
-        key[k] = lt ? x : tk;
-        x = lt ? tk : x;
-    }
-    if (found >= KB) t1 = __uint_as_float((uint32_t)(key[KB - 1] >> 32)) * 1.00001f + 1e-30f;
+    for (int k = 0; k < KB; ++k) key_insert_step(key[k], x);
+    if (found >= KB) t1 = __uint_as_float((uint32_t)(key_bits(key[KB - 1]) >> 32)) * 1.00001f + 1e-30f;
 }
 
 // All hits of one ray in (t, j) order, composited front to back until the
@@ -75,9 +89,9 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
     uint64_t last = 0;
     float T = 1.0f;
     for (;;) {
-        uint64_t key[KB];
+        double key[KB];
 #pragma unroll
-        for (int k = 0; k < KB; ++k) key[k] = ~0ull;
+        for (int k = 0; k < KB; ++k) key[k] = __longlong_as_double((long long)kKeyEmpty);
         int found = 0;
         const float tlo = last ? __uint_as_float((uint32_t)(last >> 32)) : t_eps;
         const float t0 = tlo * 0.99999f;
@@ -127,7 +141,7 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
         for (int k = 0; k < KB; ++k) {
             gam[k] = 0.0f;
             if (k < m) {
-                const SurfRec r = bv.rec[bv.inv[(uint32_t)key[k]]];
+                const SurfRec r = bv.rec[bv.inv[(uint32_t)key_bits(key[k])]];
                 const float den = __builtin_fmaf(dz, r.b.z, __builtin_fmaf(dy, r.b.y, __fmul_rn(dx, r.b.x)));
                 const float g = kernel_gamma(hit_r2_exact(r, ox, oy, oz, dx, dy, dz));
                 gam[k] = den < 0.0f ? g : -g;
@@ -136,12 +150,12 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
             if (k < m) {
-                const uint32_t j = (uint32_t)key[k];
+                const uint32_t j = (uint32_t)key_bits(key[k]);
                 const float g = fabsf(gam[k]);
                 const bool front = gam[k] > 0.0f;
                 const float x = __fmul_rn(bv.c[j], g);
                 const float alpha = -expm1f(-x);
-                on_hit(j, alpha, T, front, g, __uint_as_float((uint32_t)(key[k] >> 32)));
+                on_hit(j, alpha, T, front, g, __uint_as_float((uint32_t)(key_bits(key[k]) >> 32)));
                 T = __fmul_rn(T, exp_fx(-x));
                 if (T < t_min) return T;
             }
@@ -149,7 +163,7 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
         // a full buffer pruned every box beyond its last entry, so more hits
         // may exist: only a buffer that did not fill ends the ray
         if (found < KB) return T;
-        last = key[KB - 1];
+        last = key_bits(key[KB - 1]);
     }
 }
 
@@ -1091,6 +1105,38 @@ struct CenterSink {
     }
 };
 
+// Contributions of one thread to NF fields of one surfel that the whole
+// wave shares (the row's receiver): summed per thread in the fields' 64-bit
+// fixed point (exact), then over the wave, and added with one atomic per
+// field instead of one per contribution to the same address.
+template <int NF>
+struct SharedSurfelAcc {
+    long long q[NF];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) q[f] = 0;
+    }
+    template <int PASS, typename Sink>
+    __device__ __forceinline__ void add(Sink &sink, int slot, int field, float v) {
+        if (PASS == 0) sink.m[field] = fmaxf(sink.m[field], fabsf(v));
+        else q[slot] += __float2ll_rn(v * __builtin_ldexpf(1.0f, sink.fx[field]));
+    }
+    // every lane of the wave must call this (shuffles); lanes whose surfel
+    // differs from lane 0's are not allowed
+    template <int PASS>
+    __device__ __forceinline__ void flush(unsigned long long *acc, int64_t n, uint32_t surfel, const int *fields) {
+        if (PASS == 0) return;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            long long v = q[f];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (__lane_id() == 0 && v != 0)
+                __hip_atomic_fetch_add(acc + (int64_t)fields[f] * n + surfel, (unsigned long long)v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+};
+
 template <int PASS>
 __global__ void __launch_bounds__(kCenterThreads) k_center_bwd(BvhDev bv, const int64_t *__restrict__ row_ptr,
                                                                const int32_t *__restrict__ col,
@@ -1109,9 +1155,12 @@ __global__ void __launch_bounds__(kCenterThreads) k_center_bwd(BvhDev bv, const 
     sink.fx = fx;
     sink.n = n;
     const float t_eps = bv.bounds[6];
+    SharedSurfelAcc<6> accI;   // the row's receiver: p (fields 0-2) and n (9-11)
+    accI.zero();
+    uint32_t i = 0;
     if (idx < n) {
         const int64_t row = order ? (int64_t)order[idx] : idx;
-        const uint32_t i = (uint32_t)row;
+        i = (uint32_t)row;
         const SurfRec ri = bv.rec[bv.inv[row]];
         const int64_t b = row_ptr[row], e = row_ptr[row + 1];
         for (int64_t kk = b + __lane_id(); kk < e; kk += 64) {
@@ -1172,8 +1221,12 @@ __global__ void __launch_bounds__(kCenterThreads) k_center_bwd(BvhDev bv, const 
             const float dpy = c1 * ri.b.y + c2 * rj.b.y - c3 * g.dy;
             const float dpz = c1 * ri.b.z + c2 * rj.b.z - c3 * g.dz;
             sink.add3(0, j, dpx + gpj[0], dpy + gpj[1], dpz + gpj[2]);
-            sink.add3(0, i, gpi[0] - dpx, gpi[1] - dpy, gpi[2] - dpz);
-            sink.add3(9, i, c1 * g.dx, c1 * g.dy, c1 * g.dz);
+            accI.add<PASS>(sink, 0, 0, gpi[0] - dpx);
+            accI.add<PASS>(sink, 1, 1, gpi[1] - dpy);
+            accI.add<PASS>(sink, 2, 2, gpi[2] - dpz);
+            accI.add<PASS>(sink, 3, 9, c1 * g.dx);
+            accI.add<PASS>(sink, 4, 10, c1 * g.dy);
+            accI.add<PASS>(sink, 5, 11, c1 * g.dz);
             sink.add3(9, j, c2 * g.dx, c2 * g.dy, c2 * g.dz);
             const float phi = aa * ab / r4;
             sink.add(15, j, G * A * T * phi * kInvPi);
@@ -1182,6 +1235,11 @@ __global__ void __launch_bounds__(kCenterThreads) k_center_bwd(BvhDev bv, const 
             sink.add(13, j, gA * A * rj.b.w);
             sink.add(14, j, gA * bv.dado[j]);
         }
+    }
+    // one row per wave: every lane's receiver is the row's
+    if (idx < n) {
+        const int fI[6] = {0, 1, 2, 9, 10, 11};
+        accI.flush<PASS>(sink.acc, n, i, fI);
     }
     if (PASS == 0) {
 #pragma unroll
@@ -1268,6 +1326,8 @@ __global__ void __launch_bounds__(256) k_geometry_rec(BvhDev bv, int R, uint64_t
     sink.acc = acc + (int64_t)xcc_id() * kCenterFields * bv.n;
     sink.fx = fx;
     sink.n = bv.n;
+    SharedSurfelAcc<12> accI;   // the receiver: p, t_u, t_v, n (fields 0-11)
+    accI.zero();
     for (int r = tid; r < R; r += blockDim.x) {
         const uint32_t m = rcnt[(int64_t)i * R + r];
         if (m > (uint32_t)rcap) continue;
@@ -1337,10 +1397,17 @@ __global__ void __launch_bounds__(256) k_geometry_rec(BvhDev bv, int R, uint64_t
             gd[1] -= tf * gqy;
             gd[2] -= tf * gqz;
         }
-        sink.add3(0, i, gpi[0], gpi[1], gpi[2]);
-        sink.add3(3, i, sx * gd[0], sx * gd[1], sx * gd[2]);
-        sink.add3(6, i, sy * gd[0], sy * gd[1], sy * gd[2]);
-        sink.add3(9, i, sz * gd[0], sz * gd[1], sz * gd[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            accI.add<PASS>(sink, c, c, gpi[c]);
+            accI.add<PASS>(sink, 3 + c, 3 + c, sx * gd[c]);
+            accI.add<PASS>(sink, 6 + c, 6 + c, sy * gd[c]);
+            accI.add<PASS>(sink, 9 + c, 9 + c, sz * gd[c]);
+        }
+    }
+    {
+        const int fI[12] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
+        accI.flush<PASS>(sink.acc, bv.n, i, fI);
     }
     if (PASS == 0) {
 #pragma unroll
