@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--mc-rounds", type=int, default=32, help="mc: TD(0) rounds per step")
     ap.add_argument("--fp32-lights", type=int, default=10,
                     help="multi_light: lights timed on the plain FP32 per-light path (scaled to all lights)")
+    ap.add_argument("--fp32-all", type=int, default=1,
+                    help="multi_light: also time the FP32 sparse path with all lights in one launch (1) or not (0)")
     ap.add_argument("--batch-lights", type=int, nargs=2, default=[8, 100], metavar=("MIN", "MAX"),
                     help="uneven_batch: lights per room drawn from U{MIN..MAX}")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -698,6 +700,21 @@ def multi_light(args, g, scenes, torch, np):
         g.transport_backward(ff, tl, rho, gl)
     torch.cuda.synchronize()
     t_fp32 = (time.perf_counter() - t2) * Lt / nl
+    # plain FP32 with all lights in one sparse launch (C = Lt K 3 columns):
+    # the same operator and right-hand sides as the BF16 path, same passes
+    if args.fp32_all:
+        _, t1a = g.transport_solve(ff, rho, E, nb)
+        g.transport_backward(ff, t1a, rho, gB)
+        del t1a
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        _, t1a = g.transport_solve(ff, rho, E, nb)
+        g.transport_backward(ff, t1a, rho, gB)
+        torch.cuda.synchronize()
+        t_fp32_all = time.perf_counter() - t3
+        del t1a
+    else:
+        t_fp32_all = None
     C = Lt * K * 3
     Np = (N + 255) // 256 * 256
     Cp = (C + 255) // 256 * 256
@@ -741,6 +758,8 @@ def multi_light(args, g, scenes, torch, np):
         "fp32_per_light_fwd_bwd_ms": t_fp32 * 1e3,
         "fp32_lights_timed": nl,
         "speedup_vs_fp32_per_light": (t_fp32 * 1e3) / t_transport if t_transport > 0 else None,
+        "fp32_all_lights_one_launch_fwd_bwd_ms": t_fp32_all * 1e3 if t_fp32_all else None,
+        "speedup_vs_fp32_one_launch": (t_fp32_all * 1e3) / t_transport if t_fp32_all and t_transport > 0 else None,
         "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())},
         "roofline": roof,
     }

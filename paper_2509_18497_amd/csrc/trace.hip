@@ -62,6 +62,10 @@ __device__ __forceinline__ void visit_leaf(const SurfRec *__restrict__ rec, int 
                                            float oz, float dx, float dy, float dz, float t_eps, uint64_t last,
                                            double (&key)[KB], int &found, float &t1) {
     const SurfRec r = rec[s];
+    // all four 16-byte parts of the record are requested together: left to
+    // itself the compiler loads the part holding j first and the rest only
+    // after the self test, a second memory latency per leaf
+    asm volatile("" : : "v"(r.a.x), "v"(r.b.x), "v"(r.c.x), "v"(r.d.w));
     const uint32_t j = __float_as_uint(r.d.w);
     if (j == self) return;
     float t, r2;
