@@ -104,6 +104,7 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
             visit_leaf<KB>(bv.rec, 0, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
         } else {
             int sp = 0, node = 0;
+            bool ovf = false;
             for (;;) {
                 const Node nd = bv.nodes[node];
                 float tn0, tn1;
@@ -118,24 +119,26 @@ __device__ __forceinline__ float trace_sorted(const BvhDev &bv, float ox, float 
                     visit_leaf<KB>(bv.rec, ~c1, self, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
                     h1 = false;
                 }
-                if (h0 && h1) {
-                    if (sp >= STK) {
-                        atomicOr(err, kErrStack);
-                        return T;
-                    }
-                    const bool n0 = tn0 <= tn1;
-                    stack[sp * stride] = (uint32_t)(n0 ? c1 : c0);
-                    ++sp;
-                    node = n0 ? c0 : c1;
-                } else if (h0) {
-                    node = c0;
-                } else if (h1) {
-                    node = c1;
-                } else {
+                // descend into the nearer hit child and push the other; with
+                // no child left, pop.  A push past the stack's end ends the
+                // walk with an error (the caller traces again with the deep
+                // stack).
+                const bool both = h0 && h1;
+                const bool n0 = !h1 || (h0 && tn0 <= tn1);
+                ovf = both && sp >= STK;
+                if (both) stack[min(sp, STK - 1) * stride] = (uint32_t)(n0 ? c1 : c0);
+                sp += both ? 1 : 0;
+                node = n0 ? c0 : c1;
+                if (!h0 && !h1) {
                     if (sp == 0) break;
                     --sp;
                     node = (int)stack[sp * stride];
                 }
+                if (ovf) break;
+            }
+            if (ovf) {
+                atomicOr(err, kErrStack);
+                return T;
             }
         }
         const int m = found < KB ? found : KB;
@@ -181,6 +184,7 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
     float T = 1.0f;
     auto leaf = [&](int s) {
         const SurfRec r = bv.rec[s];
+        asm volatile("" : : "v"(r.a.x), "v"(r.b.x), "v"(r.c.x), "v"(r.d.w));   // whole record in one latency
         const uint32_t j = __float_as_uint(r.d.w);
         if (j == self) return;
         float t, r2;
@@ -195,6 +199,7 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
         return T;
     }
     int sp = 0, node = 0;
+    bool ovf = false;
     for (;;) {
         const Node nd = bv.nodes[node];
         float tn0, tn1;
@@ -209,24 +214,21 @@ __device__ __forceinline__ float trace_shadow(const BvhDev &bv, float ox, float 
             leaf(~c1);
             h1 = false;
         }
-        if (h0 && h1) {
-            if (sp >= kStackDeep) {
-                atomicOr(err, kErrStack);
-                return T;
-            }
-            stack[sp * stride] = (uint32_t)c1;
-            ++sp;
-            node = c0;
-        } else if (h0) {
-            node = c0;
-        } else if (h1) {
-            node = c1;
-        } else {
+        // descend (first child first), push the other; none left: pop.  A
+        // push past the stack's end ends the walk with an error.
+        const bool both = h0 && h1;
+        ovf = both && sp >= kStackDeep;
+        if (both) stack[min(sp, kStackDeep - 1) * stride] = (uint32_t)c1;
+        sp += both ? 1 : 0;
+        node = h0 ? c0 : c1;
+        if (!h0 && !h1) {
             if (sp == 0) break;
             --sp;
             node = (int)stack[sp * stride];
         }
+        if (ovf) break;
     }
+    if (ovf) atomicOr(err, kErrStack);
     return T;
 }
 
@@ -983,6 +985,7 @@ __device__ __forceinline__ void trace_segment(const BvhDev &bv, float ox, float 
     const float t0 = t_lo * 0.99999f, t1 = t_hi * 1.00001f;
     auto leaf = [&](int s) {
         const SurfRec r = bv.rec[s];
+        asm volatile("" : : "v"(r.a.x), "v"(r.b.x), "v"(r.c.x), "v"(r.d.w));   // whole record in one latency
         const uint32_t j = __float_as_uint(r.d.w);
         if (j == skip_a || j == skip_b) return;
         float t, r2;
@@ -995,6 +998,7 @@ __device__ __forceinline__ void trace_segment(const BvhDev &bv, float ox, float 
         return;
     }
     int sp = 0, node = 0;
+    bool ovf = false;
     for (;;) {
         const Node nd = bv.nodes[node];
         float tn0, tn1;
@@ -1009,24 +1013,21 @@ __device__ __forceinline__ void trace_segment(const BvhDev &bv, float ox, float 
             leaf(~c1);
             h1 = false;
         }
-        if (h0 && h1) {
-            if (sp >= kStackDeep) {
-                atomicOr(err, kErrStack);
-                return;
-            }
-            stack[sp * stride] = (uint32_t)c1;
-            ++sp;
-            node = c0;
-        } else if (h0) {
-            node = c0;
-        } else if (h1) {
-            node = c1;
-        } else {
+        // descend (first child first), push the other; none left: pop.  A
+        // push past the stack's end ends the walk with an error.
+        const bool both = h0 && h1;
+        ovf = both && sp >= kStackDeep;
+        if (both) stack[min(sp, kStackDeep - 1) * stride] = (uint32_t)c1;
+        sp += both ? 1 : 0;
+        node = h0 ? c0 : c1;
+        if (!h0 && !h1) {
             if (sp == 0) break;
             --sp;
             node = (int)stack[sp * stride];
         }
+        if (ovf) break;
     }
+    if (ovf) atomicOr(err, kErrStack);
 }
 
 constexpr int kCenterThreads = 128;   // two rows (waves) per workgroup
