@@ -44,9 +44,9 @@ TRAFFIC = {
                  "files": ["trace.hip", "gsrad_internal.h", "trace_api.h"],
                  "sha256": "069b72e124fba554e8296881ee66b9a1c0368904cbed6cc2b1ac50a2ad366a91",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
-    "dense_grad_F": {"fetch": 218977.99e6, "write": 4294.97e6,
+    "dense_grad_F": {"fetch": 236949.39e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],
-                     "sha256": "27ff053379d9503070bafc3e2439fc585a1be375fa81b1c0e3046490bd546911",
+                     "sha256": "93a246c63f1835d7eec00229cce3ebf5ac38b0f1d6043b6daa9f2b79004ad563",
                      "summary": "profiles/multi_light_32k_hbm_counters.txt"},
 }
 

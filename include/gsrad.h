@@ -342,7 +342,9 @@ void gsrad_batch_destroy(gsrad_batch *batch);
  * gsrad_mc_create groups the surfels by K-Means on their centres (groups
  * <= 0: round(sqrt(n)); kmeans_iters Lloyd iterations from every
  * (n/groups)-th surfel in Morton order), each group keeping its mean centre
- * and normal.  The handle follows the BVH (a rebuild needs a new handle).
+ * and normal.  The handle follows the BVH: a rebuild needs a new handle
+ * (calls on the old one return GSRAD_ESTATE), and the BVH must not be
+ * destroyed while the handle is used.
  *
  * gsrad_mc_estimate: one next event for every receiver a given the current
  * radiance B [n][Lt][K][3]: a group g drawn with probability proportional

@@ -171,6 +171,8 @@ struct gsrad_ff {
     bool has_order = false;
     DevBuf row_order;
     DevBuf t_row_ptr, t_col, t_val, perm, t_temp;
+    // unique per successful fill of the values (0: unusable); tapes record it
+    uint64_t fill_gen = 0;
     // provenance for the opacity backward
     const gsrad_bvh *bvh = nullptr;
     uint64_t bvh_gen = 0;
@@ -227,7 +229,10 @@ struct gsrad_tape {
     int64_t n = 0;
     int C = 0, nb = 0, Lt = 0, K = 0;
     int precision = GSRAD_FP32;
-    const gsrad_ff *ff = nullptr;
+    const gsrad_ff *ff = nullptr;     // null: unusable (no solve yet, or the last one failed)
+    uint64_t ff_gen = 0;              // the fill of ff the tape was recorded on
+    const gsrad_bvh *bvh = nullptr;   // directional transfer: the geometry it used
+    uint64_t bvh_gen = 0;
     DevBuf B, L, lam0, pp;
     // GSRAD_BF16: Q^(k) = F B^(k) (FP32 [nb][n][C]), B^(k) in BF16 as
     // [Np][Kp] rows (k-major columns), the adjoint's BF16 rows
@@ -358,6 +363,7 @@ inline gsrad_status einval(const char *msg) {
 bool valid_K(int K) { return K == 1 || K == 4 || K == 9 || K == 16; }
 
 std::atomic<uint64_t> g_build_gen{0};
+std::atomic<uint64_t> g_fill_gen{0};
 
 // A handle whose last (re)build or (re)fill failed part-way is left with
 // n = 0 and refuses every later use until it is rebuilt.
@@ -374,6 +380,7 @@ gsrad_status usable(const gsrad_ff *f, const char *fn) {
 }
 
 void invalidate(gsrad_ff *f) {
+    f->fill_gen = 0;
     f->n = 0;
     f->nnz = 0;
     f->max_row = 0;
@@ -640,6 +647,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     if ((e = launch_sorted_order(bvh->dev(), h->row_order.as<int32_t>(), st)) != GSRAD_OK) return fail(e);
     h->n = n;
     h->nnz = nnz;
+    h->fill_gen = ++g_fill_gen;
     h->max_row = flags[1];
     h->has_t = false;
     h->has_order = true;
@@ -733,6 +741,7 @@ gsrad_status gsrad_ff_from_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if ((e = check_hip(hipStreamSynchronize(st), "ff_from_csr sync")) != GSRAD_OK) return fail(e);
     h->n = n;
     h->nnz = nnz;
+    h->fill_gen = ++g_fill_gen;
     h->max_row = mx;
     h->has_t = false;
     h->has_order = false;
@@ -936,6 +945,8 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
     if (tape) {
         created = *tape == nullptr;
         tp = created ? new gsrad_tape() : *tape;
+        tp->ff = nullptr;   // unusable unless this solve succeeds
+        tp->has_G = false;
     }
     auto fail = [&](gsrad_status e) {
         if (created) delete tp;
@@ -981,6 +992,9 @@ gsrad_status gsrad_transport_solve(const gsrad_ff *ff, const float *rho, const f
         tp->precision = precision;
         tp->has_G = false;
         tp->ff = ff;
+        tp->ff_gen = ff->fill_gen;
+        tp->bvh = nullptr;
+        tp->bvh_gen = 0;
         *tape = tp;
     }
     return GSRAD_OK;
@@ -1067,7 +1081,8 @@ gsrad_status gsrad_transport_backward(const gsrad_ff *ff, const gsrad_tape *tape
                                       void *stream) {
     if (!ff || !tape || !rho || !grad_B || !grad_E) return einval("gsrad_transport_backward: null argument");
     GS_TRY(usable(ff, "gsrad_transport_backward"));
-    if (tape->ff != ff || tape->n != ff->n) return einval("gsrad_transport_backward: tape does not belong to this F");
+    if (tape->ff != ff || tape->ff_gen != ff->fill_gen || tape->n != ff->n)
+        return einval("gsrad_transport_backward: tape does not belong to this F as it is now");
     if (tape->precision == kTapeSH)
         return einval("gsrad_transport_backward: the tape is from gsrad_transport_solve_sh (use gsrad_transport_backward_sh)");
     hipStream_t st = S(stream);
@@ -1164,6 +1179,8 @@ gsrad_status gsrad_transport_solve_sh(const gsrad_ff *ff, const gsrad_bvh *bvh, 
     if (tape) {
         created = *tape == nullptr;
         tp = created ? new gsrad_tape() : *tape;
+        tp->ff = nullptr;   // unusable unless this solve succeeds
+        tp->has_G = false;
     }
     auto fail = [&](gsrad_status e) {
         if (created) delete tp;
@@ -1211,6 +1228,9 @@ gsrad_status gsrad_transport_solve_sh(const gsrad_ff *ff, const gsrad_bvh *bvh, 
         tp->precision = kTapeSH;
         tp->has_G = false;
         tp->ff = ff;
+        tp->ff_gen = ff->fill_gen;
+        tp->bvh = bvh;
+        tp->bvh_gen = bvh->gen;
         *tape = tp;
     }
     return GSRAD_OK;
@@ -1222,8 +1242,9 @@ gsrad_status gsrad_transport_backward_sh(const gsrad_ff *ff, const gsrad_bvh *bv
     if (!ff || !bvh || !tape || !R || !grad_B || !grad_E) return einval("gsrad_transport_backward_sh: null argument");
     GS_TRY(usable(ff, "gsrad_transport_backward_sh"));
     GS_TRY(usable(bvh, "gsrad_transport_backward_sh"));
-    if (tape->ff != ff || tape->n != ff->n || bvh->n != ff->n)
-        return einval("gsrad_transport_backward_sh: tape, F and BVH do not belong together");
+    if (tape->ff != ff || tape->ff_gen != ff->fill_gen || tape->n != ff->n || bvh->n != ff->n ||
+        tape->bvh != bvh || tape->bvh_gen != bvh->gen)
+        return einval("gsrad_transport_backward_sh: tape, F and BVH do not belong together as they are now");
     if (tape->precision != kTapeSH)
         return einval("gsrad_transport_backward_sh: the tape is not from gsrad_transport_solve_sh");
     hipStream_t st = S(stream);
@@ -1304,6 +1325,7 @@ gsrad_status gsrad_ff_center(const gsrad_bvh *bvh, const gsrad_ff *pattern, cons
     if ((e = check_hip(hipMemsetAsync(h->err.p, 0, 64, st), "flags")) != GSRAD_OK) return fail(e);
     h->n = n;
     h->nnz = nnz;
+    h->fill_gen = ++g_fill_gen;
     h->has_order = pattern->has_order;
     Csr P = h->csr();
     {
@@ -1630,6 +1652,7 @@ gsrad_status gsrad_batch_create(const gsrad_ff *const *ffs, int32_t n_scenes, co
         return fail(e);
     F->n = rows;
     F->nnz = nnz;
+    F->fill_gen = ++g_fill_gen;
     F->max_row = max_row;
     F->has_t = false;
     F->has_order = false;

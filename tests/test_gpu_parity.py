@@ -266,6 +266,26 @@ def test_solve_without_tape_and_determinism(g):
     assert torch.equal(B1, B2)
 
 
+def test_tape_is_refused_after_the_operator_is_refilled(g):
+    """A tape records the fill of F it was made on: after the handle is
+    refilled (same size), the backward refuses it; a new solve gives a
+    usable tape again."""
+    n = 600
+    rp, c, v = scenes.seeded_csr(n, 30, seed=5)
+    ff = g.ff_from_csr(dev(rp), dev(c), dev(v))
+    rho = dev(scenes.seeded_array((n, 3), seed=1, lo=0.1, hi=0.9))
+    E = dev(scenes.seeded_array((n, 1, 4, 3), seed=2))
+    gB = dev(scenes.seeded_array((n, 1, 4, 3), seed=3, lo=-1, hi=1))
+    _, tape = g.transport_solve(ff, rho, E, 3)
+    rp2, c2, v2 = scenes.seeded_csr(n, 30, seed=6)
+    g.ff_from_csr(dev(rp2), dev(c2), dev(v2), ff=ff)
+    with pytest.raises(g.GsradError):
+        g.transport_backward(ff, tape, rho, gB)
+    _, tape = g.transport_solve(ff, rho, E, 3, tape=tape)
+    gE, _, _ = g.transport_backward(ff, tape, rho, gB)
+    assert torch.isfinite(gE).all()
+
+
 def test_check_residual_and_nan(g):
     n = 800
     rp, c, v = scenes.seeded_csr(n, 30, seed=8, row_sum=0.5)

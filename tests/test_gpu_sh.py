@@ -162,3 +162,18 @@ def test_sh_tape_is_refused_by_the_scalar_backward(g):
     _, tape = g.transport_solve_sh(ff, bvh, R, E, 2)
     with pytest.raises(g.GsradError):
         g.transport_backward(ff, tape, dev(np.full((sc.n, 3), 0.5, np.float32)), E)
+
+
+def test_sh_tape_is_refused_after_the_geometry_is_rebuilt(g):
+    """The directional transfer's tape records the BVH (the pair directions)
+    it used: after an in-place rebuild the backward refuses it."""
+    sc, bvh, ff = _ray_cast(g, "furnace", None, 16, None)
+    K = 4
+    R = dev(scenes.seeded_array((sc.n, K, 3), seed=1))
+    E = dev(scenes.seeded_array((sc.n, 1, K, 3), seed=2))
+    gB = dev(scenes.seeded_array((sc.n, 1, K, 3), seed=3, lo=-1, hi=1))
+    _, tape = g.transport_solve_sh(ff, bvh, R, E, 2)
+    g.transport_backward_sh(ff, bvh, tape, R, gB)
+    g.build_bvh(dev_surfels(sc.surfels), bvh)
+    with pytest.raises(g.GsradError):
+        g.transport_backward_sh(ff, bvh, tape, R, gB)
