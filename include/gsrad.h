@@ -538,8 +538,9 @@ gsrad_status gsrad_direct_light_backward(const gsrad_bvh *bvh, const float *albe
  * plus the receiver term dL/do_i += sum_c grad_rho_ic a_ic, and
  * dL/da = grad_rho * o (both zero where the opacity clamp is active).
  * The hits are read from the per-ray records gsrad_form_factors kept (it
- * keeps them when the records of all receivers fit in 40 GB of device
- * memory and GSRAD_FF_NO_RECORDS is not set); otherwise every ray is
+ * keeps them when the record slab of all receivers, n R rcap slots of
+ * 8 B (rcap >= 256 per ray), fits in half of the device memory free at the
+ * cast, and GSRAD_FF_NO_RECORDS is not set); otherwise every ray is
  * recomputed by traversal, with identical decisions.
  * grad_F is [nnz] in F's CSR order; grad_rho and albedo [n][3];
  * grad_opacity [n], grad_albedo [n][3] (either may be NULL).  The hit

@@ -75,7 +75,6 @@ constexpr int kTapeSH = 2;          // tape precision tag of gsrad_transport_sol
 constexpr int kLog2Table = 12;      // 4096-entry aggregation table per receiver
 constexpr int kLog2TableMax = 13;   // 8192 entries: rows with more distinct senders
 constexpr int kRecCap = 256;        // recorded hits per ray to start with (composited: ~27 mean here)
-constexpr size_t kRecordBudget = size_t(40) << 30;       // records kept for the backward
 constexpr size_t kChunkRecordBudget = size_t(4) << 30;   // records of one chunk otherwise
 
 // ---------------------------------------------------------------------------
@@ -568,12 +567,17 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
     int flags[4];
     int64_t nnz = 0;
     bool keep = false;
+    // Records are kept for the backward when the slab fits in half of the
+    // device memory that is free now (counting the slab this handle holds).
+    size_t mem_free = 0, mem_total = 0;
+    if ((e = check_hip(hipMemGetInfo(&mem_free, &mem_total), "ff memory info")) != GSRAD_OK) return fail(e);
+    const size_t record_budget = (mem_free + h->recs.bytes) / 2;
     for (int attempt = 0;; ++attempt) {
         // Records of every receiver are kept for the backward when they fit;
         // otherwise receivers are traced in chunks whose records are only
         // used to build F (the backward then recomputes the rays).
         const size_t per_recv = (size_t)R * rcap * sizeof(uint2);
-        keep = (size_t)n * per_recv <= kRecordBudget && !(p->flags & GSRAD_FF_NO_RECORDS);
+        keep = (size_t)n * per_recv <= record_budget && !(p->flags & GSRAD_FF_NO_RECORDS);
         const int64_t chunk =
             keep ? n : std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(kChunkRecordBudget / per_recv)));
 #define ENS(buf, bytes, what) \

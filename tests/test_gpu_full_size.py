@@ -122,6 +122,29 @@ def test_full_size_opacity_gradient_on_sampled_rows(g, orc, bowl):
     assert np.array_equal(go, go2)
 
 
+def test_records_kept_beyond_the_former_fixed_budget(g):
+    """A 200k-surfel fruit bowl at R = 128 needs a 52 GB record slab: it is
+    kept (the geometry backward, which needs the records, runs), and the
+    opacity gradient from the records equals, bit for bit, the one that
+    recomputes every ray by traversal (a cast without records)."""
+    sc = scenes.make_config("fruit_bowl", n=200_000)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    ff = g.form_factors(bvh, sc.R, sc.seed, t_min=sc.t_min, topk=sc.topk)
+    rp, col, _ = (x.cpu().numpy() for x in ff.csr())
+    gF = np.zeros(rp[-1], np.float32)
+    rng = np.random.default_rng(3)
+    for i in rng.choice(sc.n, size=64, replace=False):
+        gF[rp[i]:rp[i + 1]] = rng.standard_normal(rp[i + 1] - rp[i]).astype(np.float32)
+    geo = g.geometry_backward(bvh, ff, dev(gF))
+    assert torch.isfinite(geo["px"]).all()
+    go = g.opacity_backward(bvh, ff, dev(gF), None, None)[0]
+    del ff
+    ff2 = g.form_factors(bvh, sc.R, sc.seed, t_min=sc.t_min, topk=sc.topk, records=False)
+    go2 = g.opacity_backward(bvh, ff2, dev(gF), None, None)[0]
+    assert torch.equal(go, go2)
+    assert int((go != 0).sum()) > 1000
+
+
 def test_full_size_transport_on_two_coefficients(g, orc):
     K, Lt, nb, topk = 16, 1, 8, 512
     slots = [0, 15]
