@@ -10,6 +10,8 @@
 //                 the top-k entries, bitonic sort by column, one ELL row.
 // k_direct        one thread per (surfel, light): shadow-ray transmittance.
 // k_opacity_bwd   compositing backward, two recomputing passes.
+#include <functional>
+
 #include "gsrad_internal.h"
 #include "sh_api.h"
 #include "sh_basis.h"
@@ -1092,21 +1094,48 @@ __global__ void __launch_bounds__(kCenterThreads) k_ff_center(BvhDev bv, const i
 // commute: bit-identical between runs) into one copy per XCD.
 template <int PASS>
 struct CenterSink {
-    float m[kCenterFields];
+    float m[kCenterFields];   // pass 0: largest |contribution| per field
+    float qm;                 // pass 1: largest |scaled contribution| (INFINITY once one is not finite)
     unsigned long long *acc;
     const int *fx;
     int64_t n;
+    __device__ __forceinline__ void track(float q) {
+        const float a = fabsf(q);
+        qm = a <= 3.0e38f ? fmaxf(qm, a) : INFINITY;
+    }
     __device__ __forceinline__ void add(int f, uint32_t surfel, float v) {
         if (PASS == 0) {
             m[f] = fmaxf(m[f], fabsf(v));
         } else {
-            fx_add(acc + (int64_t)f * n + surfel, v, __builtin_ldexpf(1.0f, fx[f]));
+            const float q = v * __builtin_ldexpf(1.0f, fx[f]);
+            track(q);
+            const long long qq = __float2ll_rn(q);
+            if (qq != 0)
+                __hip_atomic_fetch_add(acc + (int64_t)f * n + surfel, (unsigned long long)qq, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     __device__ __forceinline__ void add3(int f, uint32_t surfel, float x, float y, float z) {
         add(f, surfel, x);
         add(f + 1, surfel, y);
         add(f + 2, surfel, z);
+    }
+    // wave maxima to maxbits[0..15] (pass 0) or maxbits[32] (pass 1); every
+    // lane of the wave calls this
+    template <int P>
+    __device__ __forceinline__ void report(uint32_t *maxbits) {
+        if (P == 0) {
+#pragma unroll
+            for (int f = 0; f < kCenterFields; ++f) {
+                float v = m[f];
+                for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+                if (__lane_id() == 0 && v > 0.0f) atomicMax(maxbits + f, __float_as_uint(v));
+            }
+        } else {
+            float v = qm;
+            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+            if (__lane_id() == 0 && v > 0.0f) atomicMax(maxbits + 2 * kCenterFields, __float_as_uint(v));
+        }
     }
 };
 
@@ -1123,8 +1152,13 @@ struct SharedSurfelAcc {
     }
     template <int PASS, typename Sink>
     __device__ __forceinline__ void add(Sink &sink, int slot, int field, float v) {
-        if (PASS == 0) sink.m[field] = fmaxf(sink.m[field], fabsf(v));
-        else q[slot] += __float2ll_rn(v * __builtin_ldexpf(1.0f, sink.fx[field]));
+        if (PASS == 0) {
+            sink.m[field] = fmaxf(sink.m[field], fabsf(v));
+        } else {
+            const float qv = v * __builtin_ldexpf(1.0f, sink.fx[field]);
+            sink.track(qv);
+            q[slot] += __float2ll_rn(qv);
+        }
     }
     // every lane of the wave must call this (shuffles); lanes whose surfel
     // differs from lane 0's are not allowed
@@ -1150,12 +1184,13 @@ __global__ void __launch_bounds__(kCenterThreads) k_center_bwd(BvhDev bv, const 
                                                                const float *__restrict__ gF, uint32_t *maxbits,
                                                                const int *fx, unsigned long long *acc,
                                                                int64_t nblocks, const int32_t *__restrict__ order,
-                                                               int *err) {
+                                                               int stride, int *err) {
     extern __shared__ uint32_t stack_mem[];
-    const int64_t idx = xcd_block(blockIdx.x, nblocks) * (kCenterThreads / 64) + threadIdx.x / 64;
+    const int64_t idx = (xcd_block(blockIdx.x, nblocks) * (kCenterThreads / 64) + threadIdx.x / 64) * stride;
     CenterSink<PASS> sink;
 #pragma unroll
     for (int f = 0; f < kCenterFields; ++f) sink.m[f] = 0.0f;
+    sink.qm = 0.0f;
     sink.acc = acc + (int64_t)xcc_id() * kCenterFields * n;
     sink.fx = fx;
     sink.n = n;
@@ -1246,18 +1281,13 @@ __global__ void __launch_bounds__(kCenterThreads) k_center_bwd(BvhDev bv, const 
         const int fI[6] = {0, 1, 2, 9, 10, 11};
         accI.flush<PASS>(sink.acc, n, i, fI);
     }
-    if (PASS == 0) {
-#pragma unroll
-        for (int f = 0; f < kCenterFields; ++f) {
-            float v = sink.m[f];
-            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-            if (__lane_id() == 0 && v > 0.0f) atomicMax(maxbits + f, __float_as_uint(v));
-        }
-    }
+    sink.template report<PASS>(maxbits);
 }
 
-// per-field exponent: (max contribution) * count < 2^62, count <= 2 nnz + 2
-__global__ void k_center_exp(const uint32_t *maxbits, int64_t nnz, int *fx) {
+// per-field exponent: (max contribution) * count * 2^margin < 2^62 (count
+// bounds the contributions a surfel's field can receive; margin: headroom
+// over a maximum estimated on sampled rows)
+__global__ void k_center_exp_count(const uint32_t *maxbits, int64_t count, int margin, int *fx) {
     const int f = threadIdx.x;
     if (f >= kCenterFields) return;
     const float m = __uint_as_float(maxbits[f]);
@@ -1266,11 +1296,12 @@ __global__ void k_center_exp(const uint32_t *maxbits, int64_t nnz, int *fx) {
         e = kFxNonFinite;
     } else if (m > 0.0f) {
         int ex;
-        (void)frexpf(m * (float)(2 * nnz + 2), &ex);
-        e = min(120, max(-120, 62 - ex));
+        (void)frexpf(m * (float)count, &ex);
+        e = min(120, max(-120, 62 - ex - margin));
     }
     fx[f] = e;
 }
+
 
 __global__ void __launch_bounds__(256) k_center_finish(const unsigned long long *__restrict__ acc, const int *fx,
                                                        int64_t n, CenterOutputs out) {
@@ -1304,12 +1335,12 @@ __global__ void __launch_bounds__(256) k_geometry_rec(BvhDev bv, int R, uint64_t
                                                       const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col, const float *__restrict__ gF,
                                                       int log2h, uint32_t *maxbits, const int *fx,
-                                                      unsigned long long *acc) {
+                                                      unsigned long long *acc, int stride) {
     extern __shared__ uint32_t sm4[];
     const int H = 1 << log2h;
     uint32_t *hk = sm4;
     float *hv = reinterpret_cast<float *>(sm4 + H);
-    const int64_t b = xcd_block(blockIdx.x, nblocks);
+    const int64_t b = xcd_block(blockIdx.x, nblocks) * stride;
     const int tid = threadIdx.x;
     const SurfRec ri = bv.rec[b];
     const uint32_t i = __float_as_uint(ri.d.w);
@@ -1328,6 +1359,7 @@ __global__ void __launch_bounds__(256) k_geometry_rec(BvhDev bv, int R, uint64_t
     CenterSink<PASS> sink;
 #pragma unroll
     for (int f = 0; f < kCenterFields; ++f) sink.m[f] = 0.0f;
+    sink.qm = 0.0f;
     sink.acc = acc + (int64_t)xcc_id() * kCenterFields * bv.n;
     sink.fx = fx;
     sink.n = bv.n;
@@ -1414,31 +1446,9 @@ __global__ void __launch_bounds__(256) k_geometry_rec(BvhDev bv, int R, uint64_t
         const int fI[12] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
         accI.flush<PASS>(sink.acc, bv.n, i, fI);
     }
-    if (PASS == 0) {
-#pragma unroll
-        for (int f = 0; f < kCenterFields; ++f) {
-            float v = sink.m[f];
-            for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-            if (__lane_id() == 0 && v > 0.0f) atomicMax(maxbits + f, __float_as_uint(v));
-        }
-    }
+    sink.template report<PASS>(maxbits);
 }
 
-// per-field exponent for the recorded hits: count <= n R + n
-__global__ void k_geometry_exp(const uint32_t *maxbits, int64_t count, int *fx) {
-    const int f = threadIdx.x;
-    if (f >= kCenterFields) return;
-    const float m = __uint_as_float(maxbits[f]);
-    int e = 0;
-    if (!(m <= 3.0e38f)) {
-        e = kFxNonFinite;
-    } else if (m > 0.0f) {
-        int ex;
-        (void)frexpf(m * (float)count, &ex);
-        e = min(120, max(-120, 62 - ex));
-    }
-    fx[f] = e;
-}
 
 // ---------------------------------------------------------------------------
 // direct-light gradients: light positions and intensities, albedo, surfel
@@ -2095,21 +2105,67 @@ gsrad_status launch_ff_center(const BvhDev &bv, const Csr &P, const float *lambd
     return check_hip(hipGetLastError(), "centre-to-centre form factor launch");
 }
 
-size_t center_acc_bytes(int64_t n) { return (size_t)8 * kCenterFields * n * 8 + 256; }
+
+// The fixed-point exponents come from the largest contributions on every
+// kScaleStride-th row, with 2^kScaleMargin headroom; the accumulating pass
+// records the true maxima, and where one could overflow its field's sums the
+// pass runs again with the exact exponents (the host reads one flag).
+constexpr int kScaleStride = 64;
+constexpr int kScaleMargin = 12;
+
+size_t center_acc_bytes(int64_t n) { return (size_t)8 * kCenterFields * n * 8 + 512; }
+
+// accumulator layout: [8 XCD copies][16 fields][n] u64, then maxbits[16],
+// fx[16], the largest scaled contribution of the accumulating pass (as
+// float bits) at maxbits[32]
+static gsrad_status center_scaled_passes(int64_t n, int64_t count, void *acc, hipStream_t st,
+                                         const std::function<void(int pass, int stride)> &run) {
+    unsigned long long *a = static_cast<unsigned long long *>(acc);
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(a + (size_t)8 * kCenterFields * n);
+    int *fx = reinterpret_cast<int *>(maxbits + kCenterFields);
+    run(0, kScaleStride);
+    hipLaunchKernelGGL(k_center_exp_count, dim3(1), dim3(64), 0, st, maxbits, count, kScaleMargin, fx);
+    run(1, 1);
+    uint32_t qbits = 0;
+    gsrad_status e = check_hip(hipMemcpyAsync(&qbits, maxbits + 2 * kCenterFields, 4, hipMemcpyDeviceToHost, st),
+                               "scale check copy");
+    if (e != GSRAD_OK) return e;
+    if ((e = check_hip(hipStreamSynchronize(st), "scale check sync")) != GSRAD_OK) return e;
+    // every |scaled contribution| times the count below 2^62: no sum overflows
+    const double qmax = (double)reinterpret_cast<const float &>(qbits);
+    if (!(qmax * (double)count < 4.6e18)) {
+        // the sampled rows missed the largest contributions: exact maxima from
+        // every row, then the sums again
+        const size_t bytes = (size_t)8 * kCenterFields * n * 8;
+        if ((e = check_hip(hipMemsetAsync(a, 0, bytes + 3 * kCenterFields * 4, st), "accumulators zero")) !=
+            GSRAD_OK)
+            return e;
+        run(0, 1);
+        hipLaunchKernelGGL(k_center_exp_count, dim3(1), dim3(64), 0, st, maxbits, count, 0, fx);
+        run(1, 1);
+    }
+    return check_hip(hipGetLastError(), "scaled passes");
+}
 
 gsrad_status launch_center_backward(const BvhDev &bv, const Csr &F, const float *lambda, const float *gF, void *acc,
                                     const CenterOutputs &out, int *err, hipStream_t st) {
     if (F.n == 0) return GSRAD_OK;
     unsigned long long *a = static_cast<unsigned long long *>(acc);
-    uint32_t *maxbits = reinterpret_cast<uint32_t *>(static_cast<char *>(acc) + (size_t)8 * kCenterFields * F.n * 8);
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(a + (size_t)8 * kCenterFields * F.n);
     int *fx = reinterpret_cast<int *>(maxbits + kCenterFields);
-    const int64_t nb = (F.n + 1) / 2;
     const size_t smem = (size_t)kStackDeep * kCenterThreads * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_center_bwd<0>, dim3((unsigned)nb), dim3(kCenterThreads), smem, st, bv, F.row_ptr, F.col,
-                       F.val, F.n, lambda, gF, maxbits, fx, a, nb, F.order, err);
-    hipLaunchKernelGGL(k_center_exp, dim3(1), dim3(64), 0, st, maxbits, F.nnz, fx);
-    hipLaunchKernelGGL(k_center_bwd<1>, dim3((unsigned)nb), dim3(kCenterThreads), smem, st, bv, F.row_ptr, F.col,
-                       F.val, F.n, lambda, gF, maxbits, fx, a, nb, F.order, err);
+    auto run = [&](int pass, int stride) {
+        const int64_t rows = (F.n + stride - 1) / stride;
+        const int64_t nb = (rows + 1) / 2;
+        if (pass == 0)
+            hipLaunchKernelGGL(k_center_bwd<0>, dim3((unsigned)nb), dim3(kCenterThreads), smem, st, bv, F.row_ptr,
+                               F.col, F.val, F.n, lambda, gF, maxbits, fx, a, nb, F.order, stride, err);
+        else
+            hipLaunchKernelGGL(k_center_bwd<1>, dim3((unsigned)nb), dim3(kCenterThreads), smem, st, bv, F.row_ptr,
+                               F.col, F.val, F.n, lambda, gF, maxbits, fx, a, nb, F.order, stride, err);
+    };
+    gsrad_status e = center_scaled_passes(F.n, 2 * F.nnz + 2, acc, st, run);
+    if (e != GSRAD_OK) return e;
     const int64_t tot = F.n * kCenterFields;
     hipLaunchKernelGGL(k_center_finish, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a, fx, F.n, out);
     return check_hip(hipGetLastError(), "centre-to-centre backward launch");
@@ -2134,13 +2190,19 @@ gsrad_status launch_geometry_rec(const BvhDev &bv, int R, uint64_t seed, const u
         attr_set = true;
     }
     unsigned long long *a = static_cast<unsigned long long *>(acc);
-    uint32_t *maxbits = reinterpret_cast<uint32_t *>(static_cast<char *>(acc) + (size_t)8 * kCenterFields * bv.n * 8);
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(a + (size_t)8 * kCenterFields * bv.n);
     int *fx = reinterpret_cast<int *>(maxbits + kCenterFields);
-    hipLaunchKernelGGL(k_geometry_rec<0>, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, seed, recs, rcnt, rcap,
-                       bv.n, row_ptr, col, gF, log2h, maxbits, fx, a);
-    hipLaunchKernelGGL(k_geometry_exp, dim3(1), dim3(64), 0, st, maxbits, bv.n * (int64_t)R + bv.n, fx);
-    hipLaunchKernelGGL(k_geometry_rec<1>, dim3((unsigned)bv.n), dim3(threads), smem, st, bv, R, seed, recs, rcnt, rcap,
-                       bv.n, row_ptr, col, gF, log2h, maxbits, fx, a);
+    auto run = [&](int pass, int stride) {
+        const int64_t nb = (bv.n + stride - 1) / stride;
+        if (pass == 0)
+            hipLaunchKernelGGL(k_geometry_rec<0>, dim3((unsigned)nb), dim3(threads), smem, st, bv, R, seed, recs, rcnt,
+                               rcap, nb, row_ptr, col, gF, log2h, maxbits, fx, a, stride);
+        else
+            hipLaunchKernelGGL(k_geometry_rec<1>, dim3((unsigned)nb), dim3(threads), smem, st, bv, R, seed, recs, rcnt,
+                               rcap, nb, row_ptr, col, gF, log2h, maxbits, fx, a, stride);
+    };
+    gsrad_status e = center_scaled_passes(bv.n, bv.n * (int64_t)R + bv.n, acc, st, run);
+    if (e != GSRAD_OK) return e;
     CenterOutputs o15 = out;
     o15.p[15] = nullptr;
     const int64_t tot = bv.n * kCenterFields;
