@@ -99,6 +99,8 @@ def parse():
                     help="multi_light: lights timed on the plain FP32 per-light path (scaled to all lights)")
     ap.add_argument("--fp32-all", type=int, default=1,
                     help="multi_light: also time the FP32 sparse path with all lights in one launch (1) or not (0)")
+    ap.add_argument("--batch-precision", default="fp32", choices=["fp32", "bf16"],
+                    help="uneven_batch: precision of the batched transport's gathered rows")
     ap.add_argument("--batch-lights", type=int, nargs=2, default=[8, 100], metavar=("MIN", "MAX"),
                     help="uneven_batch: lights per room drawn from U{MIN..MAX}")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -800,6 +802,7 @@ def uneven_batch(args, g, scenes, torch, np, lights=(8, 100), topk=512):
             Es.append(g.direct_light(bvh, albs[s], lps[s], lIs[s], K))
             rhos.append(g.reflectance(bvh, albs[s]))
         batch = g.batch_create(st["ff"], Lts, K, batch=st.get("batch"))
+        g.batch_set_precision(batch, g.BF16 if args.batch_precision == "bf16" else g.FP32)
         rho = torch.cat(rhos)
         E = batch.pack(Es)
         if "gB" not in st:
@@ -851,7 +854,8 @@ def uneven_batch(args, g, scenes, torch, np, lights=(8, 100), topk=512):
     bb = prof.get("batch_bounces", {}).get("avg_ms", 0.0)
     _, nnz = batch.ff().info()
     vals = info["vals"]
-    per_bounce = nnz * 8 + 3 * vals * 4.0      # F entries + read B, E, write B (algorithmic)
+    # F entries + read B (FP32, or BF16 rows), E, write B (algorithmic)
+    per_bounce = nnz * 8 + vals * (8.0 + (2.0 if args.batch_precision == "bf16" else 4.0))
     achieved = per_bounce * nb / (bb * 1e-3) / 1e9 if bb > 0 else None
     result = {
         "metric": "fwd+bwd transport solves/s over a batch of 64 uneven scenes",
@@ -864,11 +868,11 @@ def uneven_batch(args, g, scenes, torch, np, lights=(8, 100), topk=512):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if args.batch_precision == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": f"64 cluster rooms, {sum(sc.n for sc in rooms)} surfels (2048-65536 each), "
                                f"U{{{lights[0]}..{lights[1]}}} lights per room, R={R}, top-{topk} F, K={K}, "
-                               f"{nb} bounces, fwd+bwd",
+                               f"{nb} bounces, fwd+bwd, {args.batch_precision.upper()} batched transport",
                    "scenes": len(rooms), "surfels": sum(sc.n for sc in rooms), "lights": sum(Lts),
                    "rays": rays, "nnz": nnz, "values": vals},
         "batch_transport_ms": t_batch,

@@ -330,6 +330,21 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *batch, const float *rho
  * shape (rows, stored entries, values) for the rest of the process.
  */
 gsrad_status gsrad_batch_set_lanes(gsrad_batch *batch, int32_t lanes_bounce, int32_t lanes_adjoint);
+/*
+ * Precision of the batch's transport (GSRAD_FP32, the default, or
+ * GSRAD_BF16; the batch-size paragraph of Sec. 9's ablation: many images
+ * from one propagation, here with half the bytes per gathered row).  With
+ * GSRAD_BF16 the first n_bounces - 1 bounces gather the sender rows B^(k)
+ * rounded to BF16 (round to nearest even) and sum in FP32; the last bounce
+ * gathers the FP32 B^(n-1), as the dense BF16 path's correction sweep does.
+ * The backward is the adjoint of that map with the rounding taken as the
+ * identity: its first step gathers the FP32 lambda^(n), the others
+ * lambda^(k+1) rounded to BF16; grad_F and grad_rho are formed from the
+ * FP32 iterates (their sums cancel).  Error vs FP64 within 1e-3 relative
+ * max-norm; deterministic.  A change of precision needs a new forward
+ * solve before the backward (GSRAD_ESTATE otherwise).
+ */
+gsrad_status gsrad_batch_set_precision(gsrad_batch *batch, int32_t precision);
 void gsrad_batch_destroy(gsrad_batch *batch);
 /*
  * Monte-Carlo solver (Sec. 7, Alg. Monte-Carlo Solver, App. D) of the

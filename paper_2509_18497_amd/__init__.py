@@ -9,5 +9,5 @@ from .gsrad import (BF16, BVH, FF, FP32, Batch, GsradError, RadiosityFn, Tape, b
                     effective_area, ff_dense, ff_from_csr, form_factors, opacity_backward, profile_enable, profile_report,
                     ray_hits, reflectance, tape_grad_F_dense, transport_backward, transport_solve, transport_solve_noalloc,
                     version, brdf_reflectance, brdf_backward, direct_light_sh, transport_solve_sh,
-                    transport_backward_sh, batch_set_lanes, ff_center, ff_center_backward,
+                    transport_backward_sh, batch_set_lanes, batch_set_precision, ff_center, ff_center_backward,
                     geometry_backward, direct_light_backward, MC, mc_create, mc_estimate, mc_solve)

@@ -255,19 +255,23 @@ struct gsrad_batch {
     // forward iterates B^(0..nb-1) and adjoint iterates lambda^(1..nb)
     int nb = -1;
     DevBuf Bt, Lt, lam0;
+    // GSRAD_BF16: the gathered rows of all but the last bounce (and of all but
+    // the first adjoint step) in BF16, two ping-pong slots each
+    int precision = GSRAD_FP32;
+    DevBuf Bh, Lh;
     // lanes per row chosen by timing (0: not yet)
     int lpr_fwd = 0, lpr_adj = 0;
     // captured bounce loop and the arguments it was captured with
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void *g_rho = nullptr, *g_E = nullptr, *g_B = nullptr, *g_tape = nullptr;
-    int g_nb = -1, g_lpr = 0;
+    const void *g_rho = nullptr, *g_E = nullptr, *g_B = nullptr, *g_tape = nullptr, *g_h = nullptr;
+    int g_nb = -1, g_lpr = 0, g_prec = GSRAD_FP32;
     // captured adjoint loop and its arguments
     hipGraph_t agraph = nullptr;
     hipGraphExec_t aexec = nullptr;
-    const void *a_rho = nullptr, *a_gE = nullptr, *a_L = nullptr, *a_lam0 = nullptr, *a_ft[3] = {};
-    int a_nb = -1, a_lpr = 0;
+    const void *a_rho = nullptr, *a_gE = nullptr, *a_L = nullptr, *a_lam0 = nullptr, *a_ft[3] = {}, *a_h = nullptr;
+    int a_nb = -1, a_lpr = 0, a_prec = GSRAD_FP32;
     // lanes per row forced by gsrad_batch_set_lanes (0: tuned)
     int force_fwd = 0, force_adj = 0;
     gsrad::BatchDev dev() const {
@@ -297,7 +301,7 @@ struct gsrad_batch {
         drop_graph();
         if (cap) (void)hipStreamDestroy(cap);
         delete F;
-        for (DevBuf *b : {&row_off, &val_off, &scene_C, &row_scene, &order, &counter, &temp, &Bt, &Lt, &lam0})
+        for (DevBuf *b : {&row_off, &val_off, &scene_C, &row_scene, &order, &counter, &temp, &Bt, &Lt, &lam0, &Bh, &Lh})
             b->release();
     }
 };
@@ -1730,8 +1734,8 @@ gsrad_status autotune_lanes_timed(gsrad_batch *b, const Csr &F, bool adjoint, co
     for (int lpr : {64, 32, 16}) {
         for (int rep = 0; rep < 2 && e == GSRAD_OK; ++rep) {   // the first run warms the caches
             if ((e = check_hip(hipEventRecord(e0, st), "tune record")) != GSRAD_OK) break;
-            e = launch_ragged_spmm(b->dev(), F, lpr, adjoint, in, in, rho, scratch, scratch2, b->counter.as<uint32_t>(),
-                                   st);
+            e = launch_ragged_spmm(b->dev(), F, lpr, adjoint, in, false, in, rho, scratch, scratch2,
+                                   b->counter.as<uint32_t>(), st);
             if (e == GSRAD_OK) e = check_hip(hipEventRecord(e1, st), "tune record");
         }
         if (e != GSRAD_OK) break;
@@ -1803,18 +1807,32 @@ gsrad_status gsrad_batch_transport_solve(gsrad_batch *b, const float *rho, const
         GS_TRY(autotune_lanes(b, F, false, E, rho, B_out, nullptr, st, &b->lpr_fwd));
     }
     float *tape = b->Bt.as<float>();
+    const bool bf = b->precision == GSRAD_BF16;
+    if (bf && b->Bh.bytes < (size_t)vals * 4) {
+        b->drop_graph();
+        GS_TRY(b->Bh.ensure((size_t)vals * 4, "batch BF16 rows"));
+    }
+    char *bh = bf ? static_cast<char *>(b->Bh.p) : nullptr;   // two [vals] BF16 slots
     const bool hit = b->exec && b->g_rho == rho && b->g_E == E && b->g_B == B_out && b->g_tape == tape &&
-                     b->g_nb == n_bounces && b->g_lpr == b->lpr_fwd;
+                     b->g_nb == n_bounces && b->g_lpr == b->lpr_fwd && b->g_prec == b->precision && b->g_h == bh;
     if (!hit) {
         b->drop_graph();
         if (!b->cap) GS_TRY(check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream"));
         GS_TRY(check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
         gsrad_status e = launch_copy_f32(E, vals, tape, b->cap);
+        // BF16: bounces 0 .. n-2 gather B^(k) rounded to BF16, the last one
+        // gathers the FP32 B^(n-1)
+        if (bf && n_bounces > 1 && e == GSRAD_OK) e = launch_round_bf16(E, vals, bh, b->cap);
         for (int k = 0; k < n_bounces && e == GSRAD_OK; ++k) {
-            const float *in = tape + (size_t)k * vals;
-            float *out = k == n_bounces - 1 ? B_out : tape + (size_t)(k + 1) * vals;
-            e = launch_ragged_spmm(b->dev(), F, b->lpr_fwd, false, in, E, rho, out, nullptr, b->counter.as<uint32_t>(),
-                                   b->cap);
+            const bool last = k == n_bounces - 1;
+            const bool in_bf = bf && !last;
+            const void *in = in_bf ? static_cast<const void *>(bh + (size_t)(k & 1) * vals * 2)
+                                   : static_cast<const void *>(tape + (size_t)k * vals);
+            float *out = last ? B_out : tape + (size_t)(k + 1) * vals;
+            e = launch_ragged_spmm(b->dev(), F, b->lpr_fwd, false, in, in_bf, E, rho, out, nullptr,
+                                   b->counter.as<uint32_t>(), b->cap);
+            if (e == GSRAD_OK && bf && k + 1 < n_bounces - 1)
+                e = launch_round_bf16(out, vals, bh + (size_t)((k + 1) & 1) * vals * 2, b->cap);
         }
         hipGraph_t g = nullptr;
         const gsrad_status ec = check_hip(hipStreamEndCapture(b->cap, &g), "end capture");
@@ -1830,6 +1848,8 @@ gsrad_status gsrad_batch_transport_solve(gsrad_batch *b, const float *rho, const
         b->g_tape = tape;
         b->g_nb = n_bounces;
         b->g_lpr = b->lpr_fwd;
+        b->g_prec = b->precision;
+        b->g_h = bh;
     }
     {
         ProfScope ps("batch_bounces", st);
@@ -1877,9 +1897,19 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
     // the adjoint loop is captured once into a HIP graph and replayed while
     // its arguments stay the same
     float *lam0 = b->lam0.as<float>();
+    const bool bf = b->precision == GSRAD_BF16;
+    if (bf && b->Lh.bytes < (size_t)vals * 4) {
+        if (b->aexec) (void)hipGraphExecDestroy(b->aexec);
+        if (b->agraph) (void)hipGraphDestroy(b->agraph);
+        b->aexec = nullptr;
+        b->agraph = nullptr;
+        b->a_nb = -1;
+        GS_TRY(b->Lh.ensure((size_t)vals * 4, "batch BF16 adjoint rows"));
+    }
+    char *lh = bf ? static_cast<char *>(b->Lh.p) : nullptr;   // two [vals] BF16 slots
     const bool hit = b->aexec && b->a_rho == rho && b->a_gE == grad_E && b->a_L == L && b->a_lam0 == lam0 &&
                      b->a_nb == nb && b->a_lpr == b->lpr_adj && b->a_ft[0] == FT.row_ptr && b->a_ft[1] == FT.col &&
-                     b->a_ft[2] == FT.val;
+                     b->a_ft[2] == FT.val && b->a_prec == b->precision && b->a_h == lh;
     if (!hit) {
         if (b->aexec) (void)hipGraphExecDestroy(b->aexec);
         if (b->agraph) (void)hipGraphDestroy(b->agraph);
@@ -1889,11 +1919,17 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
         if (!b->cap) GS_TRY(check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream"));
         GS_TRY(check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture"));
         gsrad_status e = GSRAD_OK;
+        // BF16: the adjoint of the forward above: its first step (the last
+        // bounce's transpose) gathers the FP32 lambda^(n), the others
+        // lambda^(k+1) rounded to BF16
         for (int k = nb - 1; k >= 0 && e == GSRAD_OK; --k) {
-            const float *in = L + (size_t)k * vals;   // lambda^(k+1)
+            const bool in_bf = bf && k < nb - 1;
+            const void *in = in_bf ? static_cast<const void *>(lh + (size_t)(k & 1) * vals * 2)
+                                   : static_cast<const void *>(L + (size_t)k * vals);   // lambda^(k+1)
             float *out = k >= 1 ? L + (size_t)(k - 1) * vals : lam0;
-            e = launch_ragged_spmm(b->dev(), FT, b->lpr_adj, true, in, nullptr, rho, out, grad_E,
+            e = launch_ragged_spmm(b->dev(), FT, b->lpr_adj, true, in, in_bf, nullptr, rho, out, grad_E,
                                    b->counter.as<uint32_t>(), b->cap);
+            if (e == GSRAD_OK && bf && k >= 1) e = launch_round_bf16(out, vals, lh + (size_t)((k - 1) & 1) * vals * 2, b->cap);
         }
         hipGraph_t gr = nullptr;
         const gsrad_status ec = check_hip(hipStreamEndCapture(b->cap, &gr), "end capture");
@@ -1912,6 +1948,8 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
         b->a_ft[0] = FT.row_ptr;
         b->a_ft[1] = FT.col;
         b->a_ft[2] = FT.val;
+        b->a_prec = b->precision;
+        b->a_h = lh;
     }
     {
         ProfScope ps("batch_adjoint", st);
@@ -1922,6 +1960,18 @@ gsrad_status gsrad_batch_transport_backward(gsrad_batch *b, const float *rho, co
         const int max_C = *std::max_element(b->scene_cols.begin(), b->scene_cols.end());
         GS_TRY(launch_ragged_sddmm(b->dev(), b->F->csr(), nb, vals, max_C, b->Bt.as<float>(), L, rho, grad_F, grad_rho,
                                    b->counter.as<uint32_t>(), st));
+    }
+    return GSRAD_OK;
+}
+
+gsrad_status gsrad_batch_set_precision(gsrad_batch *b, int32_t precision) {
+    if (!b) return einval("gsrad_batch_set_precision: null batch");
+    if (precision != GSRAD_FP32 && precision != GSRAD_BF16)
+        return einval("gsrad_batch_set_precision: precision must be GSRAD_FP32 or GSRAD_BF16");
+    if (precision != b->precision) {
+        b->drop_graph();
+        b->precision = precision;
+        b->nb = -1;   // a forward solve of the new precision must come first
     }
     return GSRAD_OK;
 }

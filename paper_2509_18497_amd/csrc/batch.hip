@@ -49,10 +49,12 @@ __device__ __forceinline__ int64_t next_row(uint32_t *counter, int64_t rows, int
 // out = E + rho * (F in) on the rows of all scenes (bounce), or
 // out = F^T (rho in) and gE += out (adjoint, FT given as F, rho applied to
 // the gathered rows).
-template <int LPR, bool ADJ>
+// The gathered rows `in` are FP32, or BF16 (IN = __bf16) in the BF16 mode of
+// the batched transport; the sums are FP32 either way.
+template <int LPR, bool ADJ, typename IN>
 __global__ void __launch_bounds__(256) k_ragged_spmm(BatchDev bd, const int64_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, const float *__restrict__ val,
-                                                     const float *__restrict__ in, const float *__restrict__ E,
+                                                     const IN *__restrict__ in, const float *__restrict__ E,
                                                      const float *__restrict__ rho, float *__restrict__ out,
                                                      float *__restrict__ gE, uint32_t *counter) {
     const int lane = __lane_id();
@@ -87,7 +89,7 @@ __global__ void __launch_bounds__(256) k_ragged_spmm(BatchDev bd, const int64_t 
                         const int64_t j = __shfl(jv, gbase + t + u, 64);
                         w[u] = __shfl(vv, gbase + t + u, 64);
                         if (ADJ) w[u] *= rho[j * 3 + colour];
-                        x[u] = in[base + (j - r0) * C + cc];
+                        x[u] = (float)in[base + (j - r0) * C + cc];
                     }
 #pragma unroll
                     for (int u = 0; u < 8; ++u) acc = __builtin_fmaf(w[u], x[u], acc);
@@ -96,7 +98,7 @@ __global__ void __launch_bounds__(256) k_ragged_spmm(BatchDev bd, const int64_t 
                     const int64_t j = __shfl(jv, gbase + t, 64);
                     float w = __shfl(vv, gbase + t, 64);
                     if (ADJ) w *= rho[j * 3 + colour];
-                    acc = __builtin_fmaf(w, in[base + (j - r0) * C + cc], acc);
+                    acc = __builtin_fmaf(w, (float)in[base + (j - r0) * C + cc], acc);
                 }
             }
             if (on) {
@@ -318,13 +320,20 @@ gsrad_status batch_order_rows(const BatchDev &bd, const int64_t *row_ptr, void *
 
 size_t batch_order_temp_bytes(int64_t n) { return 4 * ((size_t)n * 4 + 256) + radix_temp_bytes(n) + 256; }
 
-gsrad_status launch_ragged_spmm(const BatchDev &bd, const Csr &F, int lpr, bool adjoint, const float *in,
+gsrad_status launch_ragged_spmm(const BatchDev &bd, const Csr &F, int lpr, bool adjoint, const void *in, bool in_bf16,
                                 const float *E, const float *rho, float *out, float *gE, uint32_t *counter,
                                 hipStream_t st) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
     const dim3 grid(persistent_blocks()), block(256);
-#define RAGGED(L, A) \
-    hipLaunchKernelGGL((k_ragged_spmm<L, A>), grid, block, 0, st, bd, F.row_ptr, F.col, F.val, in, E, rho, out, gE, counter)
+#define RAGGED(L, A)                                                                                                 \
+    do {                                                                                                             \
+        if (in_bf16)                                                                                                 \
+            hipLaunchKernelGGL((k_ragged_spmm<L, A, __bf16>), grid, block, 0, st, bd, F.row_ptr, F.col, F.val,      \
+                               static_cast<const __bf16 *>(in), E, rho, out, gE, counter);                         \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_ragged_spmm<L, A, float>), grid, block, 0, st, bd, F.row_ptr, F.col, F.val,       \
+                               static_cast<const float *>(in), E, rho, out, gE, counter);                          \
+    } while (0)
     if (lpr == 64) {
         if (adjoint) RAGGED(64, true);
         else RAGGED(64, false);
@@ -403,6 +412,18 @@ gsrad_status launch_offset_copy_i64(const int64_t *in, int64_t n, int64_t add, i
     if (n <= 0) return GSRAD_OK;
     hipLaunchKernelGGL(k_offset_copy_i64, dim3(grid_for(n)), dim3(256), 0, st, in, n, add, out);
     return check_hip(hipGetLastError(), "offset copy launch");
+}
+
+__global__ void __launch_bounds__(256) k_round_bf16(const float *__restrict__ in, int64_t n, __bf16 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = (__bf16)in[i];   // round to nearest even
+}
+
+gsrad_status launch_round_bf16(const float *in, int64_t n, void *out, hipStream_t st) {
+    if (n <= 0) return GSRAD_OK;
+    hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, n,
+                       static_cast<__bf16 *>(out));
+    return check_hip(hipGetLastError(), "bf16 rounding launch");
 }
 
 gsrad_status launch_copy_f32(const float *in, int64_t n, float *out, hipStream_t st) {

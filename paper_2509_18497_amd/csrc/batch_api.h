@@ -23,7 +23,8 @@ gsrad_status batch_order_rows(const BatchDev &bd, const int64_t *row_ptr, void *
                               hipStream_t st);
 // bounce: out = E + rho * (F in);  adjoint (F given as F^T): out = F^T (rho in), gE += out.
 // One persistent launch; lpr = lanes per row (16, 32 or 64).  counter: one device uint32.
-gsrad_status launch_ragged_spmm(const BatchDev &bd, const Csr &F, int lpr, bool adjoint, const float *in,
+// in: FP32 rows, or BF16 rows when in_bf16 (FP32 sums either way).
+gsrad_status launch_ragged_spmm(const BatchDev &bd, const Csr &F, int lpr, bool adjoint, const void *in, bool in_bf16,
                                 const float *E, const float *rho, float *out, float *gE, uint32_t *counter,
                                 hipStream_t st);
 // grad_F at the stored entries and grad_rho from the tapes [nb][vals]
@@ -43,5 +44,7 @@ gsrad_status launch_offset_copy_i64(const int64_t *in, int64_t n, int64_t add, i
 gsrad_status launch_offset_widen(const int32_t *in, int64_t n, int64_t add, int64_t *out, hipStream_t st);
 // plain copy as a kernel (usable inside a captured graph)
 gsrad_status launch_copy_f32(const float *in, int64_t n, float *out, hipStream_t st);
+// out[k] = BF16 of in[k] (round to nearest even; out is __bf16[n])
+gsrad_status launch_round_bf16(const float *in, int64_t n, void *out, hipStream_t st);
 
 }  // namespace gsrad

@@ -28,7 +28,7 @@ EXPORTS = ("gsrad_version", "gsrad_last_error", "gsrad_build_bvh", "gsrad_bvh_in
            "gsrad_ff_copy", "gsrad_ff_from_csr", "gsrad_ff_dense", "gsrad_direct_light", "gsrad_transport_solve",
            "gsrad_transport_solve_noalloc", "gsrad_brdf_reflectance", "gsrad_brdf_backward",
            "gsrad_direct_light_sh", "gsrad_transport_solve_sh", "gsrad_transport_backward_sh",
-           "gsrad_batch_set_lanes", "gsrad_ff_center", "gsrad_ff_center_backward",
+           "gsrad_batch_set_lanes", "gsrad_batch_set_precision", "gsrad_ff_center", "gsrad_ff_center_backward",
            "gsrad_geometry_backward", "gsrad_direct_light_backward", "gsrad_mc_create", "gsrad_mc_estimate",
            "gsrad_mc_solve", "gsrad_mc_destroy",
            "gsrad_transport_backward", "gsrad_tape_grad_F_dense", "gsrad_opacity_backward", "gsrad_ray_hits",
@@ -91,6 +91,7 @@ def lib():
             "gsrad_batch_transport_solve": ([vp, vp, vp, i32, vp, vp], i32),
             "gsrad_batch_transport_backward": ([vp, vp, vp, vp, vp, vp, vp], i32),
             "gsrad_batch_set_lanes": ([vp, i32, i32], i32),
+            "gsrad_batch_set_precision": ([vp, i32], i32),
             "gsrad_ff_center": ([vp, vp, vp, pvp, vp], i32),
             "gsrad_ff_center_backward": ([vp, vp, vp, vp, vp, ctypes.POINTER(_SurfelGrads), vp], i32),
             "gsrad_geometry_backward": ([vp, vp, vp, ctypes.POINTER(_SurfelGrads), vp], i32),
@@ -323,6 +324,11 @@ def batch_create(ffs, lights, K: int, batch: Optional[Batch] = None, stream=None
 def batch_set_lanes(batch: Batch, lanes_bounce: int, lanes_adjoint: int):
     """Force the lanes per row of the batch launches (16, 32, 64; 0 = timed)."""
     _check(lib().gsrad_batch_set_lanes(batch.h, int(lanes_bounce), int(lanes_adjoint)), "gsrad_batch_set_lanes")
+
+
+def batch_set_precision(batch: Batch, precision: int):
+    """FP32 (default) or BF16 gathered rows in the batch's transport."""
+    _check(lib().gsrad_batch_set_precision(batch.h, int(precision)), "gsrad_batch_set_precision")
 
 
 def batch_transport_solve(batch: Batch, rho: torch.Tensor, E: torch.Tensor, n_bounces: int,

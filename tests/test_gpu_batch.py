@@ -247,3 +247,47 @@ def test_captured_adjoint_loop_replays_with_new_values(g):
             assert torch.equal(gEb, gEs), rep
         gB.mul_(-0.5).add_(0.25)                                 # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("nb", [1, 2, 6])
+def test_bf16_batch_within_its_bar_and_deterministic(g, orc, nb):
+    """The BF16 mode (bounces 0 .. n-2 gather BF16 rows, the last one FP32;
+    the adjoint mirrored) against the oracle's FP64 transport within 1e-3,
+    bit-identical between runs and between graph replays, and the FP32 mode
+    restored afterwards still equal to the per-scene path bit for bit.
+    n = 1 is the FP32 bounce alone."""
+    K = 9
+    sc = _scenes(g, K)
+    batch = g.batch_create([x["ff"] for x in sc], [x["lt"] for x in sc], K)
+    rho = dev(np.concatenate([x["rho"] for x in sc]))
+    E = _flat([x["E"] for x in sc])
+    gB = _flat([x["gB"] for x in sc])
+    g.batch_set_precision(batch, g.BF16)
+    with pytest.raises(g.GsradError):                      # no BF16 forward yet
+        g.batch_transport_backward(batch, rho, gB)
+    B1 = g.batch_transport_solve(batch, rho, E, nb).clone()
+    gE1, gr1, gF1 = (x.clone() for x in g.batch_transport_backward(batch, rho, gB))
+    B2 = g.batch_transport_solve(batch, rho, E, nb)
+    gE2, gr2, gF2 = g.batch_transport_backward(batch, rho, gB)
+    assert torch.equal(B1, B2) and torch.equal(gE1, gE2) and torch.equal(gr1, gr2) and torch.equal(gF1, gF2)
+    Bs, gEs = batch.unpack(B1), batch.unpack(gE1)
+    gr, gF = gr1.cpu().numpy(), gF1.cpu().numpy()
+    r0 = e0 = 0
+    worst = 0.0
+    for x, Bb, gEb in zip(sc, Bs, gEs):
+        n, nnz = x["n"], x["F"].nnz
+        Bo, tp = orc.bounce(x["F"], x["rho"], x["E"], nb, keep_tape=True)
+        gEo, gro, gFo = orc.adjoint(x["F"], x["rho"], tp, x["gB"])
+        errs = [rel_err(Bb.cpu().numpy(), Bo), rel_err(gEb.cpu().numpy(), gEo), rel_err(gr[r0:r0 + n], gro),
+                rel_err(gF[e0:e0 + nnz], gFo)]
+        assert max(errs) < 1e-3, errs
+        worst = max(worst, max(errs))
+        r0 += n
+        e0 += nnz
+    if nb == 1:
+        assert worst < TOL                                  # the FP32 bounce alone
+    g.batch_set_precision(batch, g.FP32)
+    B3 = batch.unpack(g.batch_transport_solve(batch, rho, E, nb))
+    for x, Bb in zip(sc, B3):
+        Bs1, _ = g.transport_solve(x["ff"], dev(x["rho"]), dev(x["E"]), nb)
+        assert torch.equal(Bb, Bs1)
