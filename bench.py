@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 110310.04e6, "write": 10921.42e6,
-                 "files": ["trace.hip", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "069b72e124fba554e8296881ee66b9a1c0368904cbed6cc2b1ac50a2ad366a91",
+    "ff_trace": {"fetch": 110507.73e6, "write": 10921.03e6,
+                 "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
+                 "sha256": "9cb672e0a629ebbaaab9244a0a2af7f6d27a93240069ae0cc0ead2aabbe1c095",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
     "dense_grad_F": {"fetch": 236949.39e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsrad.so")
-SOURCES = ["scan_sort.hip", "bvh.hip", "trace.hip", "sparse.hip", "sh.hip", "dense.hip", "batch.hip", "abi.cpp"]
+SOURCES = ["scan_sort.hip", "bvh.hip", "trace.hip", "grad.hip", "mc.hip", "sparse.hip", "sh.hip", "dense.hip", "batch.hip", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
