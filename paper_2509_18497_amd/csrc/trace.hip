@@ -43,6 +43,18 @@ __device__ __forceinline__ uint32_t dir_key(float dx, float dy, float dz) {
 }
 
 constexpr int kPoolRays = 1024;   // rays sorted and pooled per batch
+constexpr int kCompChunk = 5;     // buffered hits whose kernel values are found together
+// a wave composites once kFlushNum / kFlushDen of its lanes holding rays wait
+// (measured: 1/2 and 3/8 best, 1/4 and 5/8 about 2 % slower, 3/4 and 1/8 more)
+constexpr int kFlushNum = 1, kFlushDen = 2;
+
+// Lane index within the wave, recomputed at each use (volatile: not hoisted
+// out of the traversal loop into a register of its own).
+__device__ __forceinline__ int lane_index() {
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
 
 // Every composited hit of ray r of the receiver in slot `slot` is recorded
 // as (j, +-gamma), the sign being the front face, at
@@ -55,11 +67,15 @@ constexpr int kPoolRays = 1024;   // rays sorted and pooled per batch
 // One workgroup traces the rays of `group` consecutive receivers (Morton
 // order).  Per batch of up to 1024 rays the directions are generated, the
 // rays sorted by direction key, and the lanes pull rays from the sorted
-// pool through an LDS counter: neighbouring lanes trace rays that leave
-// close origins in close directions, and a lane whose ray ends early takes
-// the next one instead of idling until its wave's longest ray is done.
-// Three waves per SIMD (at most 168 VGPRs), held by a launch bound; four
-// (at most 128) were measured no faster.
+// pool through an LDS counter, so neighbouring lanes trace rays that leave
+// close origins in close directions.  Each lane walks its ray one node per
+// iteration; a lane whose k-buffer round ends waits until enough lanes of
+// its wave wait, the wave then composites them together, and a lane whose
+// ray ends takes the next ray of the pool at once instead of idling until
+// the wave's longest ray is done (the same hits, composited in the same
+// order, as the plain per-ray walk).  Three waves per SIMD (at most 168
+// VGPRs), held by a launch bound; four (at most 128) were measured no
+// faster.
 template <int STK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
                                                   int64_t s_begin, int64_t count, int group, int64_t nblocks,
@@ -111,28 +127,200 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
                 __syncthreads();
             }
         }
-        for (;;) {
-            const uint32_t p = atomicAdd(&next, 1u);
-            if (p >= (uint32_t)nb) break;
-            const int k = (int)(pool_key[p] & 1023u);
-            const int64_t id = base + k;
-            const int64_t recv = r0 + id / R;                        // chunk-relative receiver
-            const int r = (int)(id % R);
-            const SurfRec rr = bv.rec[s_begin + recv];
-            const uint32_t i = __float_as_uint(rr.d.w);
-            const int64_t slot = by_orig ? (int64_t)i : recv;
-            uint32_t q = 0;
-            uint2 *rec_out = recs + slot * rcap * R + r;
-            trace_sorted<kKB, STK>(bv, rr.a.x, rr.a.y, rr.a.z, pool_d[k][0], pool_d[k][1], pool_d[k][2], i, t_eps, t_min,
-                              stack_mem + tid, blockDim.x, err, [&](uint32_t j, float, float, bool front, float gg, float) {
-                                  if (q < (uint32_t)rcap)
-                                      rec_out[(int64_t)q * R] = make_uint2(j, __float_as_uint(front ? gg : -gg));
-                                  ++q;
-                              });
-            rcnt[slot * R + r] = q;
+        if (bv.n == 1) {
+            // a single surfel has no node to walk, and it is every ray's own
+            // receiver, which the walk skips: no ray hits anything
+            for (int p = tid; p < nb; p += 256) {
+                const int k = (int)(pool_key[p] & 1023u);
+                const int64_t id = base + k;
+                const int64_t recv = r0 + id / R;
+                const int64_t slot = by_orig ? (int64_t)__float_as_uint(bv.rec[s_begin + recv].d.w) : recv;
+                rcnt[slot * R + (int)(id % R)] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        // Lanes hold rays in one of two states: traversing (one node per
+        // iteration of the inner loop) or waiting, their k-buffer round done,
+        // to composite.  Compositing is costly per hit (the FP64 hit point,
+        // two exponentials), so the wave composites its waiting lanes
+        // together, once they are kFlushNum / kFlushDen of the lanes holding
+        // rays or no lane traverses.  The node steps have a loop of their
+        // own: the k-buffer then stays in the same registers from step to
+        // step (merged with the refill and compositing paths, the compiler
+        // copied it at every step).
+        const int lane = (int)__lane_id();
+        const int wave_base = __builtin_amdgcn_readfirstlane(tid & ~63);
+        bool have = false, trav = false, drained = false;
+        uint32_t i = 0, q = 0;
+        uint2 *rec_out = nullptr;
+        uint32_t *cnt_out = nullptr;
+        float ox = 0.0f, oy = 0.0f, oz = 0.0f, dx = 0.0f, dy = 0.0f, dz = 0.0f, ix = 0.0f, iy = 0.0f, iz = 0.0f;
+        float T = 1.0f, t0 = 0.0f, t1 = INFINITY;
+        uint64_t last = 0;
+        double key[kKB];
+#pragma unroll
+        for (int k = 0; k < kKB; ++k) key[k] = __longlong_as_double((long long)kKeyEmpty);
+        int found = 0, sp = 0, node = 0;
+        // a new k-buffer round from the root, beyond the last composited key
+        auto start_round = [&]() {
+#pragma unroll
+            for (int k = 0; k < kKB; ++k) key[k] = __longlong_as_double((long long)kKeyEmpty);
+            found = 0;
+            t0 = (last ? __uint_as_float((uint32_t)(last >> 32)) : t_eps) * 0.99999f;
+            t1 = INFINITY;
+            sp = 0;
+            node = 0;
+            trav = true;
+        };
+        auto end_ray = [&]() {
+            *cnt_out = q;
             if (q > (uint32_t)rcap) {
                 atomicOr(err, kErrRecords);
                 atomicMax(err + 3, (int)q);
+            }
+            have = false;
+            trav = false;
+        };
+        for (;;) {
+            // lanes without a ray take the next ones of the pool (one LDS
+            // atomic per wave)
+            const bool need = !have && !drained;
+            const uint64_t needm = __ballot(need);
+            if (needm) {
+                const int leader = __ffsll((unsigned long long)needm) - 1;
+                uint32_t b0 = 0;
+                if (lane == leader) b0 = atomicAdd(&next, (uint32_t)__popcll(needm));
+                b0 = (uint32_t)__shfl((int)b0, leader, 64);
+                if (need) {
+                    const uint32_t p = b0 + (uint32_t)__popcll(needm & ((1ull << lane) - 1ull));
+                    if (p >= (uint32_t)nb) {
+                        drained = true;
+                    } else {
+                        const int k = (int)(pool_key[p] & 1023u);
+                        const int64_t id = base + k;
+                        const int64_t recv = r0 + id / R;   // chunk-relative receiver
+                        const int r = (int)(id % R);
+                        const SurfRec rr = bv.rec[s_begin + recv];
+                        i = __float_as_uint(rr.d.w);
+                        const int64_t slot = by_orig ? (int64_t)i : recv;
+                        rec_out = recs + slot * rcap * R + r;
+                        cnt_out = rcnt + slot * R + r;
+                        ox = rr.a.x;
+                        oy = rr.a.y;
+                        oz = rr.a.z;
+                        dx = pool_d[k][0];
+                        dy = pool_d[k][1];
+                        dz = pool_d[k][2];
+                        ix = safe_inv(dx);
+                        iy = safe_inv(dy);
+                        iz = safe_inv(dz);
+                        q = 0;
+                        T = 1.0f;
+                        last = 0;
+                        have = true;
+                        start_round();
+                    }
+                }
+            }
+            const int nact = __popcll(__ballot(have));
+            if (nact == 0) break;
+            const int nwait = __popcll(__ballot(have && !trav));
+            if (nwait > 0 && (kFlushDen * nwait >= kFlushNum * nact || nwait == nact)) {
+                if (have && !trav) {
+                    // kernel values (FP64 hit point) and faces of the buffered
+                    // hits, kCompChunk at a time (a scheduling barrier between
+                    // chunks keeps the loads of later chunks from being
+                    // issued early, which would need more registers than
+                    // the lane's traversal state leaves), front-to-back
+                    // compositing and the records
+                    const int m = found < kKB ? found : kKB;
+                    bool done = false;
+#pragma unroll
+                    for (int c0 = 0; c0 < kKB; c0 += kCompChunk) {
+                        if (!__any(c0 < m && !done)) break;
+                        float gam[kCompChunk];
+#pragma unroll
+                        for (int k = 0; k < kCompChunk; ++k) {
+                            gam[k] = 0.0f;
+                            if (c0 + k < m && !done) {
+                                const SurfRec h = bv.rec[bv.inv[(uint32_t)key_bits(key[c0 + k])]];
+                                const float den = __builtin_fmaf(dz, h.b.z, __builtin_fmaf(dy, h.b.y, __fmul_rn(dx, h.b.x)));
+                                const float g = kernel_gamma(hit_r2_exact(h, ox, oy, oz, dx, dy, dz));
+                                gam[k] = den < 0.0f ? g : -g;
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < kCompChunk; ++k) {
+                            if (c0 + k < m && !done) {
+                                const uint32_t j = (uint32_t)key_bits(key[c0 + k]);
+                                const float g = fabsf(gam[k]);
+                                const float x = __fmul_rn(bv.c[j], g);
+                                if (q < (uint32_t)rcap)
+                                    rec_out[(int64_t)q * R] = make_uint2(j, __float_as_uint(gam[k] > 0.0f ? g : -g));
+                                ++q;
+                                T = __fmul_rn(T, exp_fx(-x));
+                                done = T < t_min;
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    // a full buffer pruned every box beyond its last entry,
+                    // so more hits may exist: only a buffer that did not fill
+                    // ends the ray
+                    if (done || found < kKB) {
+                        end_ray();
+                    } else {
+                        last = key_bits(key[kKB - 1]);
+                        start_round();
+                    }
+                }
+                continue;
+            }
+            // node steps until a flush is due or a lane needs a ray
+            for (;;) {
+                if (trav) {
+                    const Node nd = bv.nodes[node];
+                    float tn0, tn1;
+                    bool h0 = slab(nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, ox, oy, oz, ix, iy, iz, t0, t1, tn0);
+                    bool h1 = slab(nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, ox, oy, oz, ix, iy, iz, t0, t1, tn1);
+                    const int c0 = nd.ch.x, c1 = nd.ch.y;
+                    if (h0 && c0 < 0) {
+                        visit_leaf<kKB>(bv.rec, ~c0, i, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
+                        h0 = false;
+                    }
+                    if (h1 && c1 < 0) {
+                        visit_leaf<kKB>(bv.rec, ~c1, i, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
+                        h1 = false;
+                    }
+                    // descend into the nearer hit child and push the other;
+                    // with no child left, pop; an empty stack ends the round.
+                    // A push past the stack's end ends the ray with an error
+                    // (the launch is repeated with the deep stack).
+                    const bool both = h0 && h1;
+                    const bool n0 = !h1 || (h0 && tn0 <= tn1);
+                    const bool ovf = both && sp >= STK;
+                    // the lane's stack column: the wave's base (uniform) plus
+                    // the lane index, read again here rather than held in a
+                    // register across the loop
+                    uint32_t *stack = stack_mem + wave_base + lane_index();
+                    if (both) stack[min(sp, STK - 1) * 256] = (uint32_t)(n0 ? c1 : c0);
+                    sp += both ? 1 : 0;
+                    node = n0 ? c0 : c1;
+                    if (!h0 && !h1) {
+                        if (sp == 0) trav = false;
+                        else {
+                            --sp;
+                            node = (int)stack[sp * 256];
+                        }
+                    }
+                    if (ovf) {
+                        atomicOr(err, kErrStack);
+                        end_ray();
+                    }
+                }
+                const int nw = __popcll(__ballot(have && !trav));
+                if ((nw > 0 && (kFlushDen * nw >= kFlushNum * nact || nw == nact)) || __ballot(!have && !drained)) break;
             }
         }
         __syncthreads();
