@@ -1,10 +1,12 @@
 // Ray casting through the surfel LBVH with alpha compositing.
 //
-// k_ff_trace      one workgroup per receiver surfel, one thread per ray:
-//                 multi-round k-buffer traversal (the KB nearest hits beyond
-//                 the last composited key per round, keys (t, j)), front-to-
-//                 back compositing, every composited hit recorded per ray.
-// k_ff_aggregate  one workgroup per receiver: replays the records, LDS hash
+// k_ff_trace      one workgroup per group of receivers, lanes taking rays
+//                 from a direction-sorted pool: multi-round k-buffer
+//                 traversal (the KB nearest hits beyond the last composited
+//                 key per round, keys (t, j)), front-to-back compositing,
+//                 every composited hit recorded per ray.
+// k_ff_aggregate  one workgroup per receiver: replays the records (two
+//                 threads per ray when they fit), LDS hash
 //                 table with 2^-40 fixed-point sums (integer adds are order
 //                 independent, so F is bit-deterministic), radix select of
 //                 the top-k entries, bitonic sort by column, one ELL row.
@@ -411,32 +413,44 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
     }
     if (tid == 0) habort = 0;
     __syncthreads();
-    for (int r = tid; r < R; r += 256) {
+    // Two threads per ray when 2R <= 256: the first inserts the ray's first
+    // half of the hits, the second its second half, starting from the
+    // transmittance it finds by multiplying through the first half in the
+    // same order (so T is bit-identical to one thread's walk).
+    const int split = 2 * R <= 256 ? 2 : 1;
+    for (int t = tid; t < split * R; t += 256) {
+        const int r = t % R, h = t / R;
         const uint32_t m = min(rcnt[slot * R + r], (uint32_t)rcap);
         const uint2 *in = recs + slot * rcap * R + r;
+        const uint32_t qmid = split == 2 ? (m + 1) / 2 : 0;
+        const uint32_t qa = h == 0 ? 0 : qmid, qb = (split == 2 && h == 0) ? qmid : m;
         float T = 1.0f;
+        for (uint32_t q = 0; q < qa; ++q) {
+            const uint2 hq = in[(int64_t)q * R];
+            T = __fmul_rn(T, exp_fx(-(bv.c[hq.x] * fabsf(__uint_as_float(hq.y)))));
+        }
         // the record one step ahead and its sender's c, the record two
         // steps ahead: each load has a record's work to land
-        uint2 h1 = m > 0 ? in[0] : make_uint2(0u, 0u);
-        uint2 h2 = m > 1 ? in[(int64_t)R] : make_uint2(0u, 0u);
-        float c1 = m > 0 ? bv.c[h1.x] : 0.0f;
-        for (uint32_t q = 0; q < m; ++q) {
+        uint2 h1 = qa < qb ? in[(int64_t)qa * R] : make_uint2(0u, 0u);
+        uint2 h2 = qa + 1 < qb ? in[(int64_t)(qa + 1) * R] : make_uint2(0u, 0u);
+        float c1 = qa < qb ? bv.c[h1.x] : 0.0f;
+        for (uint32_t q = qa; q < qb; ++q) {
             if ((q & 7) == 0 && *abort_v) break;
-            const uint2 h = h1;
+            const uint2 hr = h1;
             const float cq = c1;
             h1 = h2;
-            if (q + 2 < m) h2 = in[(int64_t)(q + 2) * R];
-            if (q + 1 < m) c1 = bv.c[h1.x];
-            const float gs = __uint_as_float(h.y);
+            if (q + 2 < qb) h2 = in[(int64_t)(q + 2) * R];
+            if (q + 1 < qb) c1 = bv.c[h1.x];
+            const float gs = __uint_as_float(hr.y);
             const float x = cq * fabsf(gs);
             if (gs > 0.0f) {
                 const float w = -expm1f(-x) * T;
                 const unsigned long long fx = (unsigned long long)__float2ull_rn(w * kFixScaleF);
-                uint32_t hs = hash_slot(h.x, log2h);
+                uint32_t hs = hash_slot(hr.x, log2h);
                 int probe = 0;
                 for (; probe < max_probe; ++probe) {
-                    const uint32_t prev = atomicCAS(&hkey[hs], kEmpty, h.x);
-                    if (prev == kEmpty || prev == h.x) {
+                    const uint32_t prev = atomicCAS(&hkey[hs], kEmpty, hr.x);
+                    if (prev == kEmpty || prev == hr.x) {
                         atomicAdd(&hval[hs], fx);
                         break;
                     }
