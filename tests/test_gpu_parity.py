@@ -373,6 +373,28 @@ def test_opacity_backward_is_bit_identical_between_runs(g):
             assert torch.equal(r, runs[0])
 
 
+@pytest.mark.parametrize("R", [1, 100, 1500])
+def test_recorded_hits_equal_the_walk_for_ragged_ray_pools(g, R):
+    """The form-factor trace hands rays out to lanes from pools of up to 1024
+    (R = 1: one ray of each of 1024 receivers; R = 100: pools of 1000;
+    R = 1500: a full pool and a ragged one per receiver).  The opacity
+    gradient from its records equals, bit for bit, the one recomputed by the
+    plain per-ray walk, so every ray's recorded hits are the walk's."""
+    sc = _scene("fruit_bowl", n=1500)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    out = []
+    for records in (True, False):
+        ff = g.form_factors(bvh, R, sc.seed, t_min=1e-4, records=records)
+        nnz = ff.info()[1]
+        gF = dev(np.random.default_rng(7).standard_normal(nnz).astype(np.float32))
+        out.append((gpu_csr(ff), g.opacity_backward(bvh, ff, gF, None, None)[0]))
+    (Fa, ga), (Fb, gb) = out
+    assert np.array_equal(Fa.indptr, Fb.indptr) and np.array_equal(Fa.indices, Fb.indices)
+    assert np.array_equal(Fa.data.view(np.uint32), Fb.data.view(np.uint32))
+    assert ga.abs().max() > 0
+    assert torch.equal(ga, gb)
+
+
 def test_opacity_backward_scale_follows_the_gradient_size(g, orc):
     """The fixed-point scale is derived from max |dL/dF|: a dL/dF scaled by
     2^-60 or 2^40 gives the gradient scaled exactly the same way."""
