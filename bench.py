@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 122587.32e6, "write": 11505.01e6,
+    "ff_trace": {"fetch": 131844.12e6, "write": 11609.30e6,
                  "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "4829ceb15a38f90bb38a6e35bcfa89413f0e43f210810b329df5e71265a5f132",
+                 "sha256": "728d905814828c17fb929b5429f4519d135f9354f36f05d7c27ad031bc16cbb5",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
     "dense_grad_F": {"fetch": 236949.39e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],

@@ -47,8 +47,16 @@ __device__ __forceinline__ uint32_t dir_key(float dx, float dy, float dz) {
 constexpr int kPoolRays = 1024;   // rays sorted and pooled per batch
 constexpr int kCompChunk = 5;     // buffered hits whose kernel values are found together
 // a wave composites once kFlushNum / kFlushDen of its lanes holding rays wait
-// (measured: 1/2 and 3/8 best, 1/4 and 5/8 about 2 % slower, 3/4 and 1/8 more)
-constexpr int kFlushNum = 1, kFlushDen = 2;
+constexpr int kFlushNum = 3, kFlushDen = 8;
+// leaf children found by a node step wait in a per-lane queue of kLeafQ;
+// a wave tests one queued leaf per lane once kLeafNum / kLeafDen of its
+// lanes holding rays have one (or a queue is full, or no lane can step), so
+// the costly leaf test and k-buffer insertion run with more lanes at once.
+// Measured on the 100k fruit bowl: queues of 8 and a composite at 3/8 best
+// (queue 6: +0.6 ms; composite at 1/2: +1.4 ms, at 1/4: +3.7 ms; leaf
+// steps at 3/4 as good as at 1/2, at 1/4 +6 ms).
+constexpr int kLeafQ = 8;
+constexpr int kLeafNum = 1, kLeafDen = 2;
 
 // Lane index within the wave, recomputed at each use (volatile: not hoisted
 // out of the traversal loop into a register of its own).
@@ -71,11 +79,12 @@ __device__ __forceinline__ int lane_index() {
 // rays sorted by direction key, and the lanes pull rays from the sorted
 // pool through an LDS counter, so neighbouring lanes trace rays that leave
 // close origins in close directions.  Each lane walks its ray one node per
-// iteration; a lane whose k-buffer round ends waits until enough lanes of
-// its wave wait, the wave then composites them together, and a lane whose
-// ray ends takes the next ray of the pool at once instead of idling until
-// the wave's longest ray is done (the same hits, composited in the same
-// order, as the plain per-ray walk).  Three waves per SIMD (at most 168
+// iteration, queueing the leaves it reaches; the wave tests queued leaves
+// once half of its lanes hold one; a lane whose k-buffer round ends waits
+// until enough lanes of its wave wait, the wave then composites them
+// together, and a lane whose ray ends takes the next ray of the pool at
+// once instead of idling until the wave's longest ray is done (the same
+// hits, composited in the same order, as the plain per-ray walk).  Three waves per SIMD (at most 168
 // VGPRs), held by a launch bound; four (at most 128) were measured no
 // faster.
 template <int STK>
@@ -142,9 +151,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
             __syncthreads();
             continue;
         }
-        // Lanes hold rays in one of two states: traversing (one node per
-        // iteration of the inner loop) or waiting, their k-buffer round done,
-        // to composite.  Compositing is costly per hit (the FP64 hit point,
+        // Lanes hold rays in one of two states: traversing (one node or one
+        // queued leaf per iteration of the inner loop) or waiting, their
+        // k-buffer round done, to composite.  Compositing is costly per hit (the FP64 hit point,
         // two exponentials), so the wave composites its waiting lanes
         // together, once they are kFlushNum / kFlushDen of the lanes holding
         // rays or no lane traverses.  The node steps have a loop of their
@@ -164,6 +173,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
 #pragma unroll
         for (int k = 0; k < kKB; ++k) key[k] = __longlong_as_double((long long)kKeyEmpty);
         int found = 0, sp = 0, node = 0;
+        // queued leaves (LIFO; the order of the leaf tests does not change
+        // the round's buffer: it keeps the KB smallest keys whatever the
+        // order), and whether the round's walk of the tree is done
+        int lq[kLeafQ];
+#pragma unroll
+        for (int k = 0; k < kLeafQ; ++k) lq[k] = 0;
+        int qn = 0;
+        bool walked = false;
         // a new k-buffer round from the root, beyond the last composited key
         auto start_round = [&]() {
 #pragma unroll
@@ -173,6 +190,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
             t1 = INFINITY;
             sp = 0;
             node = 0;
+            qn = 0;
+            walked = false;
             trav = true;
         };
         auto end_ray = [&]() {
@@ -279,24 +298,44 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
                 }
                 continue;
             }
-            // node steps until a flush is due or a lane needs a ray
+            // node and leaf steps until a flush is due or a lane needs a ray
             for (;;) {
-                if (trav) {
+                const bool can = trav && !walked && qn <= kLeafQ - 2;
+                const int nq = __popcll(__ballot(qn > 0));
+                const bool leaf_step =
+                    nq > 0 && (kLeafDen * nq >= kLeafNum * nact || !__ballot(can) || __ballot(qn > kLeafQ - 2));
+                // per-lane conditions (a uniform if / else here made the
+                // compiler copy the k-buffer between register sets)
+                const bool do_leaf = leaf_step && qn > 0, do_node = !leaf_step && can;
+                if (do_leaf) {
+                    --qn;
+                    int s = lq[0];
+#pragma unroll
+                    for (int k = 1; k < kLeafQ; ++k) s = qn == k ? lq[k] : s;
+                    visit_leaf<kKB>(bv.rec, s, i, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
+                }
+                if (do_node) {
                     const Node nd = bv.nodes[node];
                     float tn0, tn1;
                     bool h0 = slab(nd.b0.x, nd.b0.y, nd.b0.z, nd.b0.w, nd.b1.x, nd.b1.y, ox, oy, oz, ix, iy, iz, t0, t1, tn0);
                     bool h1 = slab(nd.b1.z, nd.b1.w, nd.b2.x, nd.b2.y, nd.b2.z, nd.b2.w, ox, oy, oz, ix, iy, iz, t0, t1, tn1);
                     const int c0 = nd.ch.x, c1 = nd.ch.y;
+                    auto queue_leaf = [&](int leaf) {
+#pragma unroll
+                        for (int k = 0; k < kLeafQ; ++k) lq[k] = qn == k ? leaf : lq[k];
+                        ++qn;
+                    };
                     if (h0 && c0 < 0) {
-                        visit_leaf<kKB>(bv.rec, ~c0, i, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
+                        queue_leaf(~c0);
                         h0 = false;
                     }
                     if (h1 && c1 < 0) {
-                        visit_leaf<kKB>(bv.rec, ~c1, i, ox, oy, oz, dx, dy, dz, t_eps, last, key, found, t1);
+                        queue_leaf(~c1);
                         h1 = false;
                     }
                     // descend into the nearer hit child and push the other;
-                    // with no child left, pop; an empty stack ends the round.
+                    // with no child left, pop; an empty stack ends the walk
+                    // (the round ends once the queued leaves are tested too).
                     // A push past the stack's end ends the ray with an error
                     // (the launch is repeated with the deep stack).
                     const bool both = h0 && h1;
@@ -310,7 +349,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
                     sp += both ? 1 : 0;
                     node = n0 ? c0 : c1;
                     if (!h0 && !h1) {
-                        if (sp == 0) trav = false;
+                        if (sp == 0) walked = true;
                         else {
                             --sp;
                             node = (int)stack[sp * 256];
@@ -319,8 +358,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
                     if (ovf) {
                         atomicOr(err, kErrStack);
                         end_ray();
+                        qn = 0;
                     }
                 }
+                if (trav && walked && qn == 0) trav = false;   // the round's hits are all tested
                 const int nw = __popcll(__ballot(have && !trav));
                 if ((nw > 0 && (kFlushDen * nw >= kFlushNum * nact || nw == nact)) || __ballot(!have && !drained)) break;
             }
