@@ -51,6 +51,13 @@ TRAFFIC = {
 }
 
 
+def _updates(count, ms):
+    """Surfel-light updates per second: one update is a surfel's K x 3
+    coefficients for one light in one bounce (or adjoint step); ms is the
+    step's time in those launches."""
+    return count / (ms * 1e-3) if ms and ms > 0 else None
+
+
 def calibration_copy(args, torch, dev):
     """A plain elementwise copy that reads and writes calib_copy_mib MiB
     each: its FETCH_SIZE / WRITE_SIZE counters calibrate the ones of the
@@ -230,6 +237,8 @@ def main():
                                f"SH K={K}, {Lt} light, {nb} bounces, fwd+bwd (MSE-style grad_B)",
                    "surfels": N, "rays_per_surfel": R, "topk": topk, "K": K, "lights": Lt, "bounces": nb},
         "grays_per_s": grays,
+        "bounce_updates_per_s": _updates(nb * N * Lt, phases.get("bounce", 0.0)),
+        "adjoint_updates_per_s": _updates(nb * N * Lt, phases.get("adjoint", 0.0)),
         "fwd_bwd_solves_per_s_fixed_F": (1e3 / t_solve_bwd) if t_solve_bwd > 0 else None,
         "form_factor_ms": t_ff,
         "nnz": nnz,
@@ -757,6 +766,8 @@ def multi_light(args, g, scenes, torch, np):
                    "surfels": N, "lights": Lt, "K": K, "bounces": nb, "columns": C, "nnz": nnz},
         "transport_ms": t_transport,
         "transport_solves_per_s": 1e3 / t_transport if t_transport > 0 else None,
+        "bounce_updates_per_s": _updates(nb * N * Lt, phases.get("dense_bounce", 0.0) + phases.get("dense_bounce_fix", 0.0)),
+        "adjoint_updates_per_s": _updates(nb * N * Lt, phases.get("dense_adjoint", 0.0) + phases.get("dense_adjoint_fix", 0.0)),
         "fp32_per_light_fwd_bwd_ms": t_fp32 * 1e3,
         "fp32_lights_timed": nl,
         "speedup_vs_fp32_per_light": (t_fp32 * 1e3) / t_transport if t_transport > 0 else None,
@@ -880,6 +891,8 @@ def uneven_batch(args, g, scenes, torch, np, lights=(8, 100), topk=512):
         "speedup_vs_per_scene": t_scene / t_batch if t_batch > 0 else None,
         "lanes_per_row": {"bounce": info["lanes_bounce"], "adjoint": info["lanes_adjoint"]},
         "grays_per_s": rays / (avg("ff_trace") * 1e-3) / 1e9 if avg("ff_trace") > 0 else None,
+        "bounce_updates_per_s": _updates(nb * sum(sc.n * l for sc, l in zip(rooms, Lts)), phases.get("batch_bounces", 0.0)),
+        "adjoint_updates_per_s": _updates(nb * sum(sc.n * l for sc, l in zip(rooms, Lts)), phases.get("batch_adjoint", 0.0)),
         "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())},
         "roofline": {"kernel": "batch_bounces", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS if achieved else None,
