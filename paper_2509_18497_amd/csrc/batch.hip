@@ -117,6 +117,8 @@ __global__ void __launch_bounds__(256) k_ragged_spmm(BatchDev bd, const int64_t 
 // grad_F[e] = sum_k sum_c rho_row,c%3 lam^(k+1)[row][c] B^(k)[j][c] and
 // grad_rho[row][colour] = sum_e F[e] sum_k sum_{c of colour} (same), one
 // wave per row (tapes [nb][vals]).
+constexpr int kSddE = 12;   // entries per pass (measured on 64 uneven rooms: 1 entry 10.6 s, 2: 7.9, 4: 6.5, 8: 5.8, 12: 5.6, 16: 5.4 s with 206 VGPRs)
+
 __global__ void __launch_bounds__(256) k_ragged_sddmm(BatchDev bd, const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const float *__restrict__ val, int nb, int64_t vals,
@@ -135,29 +137,51 @@ __global__ void __launch_bounds__(256) k_ragged_sddmm(BatchDev bd, const int64_t
         const int64_t b = row_ptr[row], e = row_ptr[row + 1];
         const float rr0 = rho[row * 3 + 0], rr1 = rho[row * 3 + 1], rr2 = rho[row * 3 + 2];
         float gr0 = 0.0f, gr1 = 0.0f, gr2 = 0.0f;
-        for (int64_t k = b; k < e; ++k) {
-            const int64_t j = col[k];
-            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        // kSddE entries per pass: the row's lambda value of a (column, bounce)
+        // is read once for all of them, and their gathers are in flight
+        // together; each entry's sums run in the order of one at a time
+        for (int64_t k = b; k < e; k += kSddE) {
+            const int m = (int)min<int64_t>(kSddE, e - k);
+            int64_t jj[kSddE];
+#pragma unroll
+            for (int u = 0; u < kSddE; ++u) jj[u] = (u < m ? col[k + u] : col[k]) - r0;
+            float s0[kSddE], s1[kSddE], s2[kSddE];
+#pragma unroll
+            for (int u = 0; u < kSddE; ++u) s0[u] = s1[u] = s2[u] = 0.0f;
             for (int c = lane; c < C; c += 64) {
-                float sum = 0.0f;
-                for (int t = 0; t < nb; ++t)
-                    sum = __builtin_fmaf(Lt[t * vals + base + lr * C + c], Bt[t * vals + base + (j - r0) * C + c], sum);
+                float sum[kSddE];
+#pragma unroll
+                for (int u = 0; u < kSddE; ++u) sum[u] = 0.0f;
+                for (int t = 0; t < nb; ++t) {
+                    const float l = Lt[t * vals + base + lr * C + c];
+#pragma unroll
+                    for (int u = 0; u < kSddE; ++u)
+                        sum[u] = __builtin_fmaf(l, Bt[t * vals + base + jj[u] * C + c], sum[u]);
+                }
                 const int colour = c % 3;
-                s0 += colour == 0 ? sum : 0.0f;
-                s1 += colour == 1 ? sum : 0.0f;
-                s2 += colour == 2 ? sum : 0.0f;
+#pragma unroll
+                for (int u = 0; u < kSddE; ++u) {
+                    s0[u] += colour == 0 ? sum[u] : 0.0f;
+                    s1[u] += colour == 1 ? sum[u] : 0.0f;
+                    s2[u] += colour == 2 ? sum[u] : 0.0f;
+                }
             }
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                s0 += __shfl_xor(s0, o, 64);
-                s1 += __shfl_xor(s1, o, 64);
-                s2 += __shfl_xor(s2, o, 64);
+            for (int u = 0; u < kSddE; ++u) {
+                if (u >= m) break;
+                float a0 = s0[u], a1 = s1[u], a2 = s2[u];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    a0 += __shfl_xor(a0, o, 64);
+                    a1 += __shfl_xor(a1, o, 64);
+                    a2 += __shfl_xor(a2, o, 64);
+                }
+                if (lane == 0 && grad_F) grad_F[k + u] = rr0 * a0 + rr1 * a1 + rr2 * a2;
+                const float f = val[k + u];
+                gr0 = __builtin_fmaf(f, a0, gr0);
+                gr1 = __builtin_fmaf(f, a1, gr1);
+                gr2 = __builtin_fmaf(f, a2, gr2);
             }
-            if (lane == 0 && grad_F) grad_F[k] = rr0 * s0 + rr1 * s1 + rr2 * s2;
-            const float f = val[k];
-            gr0 = __builtin_fmaf(f, s0, gr0);
-            gr1 = __builtin_fmaf(f, s1, gr1);
-            gr2 = __builtin_fmaf(f, s2, gr2);
         }
         if (lane == 0 && grad_rho) {
             grad_rho[row * 3 + 0] = gr0;

@@ -144,6 +144,8 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+constexpr int kSddE = 12;   // entries per pass of the general SDDMM (16: slower, 206 VGPRs)
+
 // For each stored entry e = (row, j):
 //   s_c = sum_k sum_{cols of colour c} lam^(k+1)[row] * B^(k)[j]
 //   grad_F[e] = sum_c rho[row, c] s_c ;  grad_rho[row, c] = sum_e F[e] s_c
@@ -160,25 +162,44 @@ __global__ void __launch_bounds__(256) k_sddmm(const int64_t *__restrict__ row_p
     const int64_t NC = n * (int64_t)C;
     const float r0 = rho[row * 3 + 0], r1 = rho[row * 3 + 1], r2 = rho[row * 3 + 2];
     float gr0 = 0.0f, gr1 = 0.0f, gr2 = 0.0f;
-    for (int64_t k = b; k < e; ++k) {
-        const int64_t j = col[k];
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+    // kSddE entries per pass: the row's lambda value of a (column, bounce) is
+    // read once for all of them, and their gathers are in flight together;
+    // each entry's sums run in the order of one entry at a time
+    for (int64_t k = b; k < e; k += kSddE) {
+        const int m = (int)min<int64_t>(kSddE, e - k);
+        int64_t jj[kSddE];
+#pragma unroll
+        for (int u = 0; u < kSddE; ++u) jj[u] = u < m ? col[k + u] : col[k];
+        float s0[kSddE], s1[kSddE], s2[kSddE];
+#pragma unroll
+        for (int u = 0; u < kSddE; ++u) s0[u] = s1[u] = s2[u] = 0.0f;
         for (int c = lane; c < C; c += 64) {
-            float s = 0.0f;
-            for (int q = 0; q < nb; ++q) s = __builtin_fmaf(Lt[q * NC + row * C + c], Bt[q * NC + j * C + c], s);
+            float sum[kSddE];
+#pragma unroll
+            for (int u = 0; u < kSddE; ++u) sum[u] = 0.0f;
+            for (int q = 0; q < nb; ++q) {
+                const float l = Lt[q * NC + row * C + c];
+#pragma unroll
+                for (int u = 0; u < kSddE; ++u) sum[u] = __builtin_fmaf(l, Bt[q * NC + jj[u] * C + c], sum[u]);
+            }
             const int colour = c % 3;
-            s0 += colour == 0 ? s : 0.0f;
-            s1 += colour == 1 ? s : 0.0f;
-            s2 += colour == 2 ? s : 0.0f;
+#pragma unroll
+            for (int u = 0; u < kSddE; ++u) {
+                s0[u] += colour == 0 ? sum[u] : 0.0f;
+                s1[u] += colour == 1 ? sum[u] : 0.0f;
+                s2[u] += colour == 2 ? sum[u] : 0.0f;
+            }
         }
-        s0 = wave_sum(s0);
-        s1 = wave_sum(s1);
-        s2 = wave_sum(s2);
-        if (lane == 0 && grad_F) grad_F[k] = r0 * s0 + r1 * s1 + r2 * s2;
-        const float f = val[k];
-        gr0 = __builtin_fmaf(f, s0, gr0);
-        gr1 = __builtin_fmaf(f, s1, gr1);
-        gr2 = __builtin_fmaf(f, s2, gr2);
+#pragma unroll
+        for (int u = 0; u < kSddE; ++u) {
+            if (u >= m) break;
+            const float a0 = wave_sum(s0[u]), a1 = wave_sum(s1[u]), a2 = wave_sum(s2[u]);
+            if (lane == 0 && grad_F) grad_F[k + u] = r0 * a0 + r1 * a1 + r2 * a2;
+            const float f = val[k + u];
+            gr0 = __builtin_fmaf(f, a0, gr0);
+            gr1 = __builtin_fmaf(f, a1, gr1);
+            gr2 = __builtin_fmaf(f, a2, gr2);
+        }
     }
     if (lane == 0 && grad_rho) {
         grad_rho[row * 3 + 0] = gr0;
