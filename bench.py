@@ -42,7 +42,7 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 TRAFFIC = {
     "ff_trace": {"fetch": 131844.12e6, "write": 11609.30e6,
                  "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "728d905814828c17fb929b5429f4519d135f9354f36f05d7c27ad031bc16cbb5",
+                 "sha256": "6b1ebc90f0a50a565cb042d7cb48fea26e21a59f11db5fc1d04992b8fd5ef4b6",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
     "dense_grad_F": {"fetch": 236949.39e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],

@@ -45,7 +45,7 @@ struct DevBuf {
     gsrad_status ensure(size_t want, const char *what) {
         if (want <= bytes && p) return GSRAD_OK;
         if (p) {
-            hipFree(p);
+            (void)hipFree(p);
             p = nullptr;
             bytes = 0;
         }
@@ -61,7 +61,7 @@ struct DevBuf {
         return GSRAD_OK;
     }
     void release() {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -109,13 +109,13 @@ struct ProfScope {
         if (!g_prof) return;
         r.name = name;
         r.a = prof_event();
-        if (r.a) hipEventRecord(r.a, st);
+        if (r.a) (void)hipEventRecord(r.a, st);
     }
     ~ProfScope() {
         if (!g_prof || !r.a) return;
         r.b = prof_event();
         if (!r.b) return;
-        hipEventRecord(r.b, st);
+        (void)hipEventRecord(r.b, st);
         g_recs.push_back(r);
     }
 };

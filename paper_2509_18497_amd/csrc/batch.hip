@@ -200,19 +200,20 @@ __global__ void __launch_bounds__(256) k_ragged_sddmm(BatchDev bd, const int64_t
             }
 #pragma unroll
             for (int u = 0; u < kSddE; ++u) {
-                if (u >= m) break;
-                float a0 = s0[u], a1 = s1[u], a2 = s2[u];
+                if (u < m) {
+                    float a0 = s0[u], a1 = s1[u], a2 = s2[u];
 #pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) {
-                    a0 += __shfl_xor(a0, o, 64);
-                    a1 += __shfl_xor(a1, o, 64);
-                    a2 += __shfl_xor(a2, o, 64);
+                    for (int o = 32; o >= 1; o >>= 1) {
+                        a0 += __shfl_xor(a0, o, 64);
+                        a1 += __shfl_xor(a1, o, 64);
+                        a2 += __shfl_xor(a2, o, 64);
+                    }
+                    if (lane == 0 && grad_F) grad_F[k + u] = rr0 * a0 + rr1 * a1 + rr2 * a2;
+                    const float f = val[k + u];
+                    gr0 = __builtin_fmaf(f, a0, gr0);
+                    gr1 = __builtin_fmaf(f, a1, gr1);
+                    gr2 = __builtin_fmaf(f, a2, gr2);
                 }
-                if (lane == 0 && grad_F) grad_F[k + u] = rr0 * a0 + rr1 * a1 + rr2 * a2;
-                const float f = val[k + u];
-                gr0 = __builtin_fmaf(f, a0, gr0);
-                gr1 = __builtin_fmaf(f, a1, gr1);
-                gr2 = __builtin_fmaf(f, a2, gr2);
             }
         }
         if (lane == 0 && grad_rho) {

@@ -280,13 +280,14 @@ __global__ void __launch_bounds__(256) k_sddmm(const int64_t *__restrict__ row_p
         }
 #pragma unroll
         for (int u = 0; u < kSddE; ++u) {
-            if (u >= m) break;
-            const float a0 = wave_sum(s0[u]), a1 = wave_sum(s1[u]), a2 = wave_sum(s2[u]);
-            if (lane == 0 && grad_F) grad_F[k + u] = r0 * a0 + r1 * a1 + r2 * a2;
-            const float f = val[k + u];
-            gr0 = __builtin_fmaf(f, a0, gr0);
-            gr1 = __builtin_fmaf(f, a1, gr1);
-            gr2 = __builtin_fmaf(f, a2, gr2);
+            if (u < m) {
+                const float a0 = wave_sum(s0[u]), a1 = wave_sum(s1[u]), a2 = wave_sum(s2[u]);
+                if (lane == 0 && grad_F) grad_F[k + u] = r0 * a0 + r1 * a1 + r2 * a2;
+                const float f = val[k + u];
+                gr0 = __builtin_fmaf(f, a0, gr0);
+                gr1 = __builtin_fmaf(f, a1, gr1);
+                gr2 = __builtin_fmaf(f, a2, gr2);
+            }
         }
     }
     if (lane == 0 && grad_rho) {

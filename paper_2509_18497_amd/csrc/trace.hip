@@ -1102,7 +1102,7 @@ gsrad_status launch_opacity_bwd(const BvhDev &bv, int R, uint64_t seed, float t_
     const size_t smem = (size_t)max_row * 8 + ff_stack_bytes(threads);
     static bool attr_set = false;
     if (!attr_set) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_opacity_bwd), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_opacity_bwd), hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024 - 4096);
         attr_set = true;
     }
@@ -1121,7 +1121,7 @@ gsrad_status launch_opacity_rec(const BvhDev &bv, int R, const uint2 *recs, cons
     const size_t smem = (size_t)(1 << log2h) * 8;
     static bool attr_set = false;
     if (!attr_set) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_opacity_rec), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_opacity_rec), hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024 - 4096);
         attr_set = true;
     }
