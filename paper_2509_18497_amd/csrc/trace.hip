@@ -773,6 +773,17 @@ __device__ __forceinline__ float row_lookup(const uint32_t *lc, const float *lg,
 // the workgroup: every workgroup that touches copy x runs on XCD x), and
 // k_opacity_finish adds the copies.
 // One hit of the second walk: the sender's contribution to dL/do.
+// The same with the sender's c_j and raw opacity already loaded.
+__device__ __forceinline__ void opacity_hit_c(uint32_t j, float G, float alpha, float f, float T, float g, float cj,
+                                              float oraw, DF W, DF &P, unsigned long long *acc, float scale) {
+    if (G != 0.0f) P = df_add(P, df_prod3(G, alpha, T));
+    if (!(oraw > 0.0f && oraw < kOpacityMax)) return;
+    const DF Sd = df_add(W, DF{-P.hi, -P.lo});
+    const float dLda = G * T - Sd.hi / f;
+    const float dado = g * expf(cj * (1.0f - g));
+    fx_add(acc + j, dLda * dado, scale);
+}
+
 __device__ __forceinline__ void opacity_hit(const BvhDev &bv, uint32_t j, float G, float alpha, float f, float T,
                                             float g, DF W, DF &P, unsigned long long *acc, float scale) {
     if (G != 0.0f) P = df_add(P, df_prod3(G, alpha, T));
@@ -894,29 +905,53 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
         const uint32_t m = rcnt[(int64_t)i * R + r];
         if (m > (uint32_t)rcap) continue;
         const uint2 *in = recs + (int64_t)i * rcap * R + r;
+        // Records are loaded two hits ahead and the sender's constants one
+        // ahead.  In the second pass those loads are issued before the
+        // current hit's atomic add: the memory counter the waits use is in
+        // order, so a load issued after an atomic could only be waited for
+        // together with the atomic.
         DF W{0.0f, 0.0f};
         float T = 1.0f;
-        for (uint32_t q = 0; q < m; ++q) {
-            const uint2 h = in[(int64_t)q * R];
-            const float gs = __uint_as_float(h.y);
-            const float x = bv.c[h.x] * fabsf(gs);
-            if (gs > 0.0f) {
-                const float G = row_hash_lookup(hk, hv, log2h, h.x);
-                if (G != 0.0f) W = df_add(W, df_prod3(G, -expm1f(-x), T));
+        {
+            uint2 h1 = m > 0 ? in[0] : make_uint2(0u, 0u);
+            uint2 h2 = m > 1 ? in[(int64_t)R] : make_uint2(0u, 0u);
+            float c1 = m > 0 ? bv.c[h1.x] : 0.0f;
+            for (uint32_t q = 0; q < m; ++q) {
+                const uint2 h = h1;
+                const float cq = c1;
+                h1 = h2;
+                if (q + 2 < m) h2 = in[(int64_t)(q + 2) * R];
+                if (q + 1 < m) c1 = bv.c[h1.x];
+                const float gs = __uint_as_float(h.y);
+                const float x = cq * fabsf(gs);
+                if (gs > 0.0f) {
+                    const float G = row_hash_lookup(hk, hv, log2h, h.x);
+                    if (G != 0.0f) W = df_add(W, df_prod3(G, -expm1f(-x), T));
+                }
+                T = __fmul_rn(T, exp_fx(-x));
             }
-            T = __fmul_rn(T, exp_fx(-x));
         }
         if (W.hi == 0.0f) continue;   // every G_q alpha_q T_q is 0: no contribution
         DF P{0.0f, 0.0f};
         T = 1.0f;
+        uint2 h1 = in[0];
+        uint2 h2 = m > 1 ? in[(int64_t)R] : make_uint2(0u, 0u);
+        float c1 = bv.c[h1.x], o1 = bv.raw_op[h1.x];
         for (uint32_t q = 0; q < m; ++q) {
-            const uint2 h = in[(int64_t)q * R];
+            const uint2 h = h1;
+            const float cq = c1, oq = o1;
+            h1 = h2;
+            if (q + 2 < m) h2 = in[(int64_t)(q + 2) * R];
+            if (q + 1 < m) {
+                c1 = bv.c[h1.x];
+                o1 = bv.raw_op[h1.x];
+            }
             const float gs = __uint_as_float(h.y);
             const float g = fabsf(gs);
-            const float x = bv.c[h.x] * g;
+            const float x = cq * g;
             const float f = exp_fx(-x);
             const float G = gs > 0.0f ? row_hash_lookup(hk, hv, log2h, h.x) : 0.0f;
-            opacity_hit(bv, h.x, G, -expm1f(-x), f, T, g, W, P, my, scale);
+            opacity_hit_c(h.x, G, -expm1f(-x), f, T, g, cq, oq, W, P, my, scale);
             T = __fmul_rn(T, f);
         }
     }
