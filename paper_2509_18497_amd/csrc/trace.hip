@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
     // key region, FP32 values in the first half of the value region
     uint32_t *cj = hkey;
     float *cv = reinterpret_cast<float *>(hval);
-    __shared__ uint32_t hist[256], wsum[4], dsel, before_sh, habort, ticket;
+    __shared__ uint32_t hist[256], wsum[4], dsel, before_sh, dcnt, habort, ticket;
     volatile uint32_t *abort_v = &habort;
     const int tid = threadIdx.x;
     for (;;) {
@@ -575,6 +575,7 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
                     if (run < need && need <= run + c4[q]) {
                         dsel = (uint32_t)(4 * tid + q);
                         before_sh = run;
+                        dcnt = c4[q];
                     }
                     run += c4[q];
                 }
@@ -583,7 +584,14 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
             prefix |= (uint64_t)dsel << shift;
             pmask |= 255ull << shift;
             need -= before_sh;
+            const uint32_t in_bucket = dcnt;
             __syncthreads();
+            // the topk-th key is the largest of the selected digit's keys:
+            // all of them are kept, the lower digits need no pass
+            if (need == in_bucket) {
+                prefix |= ~pmask;
+                break;
+            }
         }
         // keep badness <= prefix (exactly topk entries: keys are unique),
         // compacted in place through registers
@@ -622,8 +630,13 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
     while (P < m) P <<= 1;
     for (uint32_t e = m + tid; e < P; e += 256) cj[e] = kEmpty;
     __syncthreads();
+    // A stage of stride below 64 pairs entries within the 128-entry span
+    // t / 64 of each of its pair indices t, which only one wave takes: such
+    // a stage needs a workgroup barrier only next to a stage of a wider
+    // stride, a wave's own order otherwise.
     for (uint32_t size = 2; size <= P; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t next = stride > 1 ? stride >> 1 : (2 * size <= P ? size : 0);
             for (uint32_t t = tid; t < P / 2; t += 256) {
                 const uint32_t idx = 2 * stride * (t / stride) + (t % stride);
                 const uint32_t par = idx + stride;
@@ -637,9 +650,15 @@ __global__ void __launch_bounds__(256) k_ff_aggregate(BvhDev bv, const uint2 *__
                     cv[par] = va;
                 }
             }
-            __syncthreads();
+            if (stride >= 64 || next >= 64) {
+                __syncthreads();
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
         }
     }
+    __syncthreads();
     if (m > cap_row) {
         if (tid == 0) atomicOr(err, kErrRow);
         m = (uint32_t)cap_row;
