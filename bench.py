@@ -42,7 +42,7 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 TRAFFIC = {
     "ff_trace": {"fetch": 131844.12e6, "write": 11609.30e6,
                  "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "bb2d8eea91be2bd35637b3efc668ffefdcdd5fa797d5fce35c9b6df593a32b35",
+                 "sha256": "57befa781977c6304fb4156158c7b70d88e7f7d017ee7b023636f709063f4be6",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
     "dense_grad_F": {"fetch": 236949.39e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],

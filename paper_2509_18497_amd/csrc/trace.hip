@@ -906,8 +906,22 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
     const int64_t b = xcd_block(blockIdx.x, nblocks);
     const int tid = threadIdx.x;
     const uint32_t i = __float_as_uint(bv.rec[b].d.w);
+    // With one ray per thread, the threads take the rays in ascending order
+    // of their record counts (a counting sort on min(count, 63); rays past
+    // the cap count as 0), so that each wave's rays are alike in length.
+    // Which thread takes a ray changes no sum: the per-ray arithmetic is
+    // the ray's own and the fixed-point adds commute.
+    __shared__ uint32_t bucket[64], ray_of[256];
+    const bool by_len = R == (int)blockDim.x;
+    if (by_len && tid < 64) bucket[tid] = 0;
     for (int k = tid; k < H; k += blockDim.x) hk[k] = kEmpty;
     __syncthreads();
+    uint32_t bk = 0;
+    if (by_len) {
+        const uint32_t m0 = rcnt[(int64_t)i * R + tid];
+        bk = m0 > (uint32_t)rcap ? 0u : min(m0, 63u);
+        atomicAdd(&bucket[bk], 1u);
+    }
     const int64_t e0 = row_ptr[i];
     const int len = (int)(row_ptr[i + 1] - e0);
     const float invR = 1.0f / (float)R;
@@ -920,7 +934,17 @@ __global__ void __launch_bounds__(256) k_opacity_rec(BvhDev bv, int R, const uin
         hv[h] = gF[e0 + k] * invR;
     }
     __syncthreads();
-    for (int r = tid; r < R; r += blockDim.x) {
+    if (by_len) {
+        if (tid < 64) {
+            const uint32_t v = bucket[tid];
+            bucket[tid] = wave_incl_scan_u32(v) - v;
+        }
+        __syncthreads();
+        ray_of[atomicAdd(&bucket[bk], 1u)] = (uint32_t)tid;
+        __syncthreads();
+    }
+    for (int t = tid; t < R; t += blockDim.x) {
+        const int r = by_len ? (int)ray_of[t] : t;
         const uint32_t m = rcnt[(int64_t)i * R + r];
         if (m > (uint32_t)rcap) continue;
         const uint2 *in = recs + (int64_t)i * rcap * R + r;
