@@ -40,7 +40,7 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 131844.12e6, "write": 11609.30e6,
+    "ff_trace": {"fetch": 132140.39e6, "write": 11607.94e6,
                  "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
                  "sha256": "57befa781977c6304fb4156158c7b70d88e7f7d017ee7b023636f709063f4be6",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
