@@ -169,7 +169,7 @@ struct gsrad_ff {
     // receivers in Morton order (ray-cast F): the order the row kernels take
     bool has_order = false;
     DevBuf row_order;
-    DevBuf t_row_ptr, t_col, t_val, perm, t_temp;
+    DevBuf t_row_ptr, t_col, t_val, t_temp;
     // unique per successful fill of the values (0: unusable); tapes record it
     uint64_t fill_gen = 0;
     // provenance for the opacity backward
@@ -188,7 +188,7 @@ struct gsrad_ff {
     // capacities the last ray cast needed (starting points of the next)
     int deep_stack = 0, agg_log2h = 0;
     // scratch of the ray-cast path
-    DevBuf slab, ell_col, ell_val, row_len, err, scan_temp, redo;
+    DevBuf slab, ell_col, ell_val, row_len, err, scan_temp, redo, pools;
     // opacity backward: per-XCD fixed-point accumulators and scale
     DevBuf opac, cacc;
     // dense BF16 copies (gsrad_ff_dense): F and F^T, hi and lo parts
@@ -217,8 +217,8 @@ struct gsrad_ff {
         return c;
     }
     ~gsrad_ff() {
-        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &perm, &t_temp, &slab, &ell_col, &redo, &row_order,
-                          &ell_val, &row_len, &err, &scan_temp, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl, &opac,
+        for (DevBuf *b : {&row_ptr, &col, &val, &t_row_ptr, &t_col, &t_val, &t_temp, &slab, &ell_col, &redo, &row_order,
+                          &ell_val, &row_len, &err, &scan_temp, &pools, &recs, &rcnt, &d_hi, &d_lo, &dt_hi, &dt_lo, &xa, &xb, &xl, &opac,
                           &cacc})
             b->release();
     }
@@ -416,11 +416,10 @@ gsrad_status ensure_transpose(gsrad_ff *ff, hipStream_t st) {
     GS_TRY(ff->t_row_ptr.ensure((size_t)(ff->n + 1) * 8, "F^T row_ptr"));
     GS_TRY(ff->t_col.ensure((size_t)std::max<int64_t>(ff->nnz, 1) * 4, "F^T col"));
     GS_TRY(ff->t_val.ensure((size_t)std::max<int64_t>(ff->nnz, 1) * 4, "F^T val"));
-    GS_TRY(ff->perm.ensure((size_t)std::max<int64_t>(ff->nnz, 1) * 4, "F^T perm"));
     const size_t tb = transpose_temp_bytes(ff->n, ff->nnz);
     GS_TRY(ff->t_temp.ensure(tb, "transpose temp"));
     GS_TRY(csr_transpose(ff->csr(), ff->t_row_ptr.as<int64_t>(), ff->t_col.as<int32_t>(), ff->t_val.as<float>(),
-                         ff->perm.as<uint32_t>(), ff->t_temp.p, tb, st));
+                         ff->t_temp.p, tb, st));
     ff->has_t = true;
     // a large sort scratch (batches of many scenes) is not kept
     if (tb > (size_t(2) << 30)) {
@@ -595,6 +594,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
         ENS(err, 128, "error flags");
         ENS(row_ptr, (n + 1) * 8, "row_ptr");
         ENS(scan_temp, scan_temp_bytes(n), "scan temp");
+        ENS(pools, ff_pool_list_bytes(chunk, R), "ray pools");
 #undef ENS
         int *err = h->err.as<int>();
         if ((e = check_hip(hipMemsetAsync(err, 0, 64, st), "ff flags")) != GSRAD_OK) return fail(e);
@@ -604,7 +604,7 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
             {
                 ProfScope ps("ff_trace", st);
                 if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, keep ? 1 : 0, h->recs.as<uint2>(),
-                                         h->rcnt.as<uint32_t>(), rcap, deep, err, st)) != GSRAD_OK)
+                                         h->rcnt.as<uint32_t>(), rcap, deep, h->pools.p, err, st)) != GSRAD_OK)
                     return fail(e);
             }
             ProfScope ps("ff_aggregate", st);

@@ -48,14 +48,12 @@ __global__ void __launch_bounds__(256) k_col_bounds(const uint32_t *__restrict__
 __global__ void __launch_bounds__(256) k_transpose_gather(const uint32_t *__restrict__ sorted_ids,
                                                           const uint32_t *__restrict__ rows,
                                                           const float *__restrict__ val, int64_t nnz,
-                                                          int32_t *__restrict__ t_col, float *__restrict__ t_val,
-                                                          uint32_t *__restrict__ perm) {
+                                                          int32_t *__restrict__ t_col, float *__restrict__ t_val) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= nnz) return;
     const uint32_t e = sorted_ids[k];
     t_col[k] = (int32_t)rows[e];
     t_val[k] = val[e];
-    if (perm) perm[k] = e;
 }
 
 // sum over the entries e in [b, e_end) of w_e * in[col_e][c] in CSR order,
@@ -461,8 +459,8 @@ static inline char *carve(char *&p, size_t bytes) {
     return r;
 }
 
-gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, float *t_val, uint32_t *perm,
-                           void *temp, size_t temp_bytes, hipStream_t st) {
+gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, float *t_val, void *temp,
+                           size_t temp_bytes, hipStream_t st) {
     const int64_t n = A.n, nnz = A.nnz;
     char *p = static_cast<char *>(temp);
     uint32_t *rows = reinterpret_cast<uint32_t *>(carve(p, (size_t)nnz * 4));
@@ -484,7 +482,7 @@ gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, flo
         s = radix_sort_pairs(keys, ids, skeys, sids, nnz, bits, rtemp, rbytes, st);
         if (s != GSRAD_OK) return s;
         hipLaunchKernelGGL(k_transpose_gather, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, sids, rows,
-                           A.val, nnz, t_col, t_val, perm);
+                           A.val, nnz, t_col, t_val);
     }
     hipLaunchKernelGGL(k_col_bounds, dim3((unsigned)((nnz + 1 + 255) / 256)), dim3(256), 0, st, skeys, nnz, n,
                        t_row_ptr);

@@ -74,83 +74,58 @@ __device__ __forceinline__ int lane_index() {
 // slot = original index i when the records of all receivers are kept,
 // else the receiver's position in the current chunk.
 //
-// One workgroup traces the rays of `group` consecutive receivers (Morton
-// order).  Per batch of up to 1024 rays the directions are generated, the
-// rays sorted by direction key, and the lanes pull rays from the sorted
-// pool through an LDS counter, so neighbouring lanes trace rays that leave
-// close origins in close directions.  Each lane walks its ray one node per
-// iteration, queueing the leaves it reaches; the wave tests queued leaves
-// once half of its lanes hold one; a lane whose k-buffer round ends waits
-// until enough lanes of its wave wait, the wave then composites them
-// together, and a lane whose ray ends takes the next ray of the pool at
-// once instead of idling until the wave's longest ray is done (the same
-// hits, composited in the same order, as the plain per-ray walk).  Three waves per SIMD (at most 168
-// VGPRs), held by a launch bound; four (at most 128) were measured no
-// faster.
+// The next pool for a workgroup on XCD xcd: each XCD has its own share of
+// the pools, [npools * x / 8, npools * (x + 1) / 8) for XCD x, taken in
+// order through the counter queue[64 * x] (one per 256-byte line); once its
+// own share is taken it takes from the other XCDs' shares, so every pool is
+// traced whatever XCDs the workgroups run on.  kNoPool once all are taken.
+constexpr uint32_t kNoPool = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t next_pool(uint32_t *queue, int64_t npools, int xcd) {
+    for (int t = 0; t < 8; ++t) {
+        const int x = (xcd + t) & 7;
+        const uint32_t lo = (uint32_t)((npools * x) / 8), hi = (uint32_t)((npools * (x + 1)) / 8);
+        if (lo >= hi) continue;
+        const uint32_t v = lo + atomicAdd(queue + 64 * x, 1u);
+        if (v < hi) return v;
+    }
+    return kNoPool;
+}
+
+// Rays come in pools of pool_rays <= 1024 (ray id = receiver * R + r over
+// the chunk's receivers in Morton order: the rays of 1024 / R consecutive
+// receivers, or 1024 rays of one receiver when R > 1024), sorted by
+// direction key by k_ray_pools into list[pool * 1024 + p] = (ray index in
+// the pool, direction).  The trace
+// workgroups are persistent: each XCD takes its share of the pools, in
+// order, through a counter of its own (queue[xcd]), and a workgroup's lanes
+// pull rays from its current pool through an LDS counter, so neighbouring
+// lanes trace rays that leave close origins in close directions.  The wave
+// whose pull passes the pool's last ray installs the workgroup's next pool
+// at once, so the lanes that are done take rays of the next pool while the
+// last rays of the current one are traced.  Each lane walks its ray one
+// node per iteration, queueing the leaves it reaches; the wave tests queued
+// leaves once half of its lanes hold one; a lane whose k-buffer round ends
+// waits until enough lanes of its wave wait, the wave then composites them
+// together, and a lane whose ray ends takes the next ray at once (the same
+// hits, composited in the same order, as the plain per-ray walk).  Three
+// waves per SIMD (at most 168 VGPRs), held by a launch bound; four (at most
+// 128) were measured no faster.
 template <int STK>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_ff_trace(BvhDev bv, int R, uint64_t seed, float t_eps, float t_min,
-                                                  int64_t s_begin, int64_t count, int group, int64_t nblocks,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_ff_trace(BvhDev bv, int R, float t_eps, float t_min,
+                                                  int64_t s_begin, int64_t count, int pool_rays, int64_t npools,
+                                                  const uint4 *__restrict__ list, uint32_t *queue,
                                                   int by_orig, uint2 *__restrict__ recs,
                                                   uint32_t *__restrict__ rcnt, int rcap, int *err) {
     extern __shared__ uint32_t stack_mem[];
-    __shared__ uint32_t pool_key[kPoolRays];
-    __shared__ float pool_d[kPoolRays][3];
-    __shared__ uint32_t next;
-    const int64_t gb = xcd_block(blockIdx.x, nblocks);
+    // the workgroup's current pool (high word; kNoPool: none left) and the
+    // rays taken from it (low word)
+    __shared__ unsigned long long pq;
     const int tid = threadIdx.x;
-    const int64_t r0 = gb * group;                                 // first receiver (chunk-relative)
-    const int g = (int)min<int64_t>(group, count - r0);            // receivers in this group
-    const int64_t total = (int64_t)g * R;
-    for (int64_t base = 0; base < total; base += kPoolRays) {
-        const int nb = (int)min<int64_t>(kPoolRays, total - base);
-        int P = 1;
-        while (P < nb) P <<= 1;
-        for (int k = tid; k < P; k += blockDim.x) {
-            uint32_t key = 0xffffffffu;
-            if (k < nb) {
-                const int64_t id = base + k;
-                const SurfRec rr = bv.rec[s_begin + r0 + id / R];
-                const int r = (int)(id % R);
-                float dx, dy, dz;
-                ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)r,
-                              (uint64_t)__float_as_uint(rr.d.w), seed, 0, dx, dy, dz);
-                pool_d[k][0] = dx;
-                pool_d[k][1] = dy;
-                pool_d[k][2] = dz;
-                key = (dir_key(dx, dy, dz) << 10) | (uint32_t)k;
-            }
-            pool_key[k] = key;
-        }
-        if (tid == 0) next = 0;
-        __syncthreads();
-        for (int size = 2; size <= P; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int t = tid; t < P / 2; t += blockDim.x) {
-                    const int idx = 2 * stride * (t / stride) + (t % stride);
-                    const int par = idx + stride;
-                    const bool asc = (idx & size) == 0;
-                    const uint32_t x = pool_key[idx], y = pool_key[par];
-                    if ((x > y) == asc) {
-                        pool_key[idx] = y;
-                        pool_key[par] = x;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        if (bv.n == 1) {
-            // a single surfel has no node to walk, and it is every ray's own
-            // receiver, which the walk skips: no ray hits anything
-            for (int p = tid; p < nb; p += 256) {
-                const int k = (int)(pool_key[p] & 1023u);
-                const int64_t id = base + k;
-                const int64_t recv = r0 + id / R;
-                const int64_t slot = by_orig ? (int64_t)__float_as_uint(bv.rec[s_begin + recv].d.w) : recv;
-                rcnt[slot * R + (int)(id % R)] = 0;
-            }
-            __syncthreads();
-            continue;
-        }
+    const int xcd = xcc_id();
+    if (tid == 0) pq = (unsigned long long)next_pool(queue, npools, xcd) << 32;
+    __syncthreads();
+    {
         // Lanes hold rays in one of two states: traversing (one node or one
         // queued leaf per iteration of the inner loop) or waiting, their
         // k-buffer round done, to composite.  Compositing is costly per hit (the FP64 hit point,
@@ -210,17 +185,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
             const uint64_t needm = __ballot(need);
             if (needm) {
                 const int leader = __ffsll((unsigned long long)needm) - 1;
-                uint32_t b0 = 0;
-                if (lane == leader) b0 = atomicAdd(&next, (uint32_t)__popcll(needm));
-                b0 = (uint32_t)__shfl((int)b0, leader, 64);
-                if (need) {
+                const uint32_t cnt = (uint32_t)__popcll(needm);
+                unsigned long long old = 0;
+                if (lane == leader) old = atomicAdd(&pq, (unsigned long long)cnt);
+                const uint32_t pool = (uint32_t)__shfl((int)(uint32_t)(old >> 32), leader, 64);
+                const uint32_t b0 = (uint32_t)__shfl((int)(uint32_t)old, leader, 64);
+                if (pool == kNoPool) {
+                    drained = need || drained;   // every pool is taken
+                } else {
+                    const int64_t id0 = (int64_t)pool * pool_rays;   // the pool's first ray
+                    const uint32_t pnb = (uint32_t)min<int64_t>(pool_rays, count * R - id0);
+                    // the one pull that covers the pool's end installs the
+                    // next pool (pulls after it, until then, find none)
+                    if (lane == leader && b0 <= pnb && pnb < b0 + cnt)
+                        atomicExch(&pq, (unsigned long long)next_pool(queue, npools, xcd) << 32);
                     const uint32_t p = b0 + (uint32_t)__popcll(needm & ((1ull << lane) - 1ull));
-                    if (p >= (uint32_t)nb) {
-                        drained = true;
-                    } else {
-                        const int k = (int)(pool_key[p] & 1023u);
-                        const int64_t id = base + k;
-                        const int64_t recv = r0 + id / R;   // chunk-relative receiver
+                    if (need && p < pnb) {
+                        const uint4 ent = list[(int64_t)pool * kPoolRays + p];
+                        const int64_t id = id0 + (int64_t)ent.x;
+                        const int64_t recv = id / R;   // chunk-relative receiver
                         const int r = (int)(id % R);
                         const SurfRec rr = bv.rec[s_begin + recv];
                         i = __float_as_uint(rr.d.w);
@@ -230,9 +213,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
                         ox = rr.a.x;
                         oy = rr.a.y;
                         oz = rr.a.z;
-                        dx = pool_d[k][0];
-                        dy = pool_d[k][1];
-                        dz = pool_d[k][2];
+                        dx = __uint_as_float(ent.y);
+                        dy = __uint_as_float(ent.z);
+                        dz = __uint_as_float(ent.w);
                         ix = safe_inv(dx);
                         iy = safe_inv(dy);
                         iz = safe_inv(dz);
@@ -245,7 +228,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
                 }
             }
             const int nact = __popcll(__ballot(have));
-            if (nact == 0) break;
+            if (nact == 0 && !__ballot(!drained)) break;
+            if (nact == 0) continue;   // the next pool is being installed
             const int nwait = __popcll(__ballot(have && !trav));
             if (nwait > 0 && (kFlushDen * nwait >= kFlushNum * nact || nwait == nact)) {
                 if (have && !trav) {
@@ -366,7 +350,72 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
                 if ((nw > 0 && (kFlushDen * nw >= kFlushNum * nact || nw == nact)) || __ballot(!have && !drained)) break;
             }
         }
-        __syncthreads();
+    }
+}
+
+// The ray pools of the trace: pool b holds the rays [b * pool_rays,
+// (b + 1) * pool_rays) of the chunk (ray id = receiver * R + r), their
+// directions generated and sorted by direction key (ties by ray index),
+// written as
+// list[b * 1024 + p] = (ray index in the pool, direction).  Block 0 also
+// resets the trace's per-XCD pool counters.  A scene of one surfel has no
+// node to walk and every ray starts in its own receiver, which the walk
+// skips: its rays record no hit here and the trace is not run.
+__global__ void __launch_bounds__(256) k_ray_pools(BvhDev bv, int R, uint64_t seed, int64_t s_begin, int64_t count,
+                                                   int pool_rays, int by_orig, uint4 *__restrict__ list,
+                                                   uint32_t *__restrict__ queue, uint32_t *__restrict__ rcnt) {
+    __shared__ uint32_t pool_key[kPoolRays];
+    __shared__ float pool_d[kPoolRays][3];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    if (b == 0 && tid < 8) queue[64 * tid] = 0;
+    const int64_t id0 = b * pool_rays;
+    const int nb = (int)min<int64_t>(pool_rays, count * R - id0);
+    if (bv.n == 1) {
+        for (int k = tid; k < nb; k += 256) {
+            const int64_t recv = (id0 + k) / R;
+            const int64_t slot = by_orig ? (int64_t)__float_as_uint(bv.rec[s_begin + recv].d.w) : recv;
+            rcnt[slot * R + (id0 + k) % R] = 0;
+        }
+        return;
+    }
+    int P = 1;
+    while (P < nb) P <<= 1;
+    for (int k = tid; k < P; k += 256) {
+        uint32_t key = 0xffffffffu;
+        if (k < nb) {
+            const int64_t id = id0 + k;
+            const SurfRec rr = bv.rec[s_begin + id / R];
+            float dx, dy, dz;
+            ray_direction(rr.c.x, rr.c.y, rr.c.z, rr.d.x, rr.d.y, rr.d.z, rr.b.x, rr.b.y, rr.b.z, (uint64_t)(id % R),
+                          (uint64_t)__float_as_uint(rr.d.w), seed, 0, dx, dy, dz);
+            pool_d[k][0] = dx;
+            pool_d[k][1] = dy;
+            pool_d[k][2] = dz;
+            key = (dir_key(dx, dy, dz) << 10) | (uint32_t)k;
+        }
+        pool_key[k] = key;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < P / 2; t += 256) {
+                const int idx = 2 * stride * (t / stride) + (t % stride);
+                const int par = idx + stride;
+                const bool asc = (idx & size) == 0;
+                const uint32_t x = pool_key[idx], y = pool_key[par];
+                if ((x > y) == asc) {
+                    pool_key[idx] = y;
+                    pool_key[par] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int p = tid; p < nb; p += 256) {
+        const int k = (int)(pool_key[p] & 1023u);
+        list[b * kPoolRays + p] = make_uint4((uint32_t)k, __float_as_uint(pool_d[k][0]), __float_as_uint(pool_d[k][1]),
+                                             __float_as_uint(pool_d[k][2]));
     }
 }
 
@@ -1072,21 +1121,41 @@ __global__ void __launch_bounds__(256) k_reflectance(BvhDev bv, const float *__r
 // ---------------------------------------------------------------------------
 size_t ff_stack_bytes(int threads) { return (size_t)kStackDeep * threads * sizeof(uint32_t); }
 
+size_t ff_pool_list_bytes(int64_t count, int R) {
+    const int pool_rays = R >= kPoolRays ? kPoolRays : (kPoolRays / R) * R;
+    const int64_t npools = (count * R + pool_rays - 1) / pool_rays;
+    return (size_t)npools * kPoolRays * sizeof(uint4) + 8 * 256;
+}
+
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, int *err,
-                             hipStream_t st) {
-    const int group = R >= kPoolRays ? 1 : kPoolRays / R;
-    const int64_t nblocks = (count + group - 1) / group;
+                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, void *pools,
+                             int *err, hipStream_t st) {
+    if (count <= 0) return GSRAD_OK;
+    const int pool_rays = R >= kPoolRays ? kPoolRays : (kPoolRays / R) * R;
+    const int64_t npools = (count * R + pool_rays - 1) / pool_rays;
+    uint32_t *queue = static_cast<uint32_t *>(pools);                       // 8 counters, 256 B apart
+    uint4 *list = reinterpret_cast<uint4 *>(static_cast<char *>(pools) + 8 * 256);
+    hipLaunchKernelGGL(k_ray_pools, dim3((unsigned)npools), dim3(256), 0, st, bv, R, seed, s_begin, count, pool_rays,
+                       by_orig, list, queue, rcnt);
+    gsrad_status s = check_hip(hipGetLastError(), "ray pools launch");
+    if (s != GSRAD_OK || bv.n == 1) return s;
+    // persistent workgroups: three per CU (twelve waves), at most one per pool
+    int dev = 0, cus = 0;
+    if ((s = check_hip(hipGetDevice(&dev), "ff trace device")) != GSRAD_OK) return s;
+    if ((s = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "ff trace CUs")) !=
+        GSRAD_OK)
+        return s;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(npools, 3 * (int64_t)cus));
     if (deep) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ff_trace<kStackDeep>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kStackDeep * 256 * 4);
-        hipLaunchKernelGGL(k_ff_trace<kStackDeep>, dim3((unsigned)nblocks), dim3(256),
-                           (size_t)kStackDeep * 256 * sizeof(uint32_t), st, bv, R, seed, t_eps, t_min, s_begin, count,
-                           group, nblocks, by_orig, recs, rcnt, rcap, err);
+        hipLaunchKernelGGL(k_ff_trace<kStackDeep>, dim3((unsigned)grid), dim3(256),
+                           (size_t)kStackDeep * 256 * sizeof(uint32_t), st, bv, R, t_eps, t_min, s_begin, count,
+                           pool_rays, npools, list, queue, by_orig, recs, rcnt, rcap, err);
     } else {
-        hipLaunchKernelGGL(k_ff_trace<kStackShallow>, dim3((unsigned)nblocks), dim3(256),
-                           (size_t)kStackShallow * 256 * sizeof(uint32_t), st, bv, R, seed, t_eps, t_min, s_begin,
-                           count, group, nblocks, by_orig, recs, rcnt, rcap, err);
+        hipLaunchKernelGGL(k_ff_trace<kStackShallow>, dim3((unsigned)grid), dim3(256),
+                           (size_t)kStackShallow * 256 * sizeof(uint32_t), st, bv, R, t_eps, t_min, s_begin, count,
+                           pool_rays, npools, list, queue, by_orig, recs, rcnt, rcap, err);
     }
     return check_hip(hipGetLastError(), "ff trace launch");
 }

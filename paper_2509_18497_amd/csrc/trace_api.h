@@ -15,9 +15,12 @@ constexpr int kErrRecords = 16; // a ray composited more hits than its record sl
 
 size_t ff_stack_bytes(int threads);
 size_t ff_aggregate_smem(int log2h);
+// bytes of the ray pools launch_ff_trace needs (pools argument) for a chunk
+// of count receivers
+size_t ff_pool_list_bytes(int64_t count, int R);
 gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, int *err,
-                             hipStream_t st);
+                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, void *pools,
+                             int *err, hipStream_t st);
 // Rows overflowing a table of 2^log2h entries (a probe chain of 256) are listed in
 // redo_list (count in redo_cnt[0], tickets in redo_cnt[1]; room for count
 // rows) and aggregated again with 2^log2h_max entries; err[2] counts them.
@@ -59,8 +62,8 @@ struct Csr {
 };
 
 size_t transpose_temp_bytes(int64_t n, int64_t nnz);
-gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, float *t_val, uint32_t *perm,
-                           void *temp, size_t temp_bytes, hipStream_t st);
+gsrad_status csr_transpose(const Csr &A, int64_t *t_row_ptr, int32_t *t_col, float *t_val, void *temp,
+                           size_t temp_bytes, hipStream_t st);
 // Bout = E + rho * (F Bin), rows of C columns
 // Morton-sorted position -> original surfel index (the sorted records' ids)
 gsrad_status launch_sorted_order(const BvhDev &bv, int32_t *order, hipStream_t st);
