@@ -180,8 +180,8 @@ def main():
     def avg(name):
         return prof[name]["total_ms"] / args.steps if name in prof else 0.0
 
-    t_trace = avg("ff_trace")
-    t_ff = avg("ff_trace") + avg("ff_aggregate") + avg("ff_csr")
+    t_trace = avg("ray_pools") + avg("ff_trace")   # ray generation and sorting, then the trace
+    t_ff = t_trace + avg("ff_aggregate") + avg("ff_csr")
     t_solve_bwd = avg("bounce") + avg("transpose") + avg("adjoint") + avg("sddmm") + avg("opacity_records") + \
         avg("opacity_pass1") + avg("opacity_pass2") + avg("opacity_finish")
     rays = N * R
@@ -890,7 +890,8 @@ def uneven_batch(args, g, scenes, torch, np, lights=(8, 100), topk=512):
         "per_scene_transport_ms": t_scene,
         "speedup_vs_per_scene": t_scene / t_batch if t_batch > 0 else None,
         "lanes_per_row": {"bounce": info["lanes_bounce"], "adjoint": info["lanes_adjoint"]},
-        "grays_per_s": rays / (avg("ff_trace") * 1e-3) / 1e9 if avg("ff_trace") > 0 else None,
+        "grays_per_s": (rays / ((avg("ray_pools") + avg("ff_trace")) * 1e-3) / 1e9
+                        if avg("ff_trace") > 0 else None),
         "bounce_updates_per_s": _updates(nb * sum(sc.n * l for sc, l in zip(rooms, Lts)), phases.get("batch_bounces", 0.0)),
         "adjoint_updates_per_s": _updates(nb * sum(sc.n * l for sc, l in zip(rooms, Lts)), phases.get("batch_adjoint", 0.0)),
         "phase_ms_per_step": {k: round(v, 4) for k, v in sorted(phases.items())},

@@ -602,8 +602,14 @@ gsrad_status gsrad_form_factors(const gsrad_bvh *bvh, const gsrad_ff_params *p, 
         for (int64_t s0 = 0; s0 < n; s0 += chunk) {
             const int64_t cnt = std::min(chunk, n - s0);
             {
+                ProfScope ps("ray_pools", st);
+                if ((e = launch_ray_pools(bv, R, p->seed, s0, cnt, keep ? 1 : 0, h->rcnt.as<uint32_t>(), h->pools.p,
+                                          st)) != GSRAD_OK)
+                    return fail(e);
+            }
+            {
                 ProfScope ps("ff_trace", st);
-                if ((e = launch_ff_trace(bv, R, p->seed, t_eps, p->t_min, s0, cnt, keep ? 1 : 0, h->recs.as<uint2>(),
+                if ((e = launch_ff_trace(bv, R, t_eps, p->t_min, s0, cnt, keep ? 1 : 0, h->recs.as<uint2>(),
                                          h->rcnt.as<uint32_t>(), rcap, deep, h->pools.p, err, st)) != GSRAD_OK)
                     return fail(e);
             }

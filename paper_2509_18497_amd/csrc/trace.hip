@@ -1127,9 +1127,8 @@ size_t ff_pool_list_bytes(int64_t count, int R) {
     return (size_t)npools * kPoolRays * sizeof(uint4) + 8 * 256;
 }
 
-gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, void *pools,
-                             int *err, hipStream_t st) {
+gsrad_status launch_ray_pools(const BvhDev &bv, int R, uint64_t seed, int64_t s_begin, int64_t count, int by_orig,
+                              uint32_t *rcnt, void *pools, hipStream_t st) {
     if (count <= 0) return GSRAD_OK;
     const int pool_rays = R >= kPoolRays ? kPoolRays : (kPoolRays / R) * R;
     const int64_t npools = (count * R + pool_rays - 1) / pool_rays;
@@ -1137,8 +1136,18 @@ gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps
     uint4 *list = reinterpret_cast<uint4 *>(static_cast<char *>(pools) + 8 * 256);
     hipLaunchKernelGGL(k_ray_pools, dim3((unsigned)npools), dim3(256), 0, st, bv, R, seed, s_begin, count, pool_rays,
                        by_orig, list, queue, rcnt);
-    gsrad_status s = check_hip(hipGetLastError(), "ray pools launch");
-    if (s != GSRAD_OK || bv.n == 1) return s;
+    return check_hip(hipGetLastError(), "ray pools launch");
+}
+
+gsrad_status launch_ff_trace(const BvhDev &bv, int R, float t_eps, float t_min, int64_t s_begin, int64_t count,
+                             int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, void *pools, int *err,
+                             hipStream_t st) {
+    if (count <= 0 || bv.n == 1) return GSRAD_OK;
+    const int pool_rays = R >= kPoolRays ? kPoolRays : (kPoolRays / R) * R;
+    const int64_t npools = (count * R + pool_rays - 1) / pool_rays;
+    uint32_t *queue = static_cast<uint32_t *>(pools);
+    const uint4 *list = reinterpret_cast<const uint4 *>(static_cast<char *>(pools) + 8 * 256);
+    gsrad_status s;
     // persistent workgroups: three per CU (twelve waves), at most one per pool
     int dev = 0, cus = 0;
     if ((s = check_hip(hipGetDevice(&dev), "ff trace device")) != GSRAD_OK) return s;

@@ -15,12 +15,17 @@ constexpr int kErrRecords = 16; // a ray composited more hits than its record sl
 
 size_t ff_stack_bytes(int threads);
 size_t ff_aggregate_smem(int log2h);
-// bytes of the ray pools launch_ff_trace needs (pools argument) for a chunk
-// of count receivers
+// bytes of the ray pools (pools argument) for a chunk of count receivers
 size_t ff_pool_list_bytes(int64_t count, int R);
-gsrad_status launch_ff_trace(const BvhDev &bv, int R, uint64_t seed, float t_eps, float t_min, int64_t s_begin,
-                             int64_t count, int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, void *pools,
-                             int *err, hipStream_t st);
+// the chunk's rays, generated and sorted by direction into pools (and the
+// trace's pool counters reset); a scene of one surfel gets its zero counts
+// here and needs no trace
+gsrad_status launch_ray_pools(const BvhDev &bv, int R, uint64_t seed, int64_t s_begin, int64_t count, int by_orig,
+                              uint32_t *rcnt, void *pools, hipStream_t st);
+// trace of the pools launch_ray_pools made (run it again before a repeat)
+gsrad_status launch_ff_trace(const BvhDev &bv, int R, float t_eps, float t_min, int64_t s_begin, int64_t count,
+                             int by_orig, uint2 *recs, uint32_t *rcnt, int rcap, int deep, void *pools, int *err,
+                             hipStream_t st);
 // Rows overflowing a table of 2^log2h entries (a probe chain of 256) are listed in
 // redo_list (count in redo_cnt[0], tickets in redo_cnt[1]; room for count
 // rows) and aggregated again with 2^log2h_max entries; err[2] counts them.
