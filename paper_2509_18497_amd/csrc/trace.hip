@@ -44,7 +44,10 @@ __device__ __forceinline__ uint32_t dir_key(float dx, float dy, float dz) {
     return k;
 }
 
-constexpr int kPoolRays = 1024;   // rays sorted and pooled per batch
+// pools of 256 rays (two receivers at R = 128): on the 100k fruit bowl the
+// trace took 53.7 ms, against 54.3 (512), 55.4 (1024), 58.0 (2048)
+constexpr int kPoolBits = 8;
+constexpr int kPoolRays = 1 << kPoolBits;   // rays sorted and pooled per batch
 constexpr int kCompChunk = 5;     // buffered hits whose kernel values are found together
 // a wave composites once kFlushNum / kFlushDen of its lanes holding rays wait
 constexpr int kFlushNum = 3, kFlushDen = 8;
@@ -92,10 +95,11 @@ __device__ __forceinline__ uint32_t next_pool(uint32_t *queue, int64_t npools, i
     return kNoPool;
 }
 
-// Rays come in pools of pool_rays <= 1024 (ray id = receiver * R + r over
-// the chunk's receivers in Morton order: the rays of 1024 / R consecutive
-// receivers, or 1024 rays of one receiver when R > 1024), sorted by
-// direction key by k_ray_pools into list[pool * 1024 + p] = (ray index in
+// Rays come in pools of pool_rays <= kPoolRays (ray id = receiver * R + r
+// over the chunk's receivers in Morton order: the rays of kPoolRays / R
+// consecutive receivers, or kPoolRays rays of one receiver when R is
+// larger), sorted by direction key by k_ray_pools into
+// list[pool * kPoolRays + p] = (ray index in
 // the pool, direction).  The trace
 // workgroups are persistent: each XCD takes its share of the pools, in
 // order, through a counter of its own (queue[xcd]), and a workgroup's lanes
@@ -357,7 +361,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
 // (b + 1) * pool_rays) of the chunk (ray id = receiver * R + r), their
 // directions generated and sorted by direction key (ties by ray index),
 // written as
-// list[b * 1024 + p] = (ray index in the pool, direction).  Block 0 also
+// list[b * kPoolRays + p] = (ray index in the pool, direction).  Block 0 also
 // resets the trace's per-XCD pool counters.  A scene of one surfel has no
 // node to walk and every ray starts in its own receiver, which the walk
 // skips: its rays record no hit here and the trace is not run.
@@ -392,7 +396,7 @@ __global__ void __launch_bounds__(256) k_ray_pools(BvhDev bv, int R, uint64_t se
             pool_d[k][0] = dx;
             pool_d[k][1] = dy;
             pool_d[k][2] = dz;
-            key = (dir_key(dx, dy, dz) << 10) | (uint32_t)k;
+            key = (dir_key(dx, dy, dz) << kPoolBits) | (uint32_t)k;
         }
         pool_key[k] = key;
     }
@@ -413,7 +417,7 @@ __global__ void __launch_bounds__(256) k_ray_pools(BvhDev bv, int R, uint64_t se
         }
     }
     for (int p = tid; p < nb; p += 256) {
-        const int k = (int)(pool_key[p] & 1023u);
+        const int k = (int)(pool_key[p] & (uint32_t)(kPoolRays - 1));
         list[b * kPoolRays + p] = make_uint4((uint32_t)k, __float_as_uint(pool_d[k][0]), __float_as_uint(pool_d[k][1]),
                                              __float_as_uint(pool_d[k][2]));
     }
