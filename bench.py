@@ -40,9 +40,9 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 142460.58e6, "write": 11577.42e6,
+    "ff_trace": {"fetch": 158237.97e6, "write": 11313.64e6,
                  "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "98ff8f2afb3cf17f697e0a62dd519d511c2a8e7c6e5c5247797ae6ba3303abbd",
+                 "sha256": "b19e10334d97ffae4577fad76a9aaf88996383435c41b29a3e601ed9782518ef",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
     "dense_grad_F": {"fetch": 236949.39e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],
