@@ -1,5 +1,5 @@
-// Device-wide exclusive scan and stable LSD radix sort (8-bit digits) for
-// wave64.  Used for Morton-code ordering of the surfels and for the
+// Device-wide exclusive scan and stable LSD radix sort (digits of up to 9
+// bits) for wave64.  Used for Morton-code ordering of the surfels and for the
 // deterministic CSR transpose of F.
 #include "gsrad_internal.h"
 
@@ -15,6 +15,8 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 constexpr int kWaves = kSortThreads / 64;
+constexpr int kMaxDigitBits = 9;
+constexpr int kMaxBins = 1 << kMaxDigitBits;   // two per thread
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -160,34 +162,40 @@ gsrad_status exclusive_scan_u32_i64(const uint32_t *in, int64_t *out, int64_t n,
 namespace {
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
-                                                             uint32_t *__restrict__ hist, int64_t nb) {
-    __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
+                                                             int dbits, uint32_t *__restrict__ hist, int64_t nb) {
+    __shared__ uint32_t cnt[kMaxBins];
+    const uint32_t mask = (1u << dbits) - 1u;
+    const int bins = 1 << dbits;
+    for (int d = threadIdx.x; d < bins; d += kSortThreads) cnt[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+    for (int d = threadIdx.x; d < bins; d += kSortThreads) hist[(int64_t)d * nb + blockIdx.x] = cnt[d];
 }
 
 // Stable scatter: the item order inside a tile is (round, thread), which is
 // the input order, and ranks are assigned in that order.
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *__restrict__ keys,
                                                                 const uint32_t *__restrict__ vals, uint32_t *kout,
-                                                                uint32_t *vout, int64_t n, int shift,
+                                                                uint32_t *vout, int64_t n, int shift, int dbits,
                                                                 const int64_t *__restrict__ off, int64_t nb) {
-    __shared__ uint32_t running[256];
-    __shared__ uint32_t wcnt[kWaves][256];
-    __shared__ int64_t goff[256];
+    __shared__ uint32_t running[kMaxBins];
+    __shared__ uint32_t wcnt[kWaves][kMaxBins];
+    __shared__ int64_t goff[kMaxBins];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-    running[tid] = 0;
-    goff[tid] = off[(int64_t)tid * nb + blockIdx.x];
+    const uint32_t mask = (1u << dbits) - 1u;
+    const int bins = 1 << dbits;
+    for (int d = tid; d < bins; d += kSortThreads) {
+        running[d] = 0;
+        goff[d] = off[(int64_t)d * nb + blockIdx.x];
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) wcnt[k][tid] = 0;
+        for (int k = 0; k < kWaves; ++k) wcnt[k][d] = 0;
+    }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -198,11 +206,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *
         if (valid) {
             key = keys[i];
             val = vals[i];
-            dig = (key >> shift) & 255u;
+            dig = (key >> shift) & mask;
         }
+        // lanes of the wave with the same digit
         uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < dbits; ++b) {
             const uint64_t bal = __ballot(valid && ((dig >> b) & 1u));
             peers &= ((dig >> b) & 1u) ? bal : ~bal;
         }
@@ -217,13 +225,15 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *
             vout[pos] = val;
         }
         __syncthreads();
-        uint32_t add = 0;
+        for (int d = tid; d < bins; d += kSortThreads) {
+            uint32_t add = 0;
 #pragma unroll
-        for (int k = 0; k < kWaves; ++k) {
-            add += wcnt[k][tid];
-            wcnt[k][tid] = 0;
+            for (int k = 0; k < kWaves; ++k) {
+                add += wcnt[k][d];
+                wcnt[k][d] = 0;
+            }
+            running[d] += add;
         }
-        running[tid] += add;
         __syncthreads();
     }
 }
@@ -232,7 +242,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint32_t *
 
 size_t radix_temp_bytes(int64_t n) {
     const int64_t nb = (n + kSortTile - 1) / kSortTile;
-    const int64_t m = 256 * nb;
+    const int64_t m = (int64_t)kMaxBins * nb;
     size_t b = 0;
     b += (size_t)m * sizeof(uint32_t) + 256;              // histogram
     b += (size_t)(m + 1) * sizeof(int64_t) + 256;         // offsets
@@ -251,7 +261,11 @@ gsrad_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, 
                               hipStream_t st) {
     if (n <= 0) return GSRAD_OK;
     const int64_t nb = (n + kSortTile - 1) / kSortTile;
-    const int64_t m = 256 * nb;
+    // passes of at most 9-bit digits, as few as the key bits need (17-bit
+    // keys: two of 9 bits instead of three of 8), the digits of equal width
+    const int passes = bits <= 0 ? 1 : (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+    const int dbits = bits <= 0 ? 1 : (bits + passes - 1) / passes;
+    const int64_t m = ((int64_t)1 << dbits) * nb;
     char *p = static_cast<char *>(temp);
     char *end = p + temp_bytes;
     uint32_t *hist = reinterpret_cast<uint32_t *>(p);
@@ -271,18 +285,18 @@ gsrad_status radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, 
         return GSRAD_EINVAL;
     }
     const size_t scan_bytes = (size_t)(end - p);
-    const int passes = (bits + 7) / 8;
     const uint32_t *ksrc = keys_in;
     const uint32_t *vsrc = vals_in;
     for (int pass = 0; pass < passes; ++pass) {
         const bool last = pass == passes - 1;
         uint32_t *kdst = last ? keys_out : ((pass & 1) ? kb : ka);
         uint32_t *vdst = last ? vals_out : ((pass & 1) ? vb : va);
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ksrc, n, 8 * pass, hist, nb);
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ksrc, n, dbits * pass, dbits,
+                           hist, nb);
         gsrad_status s = exclusive_scan_u32_i64(hist, off, m, p, scan_bytes, st);
         if (s != GSRAD_OK) return s;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ksrc, vsrc, kdst, vdst, n,
-                           8 * pass, off, nb);
+                           dbits * pass, dbits, off, nb);
         s = check_hip(hipGetLastError(), "radix scatter");
         if (s != GSRAD_OK) return s;
         ksrc = kdst;
