@@ -42,7 +42,7 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 TRAFFIC = {
     "ff_trace": {"fetch": 158237.97e6, "write": 11313.64e6,
                  "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
-                 "sha256": "b19e10334d97ffae4577fad76a9aaf88996383435c41b29a3e601ed9782518ef",
+                 "sha256": "fdc7be6bb7adca89ecf8c86f5069128128f4043cb4bf5720abeaf58017861ffb",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
     "dense_grad_F": {"fetch": 236949.39e6, "write": 4294.97e6,
                      "files": ["dense.hip", "dense_api.h", "gsrad_internal.h"],

@@ -99,22 +99,27 @@ __device__ __forceinline__ uint32_t next_pool(uint32_t *queue, int64_t npools, i
 // over the chunk's receivers in Morton order: the rays of kPoolRays / R
 // consecutive receivers, or kPoolRays rays of one receiver when R is
 // larger), sorted by direction key by k_ray_pools into
-// list[pool * kPoolRays + p] = (ray index in
-// the pool, direction).  The trace
-// workgroups are persistent: each XCD takes its share of the pools, in
-// order, through a counter of its own (queue[xcd]), and a workgroup's lanes
-// pull rays from its current pool through an LDS counter, so neighbouring
-// lanes trace rays that leave close origins in close directions.  The wave
-// whose pull passes the pool's last ray installs the workgroup's next pool
-// at once, so the lanes that are done take rays of the next pool while the
-// last rays of the current one are traced.  Each lane walks its ray one
-// node per iteration, queueing the leaves it reaches; the wave tests queued
-// leaves once half of its lanes hold one; a lane whose k-buffer round ends
-// waits until enough lanes of its wave wait, the wave then composites them
-// together, and a lane whose ray ends takes the next ray at once (the same
-// hits, composited in the same order, as the plain per-ray walk).  Three
-// waves per SIMD (at most 168 VGPRs), held by a launch bound; four (at most
-// 128) were measured no faster.
+// list[pool * kPoolRays + p] = (ray index in the pool, direction).
+//
+// The trace workgroups are persistent and take pools through next_pool.  A
+// workgroup's lanes pull rays from its current pool through one 64-bit LDS
+// word, (pool, rays handed out), with one atomic add per wave, so
+// neighbouring lanes trace rays that leave close origins in close
+// directions.  The single pull whose range covers the pool's end installs
+// the next pool (an exchange of the word); pulls between the two find no
+// ray and are repeated, so the lanes that are done take rays of the next
+// pool while the last rays of the current one are traced.  Every ray of a
+// pool is handed out once before its successor is installed, every pool is
+// installed once, and a wave ends when all of its lanes have found kNoPool
+// and hold no ray.
+//
+// Each lane walks its ray one node per iteration, queueing the leaves it
+// reaches; the wave tests queued leaves once half of its lanes hold one; a
+// lane whose k-buffer round ends waits until enough lanes of its wave
+// wait, the wave then composites them together, and a lane whose ray ends
+// takes the next ray at once (the same hits, composited in the same order,
+// as the plain per-ray walk).  Three waves per SIMD (at most 168 VGPRs),
+// held by a launch bound; four (at most 128) were measured no faster.
 template <int STK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_ff_trace(BvhDev bv, int R, float t_eps, float t_min,
                                                   int64_t s_begin, int64_t count, int pool_rays, int64_t npools,
