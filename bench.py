@@ -40,7 +40,7 @@ FLOP_COMP = 30     # compositing one hit (two exponentials, weights)
 # FETCH_SIZE, x1.0000 for WRITE_SIZE), valid only for the kernel sources
 # they were taken on (sha256 over the listed files, in order).
 TRAFFIC = {
-    "ff_trace": {"fetch": 158237.97e6, "write": 11313.64e6,
+    "ff_trace": {"fetch": 159148.47e6, "write": 11312.00e6,
                  "files": ["trace.hip", "traverse.h", "gsrad_internal.h", "trace_api.h"],
                  "sha256": "fdc7be6bb7adca89ecf8c86f5069128128f4043cb4bf5720abeaf58017861ffb",
                  "summary": "profiles/fruit_bowl_100k_hbm_counters.txt"},
