@@ -552,3 +552,18 @@ def test_reciprocity_check_matches_oracle(g, orc, name, kw, R):
     asym, mx = orc.reciprocity(Fo, A)
     assert abs(rec["asymmetry"] - asym) <= 1e-4 * asym
     assert abs(rec["max_entry"] - mx) <= 1e-4 * max(mx, 1e-12)
+
+
+def test_chunked_ray_cast_equals_one_pass(g):
+    """Without kept records the receivers are traced in chunks whose record
+    slabs fit a fixed budget (10k receivers x 1024 rays: more than one
+    chunk), each chunk's rays pooled and taken by the persistent workgroups
+    anew; the form factors must be those of the single pass with records,
+    bit for bit (the same rays, fixed-point sums)."""
+    sc = _scene("fruit_bowl", n=10000)
+    bvh = g.build_bvh(dev_surfels(sc.surfels))
+    one = g.form_factors(bvh, 1024, sc.seed, t_min=1e-4, topk=256)
+    chunked = g.form_factors(bvh, 1024, sc.seed, t_min=1e-4, topk=256, records=False)
+    for x, y in zip(one.csr(), chunked.csr()):
+        assert torch.equal(x, y)
+    assert one.info()[1] > 0
